@@ -1,0 +1,260 @@
+"""Pins for the CPU oracle (no GPU).
+
+Every check here ties the oracle to something other than itself: values the
+paper prints for its worked example (Figures 1 and 2), closed forms for
+complete bipartite graphs, pure-Python brute force from the definitions on
+tiny graphs, and invariants that any correct count satisfies.
+"""
+import json
+import os
+from itertools import combinations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1907_08607_amd import graphgen as gg
+from tests import brute
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def fig1():
+    with open(os.path.join(GOLDEN, "fig1_example.json")) as f:
+        d = json.load(f)
+    return d, gg.from_edges(d["n_u"], d["n_v"], d["edges_u"], d["edges_v"])
+
+
+def c2(x):
+    return x * (x - 1) // 2
+
+
+# ---------------------------------------------------------------- worked example
+
+@pytest.mark.parametrize("tier", [oracle.count_bf4, oracle.count_pairs, oracle.count])
+def test_fig1_counts(tier):
+    d, g = fig1()
+    glob, vert, edge = tier(g)
+    assert glob == d["global"]
+    assert vert.tolist() == d["per_vertex_unified"]
+    assert edge.tolist() == d["per_edge_csr_order"]
+
+
+def test_fig1_brute_matches_caption():
+    d, g = fig1()
+    assert sorted(brute.butterflies(g)) == sorted(tuple(b) for b in d["butterflies"])
+    glob, vert, edge = brute.counts(g)
+    assert (glob, vert, edge) == (d["global"], d["per_vertex_unified"], d["per_edge_csr_order"])
+
+
+def test_fig2_wedges():
+    d, g = fig1()
+    rank = np.empty(6, dtype=np.uint32)
+    rank[d["fig2_order_unified"]] = np.arange(6)
+    total, per = oracle.wedges(g, rank, per_source=True)
+    assert total == d["fig2_wedges_total"]
+    expect = np.zeros(6, dtype=np.int64)
+    for k, w in d["fig2_wedges_per_source_unified"].items():
+        expect[int(k)] = w
+    assert per.tolist() == expect.tolist()
+    ws = brute.wedges(g, rank.tolist())
+    assert len(ws) == total
+    groups = {}
+    for x, _, z in ws:
+        groups[(x, z)] = groups.get((x, z), 0) + 1
+    assert sorted(groups.items()) == sorted((tuple(p), c) for p, c in d["fig2_endpoint_pairs"])
+
+
+def test_fig1_any_order_same_counts():
+    """Ordering does not change the counts (Section 4.1): all 720 orders."""
+    from itertools import permutations
+    d, g = fig1()
+    seen_w = set()
+    for perm in permutations(range(6)):
+        rank = np.empty(6, dtype=np.uint32)
+        rank[list(perm)] = np.arange(6)
+        ws = brute.wedges(g, rank.tolist())
+        seen_w.add(len(ws))
+        assert oracle.wedges(g, rank) == len(ws)
+        # the framework's count from these wedges: sum over endpoint pairs of C(R,2)
+        groups = {}
+        for x, _, z in ws:
+            groups[(x, z)] = groups.get((x, z), 0) + 1
+        assert sum(c2(r) for r in groups.values()) == d["global"]
+    assert min(seen_w) < max(seen_w)  # the order changes the work, not the result
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("a,b", [(2, 2), (3, 5), (7, 4), (20, 15)])
+def test_complete_bipartite(a, b):
+    g = gg.complete(a, b)
+    tiers = [oracle.count, oracle.count_pairs] + ([oracle.count_bf4] if a * b <= 64 else [])
+    for tier in tiers:
+        glob, vert, edge = tier(g)
+        assert glob == c2(a) * c2(b)
+        assert (vert[:a] == (a - 1) * c2(b)).all()
+        assert (vert[a:] == (b - 1) * c2(a)).all()
+        assert (edge == (a - 1) * (b - 1)).all()
+    # U-first side order: centers are V, W = sum_v C(deg v, 2) = b C(a, 2)
+    assert oracle.wedges(g, oracle.rank(g, "side_u")) == b * c2(a)
+    assert oracle.wedges(g, oracle.rank(g, "side_v")) == a * c2(b)
+
+
+def test_planted_complete_component():
+    base = gg.workload_er_1k()
+    g = gg.workload_er_1k_planted()
+    gb, vb, eb = oracle.count(base)
+    glob, vert, edge = oracle.count(g)
+    assert glob == gb + 19_950
+    assert (vert[base.n_u:base.n_u + 20] == 1995).all()
+    assert (vert[g.n_u + base.n_v:] == 2660).all()
+    assert (edge[base.m:] == 266).all()
+    assert (edge[:base.m] == eb).all()
+
+
+# ---------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("seed", range(40))
+def test_tiny_graphs_match_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    g = gg.random_small(int(rng.integers(1, 8)), int(rng.integers(1, 8)), float(rng.uniform(0.2, 0.9)), seed)
+    want = brute.counts(g)
+    for tier in (oracle.count_bf4, oracle.count_pairs, oracle.count):
+        glob, vert, edge = tier(g)
+        assert (glob, vert.tolist(), edge.tolist()) == want
+
+
+def test_empty_and_degenerate():
+    for g in (gg.from_edges(0, 0, [], []), gg.from_edges(5, 0, [], []), gg.from_edges(3, 4, [], []),
+              gg.complete(1, 9), gg.complete(9, 1)):
+        for tier in (oracle.count_bf4, oracle.count_pairs, oracle.count):
+            glob, vert, edge = tier(g)
+            assert glob == 0 and not vert.any() and not edge.any()
+
+
+# ---------------------------------------------------------------- invariants
+
+def test_invariants_er():
+    g = gg.workload_er_1k()
+    glob, vert, edge = oracle.count(g)
+    p = oracle.count_pairs(g)
+    assert glob == p[0] and (vert == p[1]).all() and (edge == p[2]).all()
+    assert glob > 0
+    assert vert.sum() == 4 * glob and edge.sum() == 4 * glob
+    assert vert[:g.n_u].sum() == 2 * glob and vert[g.n_u:].sum() == 2 * glob
+    u, v = g.edges()
+    half = np.zeros(g.n_u + g.n_v, dtype=np.int64)
+    np.add.at(half, u, edge)
+    np.add.at(half, g.n_u + v, edge)
+    assert (half == 2 * vert).all()  # each butterfly at x holds two edges at x
+    assert (edge <= np.minimum(vert[u], vert[g.n_u + v])).all()
+
+
+def test_transpose_and_relabel_symmetry():
+    g = gg.random_small(40, 30, 0.25, 11)
+    glob, vert, edge = oracle.count(g)
+    t = gg.transpose(g)
+    tg, tv, te = oracle.count(t)
+    assert tg == glob
+    assert (tv[:g.n_v] == vert[g.n_u:]).all() and (tv[g.n_v:] == vert[:g.n_u]).all()
+    tu, tvv = t.edges()  # t edge (v, u) has count of g edge (u, v)
+    emap = {(int(a), int(b)): k for k, (a, b) in enumerate(zip(*g.edges()))}
+    assert all(te[k] == edge[emap[(int(b), int(a))]] for k, (a, b) in enumerate(zip(tu, tvv)))
+    rng = np.random.default_rng(5)
+    pu, pv = rng.permutation(g.n_u), rng.permutation(g.n_v)
+    r = gg.relabel(g, pu, pv)
+    rg, rv, _ = oracle.count(r)
+    assert rg == glob
+    assert (rv[pu] == vert[:g.n_u]).all() and (rv[g.n_u + pv] == vert[g.n_u:]).all()
+
+
+def test_disjoint_union_additive():
+    a = gg.random_small(12, 9, 0.4, 1)
+    b = gg.random_small(7, 13, 0.5, 2)
+    ga, va, ea = oracle.count(a)
+    gb, vb, eb = oracle.count(b)
+    gu, vu, eu = oracle.count(gg.disjoint_union(a, b))
+    assert gu == ga + gb
+    assert (vu[:a.n_u] == va[:a.n_u]).all() and (vu[a.n_u:a.n_u + b.n_u] == vb[:b.n_u]).all()
+    assert (eu[:a.m] == ea).all() and (eu[a.m:] == eb).all()
+
+
+def test_sampler_matches_full_counts():
+    g = gg.workload_er_1k_planted()
+    _, vert, edge = oracle.count(g)
+    s = oracle.Sampler(g)
+    rng = np.random.default_rng(3)
+    for x in rng.integers(0, g.n_u + g.n_v, 60):
+        assert s.vertex(x) == vert[x]
+    for e in list(rng.integers(0, g.m, 60)) + [0, g.m - 1]:
+        assert s.edge(e) == edge[e]
+
+
+# ---------------------------------------------------------------- wedges and ranks
+
+KINDS = ["side_auto", "side_u", "side_v", "degree", "approx_degree", "codeg", "approx_codeg"]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_rank_and_wedges_match_brute(seed):
+    rng = np.random.default_rng(100 + seed)
+    g = gg.random_small(int(rng.integers(2, 9)), int(rng.integers(2, 9)), float(rng.uniform(0.2, 0.8)), seed)
+    for kind in KINDS:
+        r = oracle.rank(g, kind)
+        assert r.tolist() == brute.order(g, kind), kind
+        assert oracle.wedges(g, r) == len(brute.wedges(g, r.tolist()))
+    perm = rng.permutation(g.n_u + g.n_v).astype(np.uint32)
+    assert oracle.wedges(g, perm) == len(brute.wedges(g, perm.tolist()))
+
+
+def test_rank_properties_er():
+    g = gg.workload_er_1k_planted()
+    u, v = g.edges()
+    deg = np.concatenate([np.diff(g.u_off), np.bincount(v, minlength=g.n_v)])
+    bound = int(np.minimum(deg[u], deg[g.n_u + v]).sum())  # sum over edges of min degree
+    for kind in KINDS:
+        r = oracle.rank(g, kind)
+        assert sorted(r.tolist()) == list(range(g.n_u + g.n_v))
+        seq = np.argsort(r)
+        w = oracle.wedges(g, r)
+        if kind == "degree":
+            assert (np.diff(deg[seq]) <= 0).all()
+        if kind == "approx_degree":
+            lv = np.array([brute.level(int(d)) for d in deg[seq]])
+            assert (np.diff(lv) <= 0).all()
+        # work bounds of the theorems in Sections 4.5-4.6
+        if kind in ("degree", "codeg"):
+            assert w <= bound
+        if kind in ("approx_degree", "approx_codeg"):
+            assert w <= 2 * bound
+    # side order wedges equal the closed form of each side
+    wu = int(sum(c2(int(d)) for d in deg[g.n_u:]))
+    wv = int(sum(c2(int(d)) for d in deg[:g.n_u]))
+    assert oracle.wedges(g, oracle.rank(g, "side_u")) == wu
+    assert oracle.wedges(g, oracle.rank(g, "side_v")) == wv
+    assert oracle.wedges(g, oracle.rank(g, "side_auto")) == min(wu, wv)
+
+
+def test_oracle_rejects_bad_csr():
+    g = gg.complete(3, 3)
+    bad = gg.BipartiteCSR(3, 3, g.u_off.copy(), g.u_adj.copy())
+    bad.u_adj[1] = bad.u_adj[0]  # duplicate edge
+    with pytest.raises(ValueError):
+        oracle.count(bad)
+    bad2 = gg.BipartiteCSR(3, 2, g.u_off.copy(), g.u_adj.copy())  # id out of range
+    with pytest.raises(ValueError):
+        oracle.count(bad2)
+
+
+def test_generators_deterministic():
+    a = gg.workload_er_1k(1)
+    b = gg.workload_er_1k(1)
+    assert a.sha256() == b.sha256() and a.m == 10_000
+    c = gg.workload_powerlaw_50m(scale=0.002)
+    d = gg.workload_powerlaw_50m(scale=0.002)
+    assert c.sha256() == d.sha256()
+    for g in (a, c):
+        for u in range(g.n_u):
+            row = g.u_adj[g.u_off[u]:g.u_off[u + 1]]
+            assert (np.diff(row.astype(np.int64)) > 0).all()
