@@ -34,6 +34,7 @@ def _load():
         for name in ("orc_bf4", "orc_pairs", "orc_count"):
             getattr(lib, name).argtypes = [_I, _I, _P, _P, _P, _P, _P]
         lib.orc_vside.argtypes = [_I, _I, _P, _P, _P, _P]
+        lib.orc_count_sample.argtypes = [_I, _I, _P, _P, _I, _P]
         lib.orc_vertex_one.argtypes = [_I, _I, _P, _P, _P, _P, _I, _P]
         lib.orc_edge_one.argtypes = [_I, _I, _P, _P, _P, _P, _I, _P]
         lib.orc_wedges.argtypes = [_I, _I, _P, _P, _P, _P, _P]
@@ -78,6 +79,18 @@ def count_pairs(g, want_vertex=True, want_edge=True):
 def count(g, want_vertex=True, want_edge=True):
     """The oracle proper: (global, per-vertex int64[n], per-edge int64[m])."""
     return _counts(_load().orc_count, g, want_vertex, want_edge)
+
+
+def count_sample(g, stride: int) -> float:
+    """Seconds the oracle proper takes on every stride-th endpoint (one thread);
+    times stride estimates its full run (a bounded CPU-baseline sample)."""
+    import time
+    off, adj = _csr(g)
+    glob = np.zeros(1, dtype=np.int64)
+    lib = _load()
+    t0 = time.perf_counter()
+    _check(lib.orc_count_sample(g.n_u, g.n_v, _ptr(off), _ptr(adj), int(stride), _ptr(glob)), "orc_count_sample")
+    return time.perf_counter() - t0
 
 
 class Sampler:

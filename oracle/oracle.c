@@ -196,8 +196,30 @@ int orc_pairs(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_
  *   b(s)   = (1/2) sum_{t in N(s)} b(t,s)  (a butterfly holds two edges at s)
  *   B      = (1/2) sum_t b(t)              (a butterfly holds two T vertices)
  */
+static int count_t2(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_adj,
+                    int64_t t_stride, int64_t *glob, int64_t *vert, int64_t *edge);
+
 int orc_count(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_adj,
               int64_t *glob, int64_t *vert, int64_t *edge) {
+    return count_t2(n_u, n_v, u_off, u_adj, 1, glob, vert, edge);
+}
+
+/* The same computation restricted to every t_stride-th endpoint (outputs are
+ * partial sums): lets a caller time a bounded sample of the full oracle run. */
+int orc_count_sample(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_adj,
+                     int64_t t_stride, int64_t *glob) {
+    if (t_stride < 1) return -1;
+    int64_t m = u_off[n_u];
+    int64_t *vert = (int64_t *)malloc((size_t)(n_u + n_v > 0 ? n_u + n_v : 1) * sizeof(int64_t));
+    int64_t *edge = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    int rc = (vert && edge) ? count_t2(n_u, n_v, u_off, u_adj, t_stride, glob, vert, edge) : -4;
+    free(vert);
+    free(edge);
+    return rc;
+}
+
+static int count_t2(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_adj,
+                    int64_t t_stride, int64_t *glob, int64_t *vert, int64_t *edge) {
     int rc = check_csr(n_u, n_v, u_off, u_adj);
     if (rc) return rc;
     int64_t m = u_off[n_u];
@@ -227,7 +249,7 @@ int orc_count(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_
     }
     zero_outputs(n_u + n_v, m, glob, vert, edge);
     int64_t twice_total = 0;
-    for (int64_t t = 0; t < n_t; ++t) {
+    for (int64_t t = 0; t < n_t; t += t_stride) {
         int64_t nt = 0;
         for (int64_t a = t_off[t]; a < t_off[t + 1]; ++a) {
             int64_t s = t_adj[a];

@@ -19,6 +19,8 @@ int orc_pairs(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_
               int64_t *glob, int64_t *vert, int64_t *edge);
 int orc_count(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_adj,
               int64_t *glob, int64_t *vert, int64_t *edge);
+int orc_count_sample(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_adj,
+                     int64_t t_stride, int64_t *glob);
 int orc_vside(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_adj,
               int64_t *v_off, uint32_t *v_adj);
 int orc_vertex_one(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_adj,
