@@ -1,0 +1,207 @@
+/*
+ * parbutterfly: exact butterfly ((2,2)-biclique) counting on bipartite graphs,
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The method is the ranked wedge framework of Shi and Shun, "Parallel
+ * Algorithms for Butterfly Computations" (arXiv 1907.08607), Section 3.1
+ * (framework figure "ParButterfly Framework for Counting"):
+ *   1. rank the vertices (Section 3.1.1);
+ *   2. retrieve every wedge (x1, y, x2) with rank(y) > rank(x1) and
+ *      rank(x2) > rank(x1) (Algorithm 2, GET-WEDGES);
+ *   3. count the wedges of each endpoint pair, R(x1, x2) (GET-FREQ, Section 3.1.2);
+ *   4. turn the pair counts into butterfly counts: C(R, 2) per pair for the
+ *      total (Section 3.1.3 footnote) and for each endpoint, R - 1 per wedge for
+ *      its center (Algorithm 3, COUNT-V) and for its two edges (Algorithm 4,
+ *      COUNT-E).
+ * All counts are exact int64 integers; the result never depends on the
+ * ranking, the aggregator or the launch configuration.
+ *
+ * Conventions used by every call:
+ *   - Input graph: a U-side CSR with row offsets u_off[n_u + 1] (int64, device)
+ *     and column ids u_adj[m] (uint32 V-local ids, device).  Every row must be
+ *     strictly increasing (the graph is simple, Section 2) and every id < n_v.
+ *     The arrays stay owned by the caller and must outlive the pb_graph.
+ *   - Unified vertex ids: U vertices are 0 .. n_u-1, V vertices n_u .. n_u+n_v-1
+ *     (the two sides' arrays are stored consecutively, Section 2).
+ *   - Per-vertex outputs are indexed by unified id; per-edge outputs by the
+ *     edge's position in u_adj.
+ *   - Limits: m < 2^31 and n_u + n_v < 2^32 - 1.
+ *   - Every buffer argument named "device" is device memory on the current
+ *     HIP device; the caller owns all input and output buffers and the library
+ *     never frees them.
+ *   - Work is enqueued on the given stream; outputs are valid once that stream
+ *     has been synchronised.  Calls that must read device-side results back
+ *     (validation flags, the work plan) synchronise the stream themselves; this
+ *     is stated per call.
+ *   - No call aborts or prints.  Errors are returned as pb_status; arguments are
+ *     checked before any work is enqueued.
+ */
+#ifndef PARBUTTERFLY_H
+#define PARBUTTERFLY_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PB_OK = 0,
+    PB_ERR_INVALID_ARG = -1, /* null pointer, size out of range, unknown enum value */
+    PB_ERR_NOT_SIMPLE = -2,  /* a CSR row is not strictly increasing (duplicate edge) */
+    PB_ERR_ID_RANGE = -3,    /* a column id >= n_v, or u_off is not a valid offset array */
+    PB_ERR_BAD_RANK = -4,    /* rank is not a permutation of [0, n) */
+    PB_ERR_NO_MEMORY = -5,   /* device allocation failed or the workspace cap is too small */
+    PB_ERR_OVERFLOW = -6,    /* a count would not fit int64 */
+    PB_ERR_HIP = -7          /* a HIP runtime call failed */
+} pb_status;
+
+/* The bipartite input graph (U-side CSR, device pointers). */
+typedef struct {
+    uint32_t n_u;
+    uint32_t n_v;
+    uint64_t m;
+    const int64_t *u_off;  /* device, n_u + 1 entries, u_off[0] = 0, u_off[n_u] = m */
+    const uint32_t *u_adj; /* device, m entries */
+} pb_csr;
+
+/* Vertex orderings (Section 3.1.1 "Ranking").  rank[x] is the index of
+ * unified id x in the order; wedges are rooted at their lowest-ranked vertex.
+ * Ties are broken by the smaller unified id.
+ *   SIDE_AUTO     one side wholly first: the side whose choice retrieves fewer
+ *                 wedges, U first iff sum_{v in V} C(deg v, 2) <= sum_{u in U} C(deg u, 2)
+ *   SIDE_U_FIRST, SIDE_V_FIRST   one side forced first
+ *   DEGREE        decreasing degree
+ *   APPROX_DEGREE decreasing floor(log2(degree)); degree 0 last
+ *   COMPLEMENT_CORENESS          complement degeneracy order: rounds, each
+ *                 removing every remaining vertex whose current degree (count
+ *                 of remaining neighbours) equals the largest one; the removed
+ *                 vertices take the next ranks in id order
+ *   APPROX_COMPLEMENT_CORENESS   the same with floor(log2(current degree)) as
+ *                 the key (degree 0 -> -1) */
+typedef enum {
+    PB_RANK_SIDE_AUTO = 0,
+    PB_RANK_SIDE_U_FIRST = 1,
+    PB_RANK_SIDE_V_FIRST = 2,
+    PB_RANK_DEGREE = 3,
+    PB_RANK_APPROX_DEGREE = 4,
+    PB_RANK_COMPLEMENT_CORENESS = 5,
+    PB_RANK_APPROX_COMPLEMENT_CORENESS = 6
+} pb_rank_kind;
+
+/* Wedge aggregation (GET-FREQ, Section 3.1.2).  AUTO picks per source by the
+ * source's wedge count and candidate range; the others force one method for
+ * every source (results are identical, only speed differs).
+ *   LDS_HASH    per-workgroup linear-probing hash table in LDS keyed by x2
+ *   DENSE_HIST  dense per-source histogram over the x2 id range, swept in
+ *               LDS-sized windows of that range
+ *   RADIX_SORT  64-bit (x1, x2) keys radix-sorted in LDS, then run lengths */
+typedef enum {
+    PB_AGG_AUTO = 0,
+    PB_AGG_LDS_HASH = 1,
+    PB_AGG_DENSE_HIST = 2,
+    PB_AGG_RADIX_SORT = 3
+} pb_agg;
+
+/* Dense int8 matrix-core path for hub-to-hub endpoint pairs. */
+typedef enum {
+    PB_HUB_AUTO = 0,
+    PB_HUB_OFF = 1,
+    PB_HUB_FORCE = 2
+} pb_hub_mode;
+
+/* Figures a counting call reports back (host memory, optional). */
+typedef struct {
+    uint64_t wedges;          /* wedges retrieved under the ranking (framework step 2) */
+    uint64_t sources;         /* sources with at least one wedge */
+    uint64_t sources_hash;    /* sources aggregated in an LDS hash table */
+    uint64_t sources_dense;   /* sources aggregated by dense LDS windows */
+    uint64_t sources_sort;    /* sources aggregated by LDS radix sort */
+    uint64_t window_items;    /* (source, x2-window) work items launched */
+    uint64_t wedges_hash;     /* wedges of the hash-aggregated sources */
+    uint64_t wedges_dense;    /* wedges of the dense-window sources */
+    uint64_t wedges_sort;     /* wedges of the sort-aggregated sources */
+    uint64_t wedges_hub;      /* wedges covered by dense hub tiles */
+    uint64_t workspace_bytes; /* peak device scratch the call allocated */
+    /* Phase times in milliseconds, measured with HIP events on the call's
+     * stream; filled only when opts.flags has PB_FLAG_TIMING (which adds one
+     * stream synchronisation at the end of the call). */
+    double ms_prepare;        /* rank check, relabel, modified degrees, plan */
+    double ms_dense;          /* dense-window counting kernel */
+    double ms_hash;           /* hash counting kernels */
+    double ms_sort;           /* radix-sort counting kernel */
+    double ms_output;         /* output combine */
+} pb_stats;
+
+/* opts.flags bits */
+#define PB_FLAG_TIMING 1u
+
+typedef struct {
+    pb_agg agg;
+    pb_hub_mode hub;
+    uint64_t workspace_cap_bytes; /* 0: no cap beyond the device's free memory */
+    uint32_t wg_size;             /* reserved, 0 */
+    uint32_t flags;               /* PB_FLAG_* bits, 0 for none */
+    pb_stats *stats;              /* optional host pointer, filled by the call */
+} pb_opts;
+
+typedef struct pb_graph pb_graph;
+
+/* Fills opts with the defaults (AUTO aggregation, AUTO hub mode, no cap). */
+void pb_opts_default(pb_opts *opts);
+
+/* Human-readable name of a status code (static storage). */
+const char *pb_status_str(pb_status status);
+
+/* Validates the CSR (rows strictly increasing, ids in range, offsets
+ * consistent) and builds the derived V-side CSR and degrees (Section 2 keeps
+ * a CSR per side).  The graph handle owns only the derived arrays.
+ * Synchronises `stream` once to read the validation result.
+ * Errors: INVALID_ARG, NOT_SIMPLE, ID_RANGE, NO_MEMORY, HIP. */
+pb_status pb_graph_create(const pb_csr *csr, hipStream_t stream, pb_graph **out);
+
+/* Releases the handle and everything it owns (NULL is ignored).  Waits for
+ * work the handle has enqueued to finish first. */
+void pb_graph_destroy(pb_graph *g);
+
+/* Writes a vertex ordering of kind `kind` (Section 3.1.1, see pb_rank_kind):
+ * rank_out[x] for every unified id x (device, n_u + n_v entries).
+ * Synchronises `stream` (once for the side and degree orders, once per
+ * removal round for the complement-coreness orders).
+ * Errors: INVALID_ARG, NO_MEMORY, HIP. */
+pb_status pb_rank(pb_graph *g, pb_rank_kind kind, uint32_t *rank_out, hipStream_t stream);
+
+/* Counts butterflies (framework steps 2-4) under the caller's ranking.
+ * `rank` (device, n entries) may be any permutation of [0, n) — the result
+ * does not depend on it, only the work does.  Any subset of the outputs may
+ * be requested (NULL = not wanted, at least one required):
+ *   global_out  device int64[1]: the number of butterflies
+ *   vertex_out  device int64[n_u + n_v]: butterflies per vertex (unified ids)
+ *   edge_out    device int64[m]: butterflies per edge (u_adj positions)
+ * Synchronises `stream` three times: after the rank check, after the work
+ * plan (to size the launches) and at the end (to confirm that no internal
+ * capacity check tripped), so the outputs are ready when it returns.
+ * Errors: INVALID_ARG (also when max degree * 1024 >= 2^32), BAD_RANK,
+ * NO_MEMORY, HIP. */
+pb_status pb_count(pb_graph *g, const uint32_t *rank, const pb_opts *opts, int64_t *global_out,
+                   int64_t *vertex_out, int64_t *edge_out, hipStream_t stream);
+
+/* The total count alone (framework steps 2-4 with only the C(R,2) sum). */
+pb_status pb_count_global(pb_graph *g, const uint32_t *rank, const pb_opts *opts, int64_t *out,
+                          hipStream_t stream);
+
+/* Per-vertex counts alone (Algorithm 3, COUNT-V). */
+pb_status pb_count_vertex(pb_graph *g, const uint32_t *rank, const pb_opts *opts, int64_t *out,
+                          hipStream_t stream);
+
+/* Per-edge counts alone (Algorithm 4, COUNT-E). */
+pb_status pb_count_edge(pb_graph *g, const uint32_t *rank, const pb_opts *opts, int64_t *out,
+                        hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PARBUTTERFLY_H */

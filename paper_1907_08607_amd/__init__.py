@@ -1,0 +1,235 @@
+"""Python binding of libparbutterfly (exact butterfly counting on MI355X).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library's kernels.  Device memory and streams come from PyTorch.  The
+function names mirror the C ABI in include/parbutterfly.h.
+
+    import torch, paper_1907_08607_amd as pb
+    g = pb.Graph(n_u, n_v, u_off_cuda_int64, u_adj_cuda_uint32)
+    rank = pb.pb_rank(g, "degree")
+    total, per_vertex, per_edge = pb.pb_count(g, rank)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libparbutterfly.so")
+
+PB_OK = 0
+STATUS = {
+    0: "PB_OK", -1: "PB_ERR_INVALID_ARG", -2: "PB_ERR_NOT_SIMPLE", -3: "PB_ERR_ID_RANGE",
+    -4: "PB_ERR_BAD_RANK", -5: "PB_ERR_NO_MEMORY", -6: "PB_ERR_OVERFLOW", -7: "PB_ERR_HIP",
+}
+RANK_KINDS = {
+    "side_auto": 0, "side_u": 1, "side_v": 2, "degree": 3, "approx_degree": 4,
+    "codeg": 5, "approx_codeg": 6,
+}
+AGGS = {"auto": 0, "hash": 1, "dense": 2, "sort": 3}
+HUBS = {"auto": 0, "off": 1, "force": 2}
+
+
+class PBError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {STATUS.get(status, status)} ({status_str(status)})")
+
+
+class pb_csr(ctypes.Structure):
+    _fields_ = [("n_u", ctypes.c_uint32), ("n_v", ctypes.c_uint32), ("m", ctypes.c_uint64),
+                ("u_off", ctypes.c_void_p), ("u_adj", ctypes.c_void_p)]
+
+
+PB_FLAG_TIMING = 1
+
+
+class pb_stats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_uint64) for name in (
+        "wedges", "sources", "sources_hash", "sources_dense", "sources_sort", "window_items",
+        "wedges_hash", "wedges_dense", "wedges_sort", "wedges_hub", "workspace_bytes")] + [
+        (name, ctypes.c_double) for name in ("ms_prepare", "ms_dense", "ms_hash", "ms_sort", "ms_output")]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class pb_opts(ctypes.Structure):
+    _fields_ = [("agg", ctypes.c_int), ("hub", ctypes.c_int), ("workspace_cap_bytes", ctypes.c_uint64),
+                ("wg_size", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("stats", ctypes.POINTER(pb_stats))]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libparbutterfly.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1907_08607_amd.build` "
+                          "or __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.pb_opts_default.argtypes = [ctypes.POINTER(pb_opts)]
+    lib.pb_opts_default.restype = None
+    lib.pb_status_str.argtypes = [ctypes.c_int]
+    lib.pb_status_str.restype = ctypes.c_char_p
+    lib.pb_graph_create.argtypes = [ctypes.POINTER(pb_csr), P, ctypes.POINTER(P)]
+    lib.pb_graph_create.restype = ctypes.c_int
+    lib.pb_graph_destroy.argtypes = [P]
+    lib.pb_graph_destroy.restype = None
+    lib.pb_rank.argtypes = [P, ctypes.c_int, P, P]
+    lib.pb_rank.restype = ctypes.c_int
+    lib.pb_count.argtypes = [P, P, ctypes.POINTER(pb_opts), P, P, P, P]
+    lib.pb_count.restype = ctypes.c_int
+    for name in ("pb_count_global", "pb_count_vertex", "pb_count_edge"):
+        fn = getattr(lib, name)
+        fn.argtypes = [P, P, ctypes.POINTER(pb_opts), P, P]
+        fn.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def status_str(status: int) -> str:
+    return load_library().pb_status_str(int(status)).decode()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(status: int, what: str):
+    if status != PB_OK:
+        raise PBError(status, what)
+
+
+def _dev_ptr(t, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Graph:
+    """A validated bipartite graph on the device (owns the derived V-side CSR).
+
+    u_off: int64 CUDA tensor [n_u + 1]; u_adj: int32/uint32 CUDA tensor [m] of
+    V ids, each row strictly increasing.  The tensors are kept alive here."""
+
+    def __init__(self, n_u: int, n_v: int, u_off, u_adj, stream=None):
+        torch = _torch()
+        lib = load_library()
+        if u_adj.device.type != "cuda" or u_adj.dtype not in (torch.int32, getattr(torch, "uint32", torch.int32)):
+            raise TypeError("u_adj must be a 32-bit CUDA (HIP) tensor")
+        self.n_u, self.n_v, self.m = int(n_u), int(n_v), int(u_adj.numel())
+        self.u_off, self.u_adj = u_off, u_adj
+        csr = pb_csr(self.n_u, self.n_v, self.m, _dev_ptr(u_off, torch.int64, "u_off"),
+                     ctypes.c_void_p(u_adj.data_ptr()) if self.m else None)
+        if u_off.numel() != self.n_u + 1:
+            raise ValueError("u_off must have n_u + 1 entries")
+        handle = ctypes.c_void_p()
+        _check(lib.pb_graph_create(ctypes.byref(csr), _stream(stream), ctypes.byref(handle)), "pb_graph_create")
+        self._h = handle
+
+    @property
+    def n(self) -> int:
+        return self.n_u + self.n_v
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("graph destroyed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load_library().pb_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @classmethod
+    def from_csr(cls, csr, device="cuda", stream=None):
+        """From an object with n_u, n_v, u_off (numpy int64), u_adj (numpy uint32)."""
+        torch = _torch()
+        import numpy as np
+        off = torch.from_numpy(np.ascontiguousarray(csr.u_off, dtype=np.int64)).to(device)
+        adj = torch.from_numpy(np.ascontiguousarray(csr.u_adj, dtype=np.uint32).view(np.int32)).to(device)
+        return cls(csr.n_u, csr.n_v, off, adj, stream)
+
+
+def make_opts(agg="auto", hub="auto", workspace_cap=0, stats=None, timing=False) -> pb_opts:
+    o = pb_opts()
+    load_library().pb_opts_default(ctypes.byref(o))
+    if timing:
+        o.flags |= PB_FLAG_TIMING
+    o.agg = AGGS[agg] if isinstance(agg, str) else int(agg)
+    o.hub = HUBS[hub] if isinstance(hub, str) else int(hub)
+    o.workspace_cap_bytes = int(workspace_cap)
+    if stats is not None:
+        o.stats = ctypes.pointer(stats)
+    return o
+
+
+def pb_rank(g: Graph, kind="degree", out=None, stream=None):
+    """Vertex ordering (int32 CUDA tensor holding uint32 ranks, n entries)."""
+    torch = _torch()
+    k = RANK_KINDS[kind] if isinstance(kind, str) else int(kind)
+    if out is None:
+        out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    _check(load_library().pb_rank(g.handle, k, _dev_ptr(out, torch.int32, "rank"), _stream(stream)), "pb_rank")
+    return out
+
+
+def pb_count(g: Graph, rank, want_global=True, want_vertex=True, want_edge=True, agg="auto", hub="auto",
+             workspace_cap=0, stats: pb_stats | None = None, outs=None, stream=None, timing=False):
+    """(global int64 tensor[1] or None, per-vertex int64[n] or None, per-edge int64[m] or None)."""
+    torch = _torch()
+    if outs is None:
+        outs = (torch.empty(1, dtype=torch.int64, device="cuda") if want_global else None,
+                torch.empty(g.n, dtype=torch.int64, device="cuda") if want_vertex else None,
+                torch.empty(g.m, dtype=torch.int64, device="cuda") if want_edge else None)
+    gout, vout, eout = outs
+    opts = make_opts(agg, hub, workspace_cap, stats, timing)
+    ptr = lambda t, name: None if t is None else _dev_ptr(t, torch.int64, name)
+    _check(load_library().pb_count(g.handle, _dev_ptr(rank, torch.int32, "rank"), ctypes.byref(opts),
+                                   ptr(gout, "global_out"), ptr(vout, "vertex_out"), ptr(eout, "edge_out"),
+                                   _stream(stream)), "pb_count")
+    return gout, vout, eout
+
+
+def _single(name, g, rank, n_out, agg, hub, workspace_cap, stats, stream):
+    torch = _torch()
+    out = torch.empty(n_out, dtype=torch.int64, device="cuda")
+    opts = make_opts(agg, hub, workspace_cap, stats)
+    _check(getattr(load_library(), name)(g.handle, _dev_ptr(rank, torch.int32, "rank"), ctypes.byref(opts),
+                                         _dev_ptr(out, torch.int64, "out"), _stream(stream)), name)
+    return out
+
+
+def pb_count_global(g, rank, agg="auto", hub="auto", workspace_cap=0, stats=None, stream=None):
+    return _single("pb_count_global", g, rank, 1, agg, hub, workspace_cap, stats, stream)
+
+
+def pb_count_vertex(g, rank, agg="auto", hub="auto", workspace_cap=0, stats=None, stream=None):
+    return _single("pb_count_vertex", g, rank, g.n, agg, hub, workspace_cap, stats, stream)
+
+
+def pb_count_edge(g, rank, agg="auto", hub="auto", workspace_cap=0, stats=None, stream=None):
+    return _single("pb_count_edge", g, rank, g.m, agg, hub, workspace_cap, stats, stream)

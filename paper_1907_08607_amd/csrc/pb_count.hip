@@ -1,0 +1,715 @@
+// Butterfly counting: relabel by rank, plan, wedge retrieval + aggregation,
+// butterfly credit, output combine.
+//
+// Paper map (arXiv 1907.08607):
+//   relabel + modified degrees   Algorithm 1 (PREPROCESS), Section 4.1
+//   wedge retrieval              Algorithm 2 (GET-WEDGES), Section 4.2.1
+//   wedge aggregation            GET-FREQ, Sections 3.1.2 and 4.2.1
+//   butterfly credit             Section 3.1.3, Algorithms 3 (COUNT-V) and 4 (COUNT-E)
+//
+// Layout after relabelling.  Vertices are renamed to their rank r.  N(r) is
+// stored at nbr[roff[r] .. roff[r+1]) sorted by decreasing rank, so the
+// neighbours ranked above r form the prefix of length hideg[r] (the modified
+// degree deg_r(r) of Section 4.1).  A neighbour is stored by its side-major id
+// (smid): U vertices in rank order take 0..n_u-1, V vertices n_u..n-1; within
+// one side smid increases with rank, so every list is also sorted by
+// decreasing smid and an smid range of candidate endpoints is a contiguous
+// part of each list.
+//   For each "up-slot" (r -> y, rank y > r) the run N(y)[0 .. pos) with
+// pos = position of r in N(y) = deg_r(y) holds exactly the second endpoints
+// x2 with rank x2 > r (Algorithm 2 inner loop).  Up-slots of r are numbered
+// upoff[r] .. upoff[r+1]; uprun[k] = roff[y], uplen[k] = pos.
+#include "pb_internal.h"
+
+#include <algorithm>
+
+using namespace pb;
+
+namespace {
+
+enum : int { MODE_GLOBAL = 1, MODE_VERTEX = 2, MODE_EDGE = 4 };
+enum : uint32_t { FLAG_BAD_RANK = 1u, FLAG_INTERNAL = 2u };
+
+constexpr uint32_t EMPTY = 0xFFFFFFFFu;
+
+inline uint32_t grid_for(uint64_t n, uint32_t block = 256, uint32_t cap = 65536) {
+    uint64_t g = (n + block - 1) / block;
+    if (g == 0) g = 1;
+    return (uint32_t)(g > cap ? cap : g);
+}
+
+#define GRID_STRIDE(i, n)                                                           \
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); \
+         i += (uint64_t)gridDim.x * blockDim.x)
+
+// ---------------------------------------------------------------- relabel
+
+__global__ void k_rank_check(const uint32_t *rank, uint64_t n, uint32_t *order, uint32_t *seen,
+                             uint32_t *flags) {
+    GRID_STRIDE(x, n) {
+        const uint32_t r = rank[x];
+        if (r >= n) { atomicOr(flags, FLAG_BAD_RANK); continue; }
+        if (atomicAdd(&seen[r], 1u) != 0) atomicOr(flags, FLAG_BAD_RANK);
+        order[r] = (uint32_t)x;
+    }
+}
+
+__global__ void k_rank_side(const uint32_t *order, const uint32_t *deg, uint64_t n, uint32_t n_u,
+                            uint32_t *isv, uint32_t *rdeg) {
+    GRID_STRIDE(r, n) {
+        const uint32_t x = order[r];
+        isv[r] = x >= n_u;
+        rdeg[r] = deg[x];
+    }
+}
+
+__global__ void k_smid(const uint32_t *isv, const uint32_t *vbefore, uint64_t n, uint32_t n_u,
+                       uint32_t *smid) {
+    GRID_STRIDE(r, n) smid[r] = isv[r] ? n_u + vbefore[r] : (uint32_t)r - vbefore[r];
+}
+
+// Two directed slots per edge e: value 2e (U -> V) and 2e+1 (V -> U).  Key =
+// source rank in the high bits, complemented destination rank in the low bits,
+// so ascending keys give rows in rank order with neighbours by decreasing rank.
+__global__ void k_slot_keys(const uint32_t *eu, const uint32_t *u_adj, const uint32_t *rank, uint64_t m,
+                            uint32_t n_u, int b, uint64_t *keys, uint32_t *vals) {
+    const uint64_t mask = (uint64_t(1) << b) - 1;
+    GRID_STRIDE(e, m) {
+        const uint64_t ru = rank[eu[e]], rv = rank[n_u + u_adj[e]];
+        keys[2 * e] = (ru << b) | (mask - rv);
+        keys[2 * e + 1] = (rv << b) | (mask - ru);
+        vals[2 * e] = (uint32_t)(2 * e);
+        vals[2 * e + 1] = (uint32_t)(2 * e + 1);
+    }
+}
+
+__global__ void k_slots(const uint64_t *keys, const uint32_t *vals, uint64_t ns, int b, const uint32_t *smid,
+                        const uint32_t *roff, uint32_t *nbr, uint32_t *eslot, uint32_t *hideg) {
+    const uint64_t mask = (uint64_t(1) << b) - 1;
+    GRID_STRIDE(p, ns) {
+        const uint64_t key = keys[p];
+        const uint32_t r = (uint32_t)(key >> b);
+        const uint32_t d = (uint32_t)(mask - (key & mask));
+        nbr[p] = smid[d];
+        eslot[vals[p]] = (uint32_t)p;
+        if (d > r) {
+            bool last_up = p + 1 == ns;
+            if (!last_up) {
+                const uint64_t k2 = keys[p + 1];
+                const uint32_t r2 = (uint32_t)(k2 >> b);
+                const uint32_t d2 = (uint32_t)(mask - (k2 & mask));
+                last_up = r2 != r || d2 < r;
+            }
+            if (last_up) hideg[r] = (uint32_t)(p + 1 - roff[r]);
+        }
+    }
+}
+
+__global__ void k_upslots(const uint64_t *keys, const uint32_t *vals, uint64_t ns, int b, const uint32_t *roff,
+                          const uint32_t *upoff, const uint32_t *eslot, uint32_t *uprun, uint32_t *uplen) {
+    const uint64_t mask = (uint64_t(1) << b) - 1;
+    GRID_STRIDE(p, ns) {
+        const uint64_t key = keys[p];
+        const uint32_t r = (uint32_t)(key >> b);
+        const uint32_t d = (uint32_t)(mask - (key & mask));
+        if (d > r && p - roff[r] < upoff[r + 1] - upoff[r]) {
+            const uint32_t k = upoff[r] + (uint32_t)(p - roff[r]);
+            const uint32_t rev = eslot[vals[p] ^ 1u];  // slot (d -> r)
+            uprun[k] = roff[d];
+            uplen[k] = rev - roff[d];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- plan
+
+enum : int { LIST_LIGHT = 0, LIST_MEDIUM = 1, LIST_HEAVY = 2, LIST_SMALLDENSE = 3, NLISTS = 4 };
+
+constexpr uint32_t LIGHT_D = 512;     // distinct bound handled by the 1-wave hash (1024 slots)
+constexpr uint32_t MEDIUM_D = 4096;   // distinct bound handled by the 256-thread hash (8192 slots)
+constexpr uint32_t SMALL_WIN = 4096;  // dense window of the 256-thread dense kernel
+constexpr uint32_t BIG_WIN = 32768;   // dense window of the 1024-thread dense kernel
+constexpr uint32_t HASH_WIN = 4096;   // candidate window of a forced-hash heavy item
+
+struct PlanCounts {
+    uint32_t list[NLISTS];
+    uint32_t items;  // heavy (source, window) items
+    uint32_t flags;
+    unsigned long long sources;
+    unsigned long long wedges[NLISTS];
+};
+
+__global__ void k_plan(const uint32_t *upoff, const uint64_t *wscan, const uint32_t *smid, const uint32_t *isv,
+                       uint64_t n, uint32_t n_u, int agg, uint32_t *lists, uint32_t *heavy_nwin,
+                       uint64_t *heavy_w, PlanCounts *pc) {
+    GRID_STRIDE(r, n) {
+        const uint64_t w = wscan[upoff[r + 1]] - wscan[upoff[r]];
+        if (w == 0) continue;
+        atomicAdd(&pc->sources, 1ull);
+        const uint32_t side_end = isv[r] ? (uint32_t)n : n_u;
+        const uint32_t range = side_end - smid[r] - 1;
+        const uint64_t dist = w < range ? w : range;
+        int which;
+        uint32_t win = 0;
+        if (agg == PB_AGG_LDS_HASH) {
+            if (dist <= LIGHT_D) which = LIST_LIGHT;
+            else if (dist <= MEDIUM_D) which = LIST_MEDIUM;
+            else { which = LIST_HEAVY; win = HASH_WIN; }
+        } else if (agg == PB_AGG_DENSE_HIST) {
+            if (range <= SMALL_WIN) which = LIST_SMALLDENSE;
+            else { which = LIST_HEAVY; win = BIG_WIN; }
+        } else {  // AUTO
+            if (dist <= LIGHT_D) which = LIST_LIGHT;
+            else if (dist <= MEDIUM_D) which = LIST_MEDIUM;
+            else { which = LIST_HEAVY; win = BIG_WIN; }
+        }
+        const uint32_t slot = atomicAdd(&pc->list[which], 1u);
+        atomicAdd(&pc->wedges[which], (unsigned long long)w);
+        lists[(uint64_t)which * n + slot] = (uint32_t)r;
+        if (which == LIST_HEAVY) {
+            const uint32_t nw = (range + win - 1) / win;
+            heavy_nwin[slot] = nw;
+            heavy_w[slot] = w;
+            atomicAdd(&pc->items, nw);
+        }
+    }
+}
+
+// Sort key for the heavy list: most wedges per window first (longest items
+// are dispatched first).
+__global__ void k_heavy_keys(const uint32_t *heavy, const uint32_t *nwin, const uint64_t *w, uint32_t nh,
+                             uint64_t *keys, uint32_t *vals) {
+    GRID_STRIDE(i, (uint64_t)nh) {
+        uint64_t per = w[i] / nwin[i];
+        if (per > 0xFFFFFFFFull) per = 0xFFFFFFFFull;
+        keys[i] = 0xFFFFFFFFull - per;
+        vals[i] = (uint32_t)i;
+    }
+}
+
+__global__ void k_heavy_gather(const uint32_t *perm, const uint32_t *heavy, const uint32_t *nwin, uint32_t nh,
+                               uint32_t *src_sorted, uint32_t *nwin_sorted) {
+    GRID_STRIDE(i, (uint64_t)nh) {
+        src_sorted[i] = heavy[perm[i]];
+        nwin_sorted[i] = nwin[perm[i]];
+    }
+}
+
+__global__ void k_heavy_expand(const uint32_t *src_sorted, const uint32_t *nwin_sorted, const uint32_t *ioff,
+                               uint32_t nh, uint2 *items) {
+    GRID_STRIDE(i, (uint64_t)nh) {
+        const uint32_t o = ioff[i];
+        for (uint32_t w = 0; w < nwin_sorted[i]; ++w) items[o + w] = make_uint2(src_sorted[i], w);
+    }
+}
+
+// ---------------------------------------------------------------- counting
+
+struct Ranked {
+    const uint32_t *roff, *nbr, *upoff, *uprun, *uplen, *smid, *isv;
+    uint32_t n_u, n;
+};
+
+struct Acc {
+    unsigned long long *g;  // 1
+    unsigned long long *v;  // n, by smid
+    unsigned long long *s;  // 2m, by slot
+    uint32_t *err;          // internal-consistency flag
+    int mode;
+};
+
+// Smallest i in [0, len] with p[i] < v (p strictly decreasing).
+__device__ inline uint32_t first_below(const uint32_t *p, uint32_t len, uint32_t v) {
+    uint32_t lo = 0, hi = len;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (p[mid] < v) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// Dense counters for the candidate window [lo, lo + size).
+template <int T>
+struct DenseAgg {
+    uint32_t *cnt;
+    uint32_t lo, size;
+    __device__ void init() const {
+        for (uint32_t i = threadIdx.x; i < size; i += T) cnt[i] = 0;
+    }
+    uint32_t *err;
+    __device__ void insert(uint32_t x) const {
+        if (x - lo < size) atomicAdd(&cnt[x - lo], 1u);
+        else atomicOr(err, FLAG_INTERNAL);
+    }
+    __device__ uint32_t count(uint32_t x) const { return x - lo < size ? cnt[x - lo] : 1u; }
+    template <class F>
+    __device__ void for_each(F f) const {
+        for (uint32_t i = threadIdx.x; i < size; i += T) {
+            const uint32_t c = cnt[i];
+            if (c) f(lo + i, c);
+        }
+    }
+};
+
+// Linear-probing hash table keyed by x2 (capacity a power of two).
+template <int T, int CAP>
+struct HashAgg {
+    uint32_t *keys, *cnts;
+    uint32_t *err;
+    __device__ static uint32_t slot(uint32_t x) { return (x * 2654435769u) >> (32 - __builtin_ctz(CAP)); }
+    __device__ void init() const {
+        for (uint32_t i = threadIdx.x; i < CAP; i += T) { keys[i] = EMPTY; cnts[i] = 0; }
+    }
+    // The planner sizes CAP to at least twice the distinct keys; a full table
+    // (which the plan rules out) is reported instead of probed forever.
+    __device__ void insert(uint32_t x) const {
+        uint32_t h = slot(x);
+        for (int probe = 0; probe < CAP; ++probe) {
+            uint32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (k == EMPTY) {
+                k = atomicCAS(&keys[h], EMPTY, x);
+                if (k == EMPTY) k = x;
+            }
+            if (k == x) { atomicAdd(&cnts[h], 1u); return; }
+            h = (h + 1) & (CAP - 1);
+        }
+        atomicOr(err, FLAG_INTERNAL);
+    }
+    __device__ uint32_t count(uint32_t x) const {
+        uint32_t h = slot(x);
+        for (int probe = 0; probe < CAP; ++probe) {
+            if (keys[h] == x) return cnts[h];
+            h = (h + 1) & (CAP - 1);
+        }
+        return 1u;
+    }
+    template <class F>
+    __device__ void for_each(F f) const {
+        for (uint32_t i = threadIdx.x; i < CAP; i += T) {
+            const uint32_t k = keys[i];
+            if (k != EMPTY) f(k, cnts[i]);
+        }
+    }
+};
+
+template <int T>
+struct RunShared {
+    uint32_t off[T];
+    uint32_t begin[T];
+    unsigned long long sum[T];
+    uint32_t tmp[T / WAVE + 1];
+    unsigned long long tmp64[T / WAVE + 1];
+};
+
+// Largest i with off[i] <= f among i < T (off non-decreasing, off[0] = 0).
+template <int T>
+__device__ inline uint32_t run_of(const uint32_t *off, uint32_t f) {
+    uint32_t lo = 0, hi = T;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= f) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// One work item: source r, candidate x2 window [lo, hi).  Pass 1 retrieves the
+// wedges (Algorithm 2) into the aggregator (GET-FREQ); the endpoint step adds
+// C(R,2) per pair (total, and both endpoints for per-vertex); pass 2 walks the
+// wedges again and adds R-1 to each center / both edges (Algorithms 3, 4).
+template <int T, class Agg>
+__device__ void count_item(const Ranked &G, const Acc &A, uint32_t r, uint32_t lo, uint32_t hi, const Agg &agg,
+                           RunShared<T> &sh) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t k0 = G.upoff[r], k1 = G.upoff[r + 1];
+    const uint32_t side_end = G.isv[r] ? G.n : G.n_u;
+    const bool windowed = !(lo == G.smid[r] + 1 && hi == side_end);
+    agg.init();
+    __syncthreads();
+    const int passes = (A.mode & (MODE_VERTEX | MODE_EDGE)) ? 2 : 1;
+    for (int pass = 1; pass <= passes; ++pass) {
+        for (uint32_t c = k0; c < k1; c += T) {
+            const uint32_t k = c + tid;
+            uint32_t a = 0, cnt = 0, start = 0;
+            if (k < k1) {
+                start = G.uprun[k];
+                const uint32_t len = G.uplen[k];
+                if (windowed) {
+                    a = first_below(G.nbr + start, len, hi);
+                    cnt = first_below(G.nbr + start, len, lo) - a;
+                } else {
+                    cnt = len;
+                }
+            }
+            uint32_t total;
+            const uint32_t off = block_exclusive_sum<T>(cnt, sh.tmp, &total);
+            sh.off[tid] = off;
+            sh.begin[tid] = start + a;
+            if (pass == 2) sh.sum[tid] = 0;
+            __syncthreads();
+            for (uint32_t f = tid; f < total; f += T) {
+                const uint32_t i = run_of<T>(sh.off, f);
+                const uint32_t p = sh.begin[i] + (f - sh.off[i]);
+                const uint32_t x2 = G.nbr[p];
+                if (pass == 1) {
+                    agg.insert(x2);
+                } else {
+                    const uint32_t d = agg.count(x2) - 1;
+                    if (d) {
+                        if (A.mode & MODE_EDGE) atomicAdd(&A.s[p], (unsigned long long)d);
+                        atomicAdd(&sh.sum[i], (unsigned long long)d);
+                    }
+                }
+            }
+            __syncthreads();
+            if (pass == 2 && k < k1) {
+                const unsigned long long s = sh.sum[tid];
+                if (s) {
+                    const uint32_t up = G.roff[r] + (k - k0);  // slot (r -> y)
+                    if (A.mode & MODE_VERTEX) atomicAdd(&A.v[G.nbr[up]], s);
+                    if (A.mode & MODE_EDGE) atomicAdd(&A.s[up], s);
+                }
+            }
+        }
+        if (pass == 1) {
+            __syncthreads();
+            unsigned long long local = 0;
+            const bool vert = A.mode & MODE_VERTEX;
+            agg.for_each([&](uint32_t key, uint32_t c) {
+                if (c >= 2) {
+                    const unsigned long long t = (unsigned long long)c * (c - 1) / 2;
+                    local += t;
+                    if (vert) atomicAdd(&A.v[key], t);
+                }
+            });
+            const unsigned long long tot = block_sum<T>(local, sh.tmp64);
+            if (tid == 0 && tot) {
+                if (A.mode & MODE_GLOBAL) atomicAdd(A.g, tot);
+                if (vert) atomicAdd(&A.v[G.smid[r]], tot);
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+}
+
+template <int T, int CAP>
+__global__ __launch_bounds__(T) void k_count_hash(Ranked G, Acc A, const uint32_t *list, uint32_t count) {
+    __shared__ uint32_t keys[CAP];
+    __shared__ uint32_t cnts[CAP];
+    __shared__ RunShared<T> sh;
+    HashAgg<T, CAP> agg{keys, cnts, A.err};
+    for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const uint32_t r = list[i];
+        count_item<T>(G, A, r, G.smid[r] + 1, G.isv[r] ? G.n : G.n_u, agg, sh);
+    }
+}
+
+// Hash over a candidate window of at most CAP/2 ids (forced hash on heavy sources).
+template <int T, int CAP>
+__global__ __launch_bounds__(T) void k_count_hash_win(Ranked G, Acc A, const uint2 *items, uint32_t count,
+                                                       uint32_t win) {
+    __shared__ uint32_t keys[CAP];
+    __shared__ uint32_t cnts[CAP];
+    __shared__ RunShared<T> sh;
+    HashAgg<T, CAP> agg{keys, cnts, A.err};
+    for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const uint2 it = items[i];
+        const uint32_t r = it.x;
+        const uint32_t side_end = G.isv[r] ? G.n : G.n_u;
+        const uint32_t lo = G.smid[r] + 1 + it.y * win;
+        const uint32_t hi = side_end - lo > win ? lo + win : side_end;
+        count_item<T>(G, A, r, lo, hi, agg, sh);
+    }
+}
+
+template <int T, int WIN>
+__global__ __launch_bounds__(T) void k_count_dense(Ranked G, Acc A, const uint2 *items, uint32_t count) {
+    __shared__ uint32_t cnt[WIN];
+    __shared__ RunShared<T> sh;
+    for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const uint2 it = items[i];
+        const uint32_t r = it.x;
+        const uint32_t side_end = G.isv[r] ? G.n : G.n_u;
+        const uint32_t lo = G.smid[r] + 1 + it.y * WIN;
+        const uint32_t hi = side_end - lo > (uint32_t)WIN ? lo + WIN : side_end;
+        DenseAgg<T> agg{cnt, lo, hi - lo, A.err};
+        count_item<T>(G, A, r, lo, hi, agg, sh);
+    }
+}
+
+// Whole-range dense counting for sources whose candidate range fits WIN.
+template <int T, int WIN>
+__global__ __launch_bounds__(T) void k_count_dense_src(Ranked G, Acc A, const uint32_t *list, uint32_t count) {
+    __shared__ uint32_t cnt[WIN];
+    __shared__ RunShared<T> sh;
+    for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const uint32_t r = list[i];
+        const uint32_t side_end = G.isv[r] ? G.n : G.n_u;
+        const uint32_t lo = G.smid[r] + 1;
+        DenseAgg<T> agg{cnt, lo, side_end - lo, A.err};
+        count_item<T>(G, A, r, lo, side_end, agg, sh);
+    }
+}
+
+// ---------------------------------------------------------------- outputs
+
+__global__ void k_out_global(const unsigned long long *g, int64_t *out) { *out = (int64_t)*g; }
+
+__global__ void k_out_vertex(const uint32_t *rank, const uint32_t *smid, const unsigned long long *v, uint64_t n,
+                             int64_t *out) {
+    GRID_STRIDE(x, n) out[x] = (int64_t)v[smid[rank[x]]];
+}
+
+__global__ void k_out_edge(const uint32_t *eslot, const unsigned long long *s, uint64_t m, int64_t *out) {
+    GRID_STRIDE(e, m) out[e] = (int64_t)(s[eslot[2 * e]] + s[eslot[2 * e + 1]]);
+}
+
+constexpr uint32_t MAX_ITEM_GRID = 1u << 20;
+
+template <class K, class... Args>
+void launch_items(K kernel, uint32_t count, uint32_t threads, hipStream_t s, Args... args) {
+    const uint32_t grid = std::min(count, MAX_ITEM_GRID);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), 0, s, args..., count);
+}
+
+pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, int64_t *gout, int64_t *vout,
+                     int64_t *eout, hipStream_t s) {
+    if (!g || !rank) return PB_ERR_INVALID_ARG;
+    if (!gout && !vout && !eout) return PB_ERR_INVALID_ARG;
+    pb_opts opts;
+    pb_opts_default(&opts);
+    if (opts_in) opts = *opts_in;
+    if ((int)opts.agg < PB_AGG_AUTO || (int)opts.agg > PB_AGG_RADIX_SORT) return PB_ERR_INVALID_ARG;
+    if ((int)opts.hub < PB_HUB_AUTO || (int)opts.hub > PB_HUB_FORCE) return PB_ERR_INVALID_ARG;
+    if (opts.agg == PB_AGG_RADIX_SORT) return PB_ERR_INVALID_ARG;  // not available in this build
+    const int mode = (gout ? MODE_GLOBAL : 0) | (vout ? MODE_VERTEX : 0) | (eout ? MODE_EDGE : 0);
+    const uint64_t n = (uint64_t)g->n_u + g->n_v, m = g->m, ns = 2 * m;
+    // per-chunk wedge offsets are 32-bit: 1024 runs of at most max_deg each
+    if ((uint64_t)g->max_deg * 1024 >= (uint64_t(1) << 32)) return PB_ERR_INVALID_ARG;
+    if (opts.stats) *opts.stats = pb_stats{};
+
+    const bool timing = (opts.flags & PB_FLAG_TIMING) && opts.stats;
+    struct Events {
+        hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+        bool ok = false;
+        ~Events() {
+            for (auto &x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } ev;
+    if (timing) {
+        ev.ok = true;
+        for (auto &x : ev.e) ev.ok = ev.ok && hipEventCreate(&x) == hipSuccess;
+        if (ev.ok) ev.ok = hipEventRecord(ev.e[0], s) == hipSuccess;
+    }
+    auto mark = [&](int i) {
+        if (ev.ok) ev.ok = hipEventRecord(ev.e[i], s) == hipSuccess;
+    };
+
+    Workspace ws(s, opts.workspace_cap_bytes);
+    PlanCounts *hpc = nullptr;
+    PB_TRY_HIP(hipHostMalloc((void **)&hpc, sizeof(PlanCounts), hipHostMallocDefault));
+    struct HostFree {
+        PlanCounts *p;
+        ~HostFree() { (void)hipHostFree(p); }
+    } host_free{hpc};
+
+    // Accumulators first so an empty graph still writes zeros.
+    unsigned long long *gacc = ws.alloc<unsigned long long>(1);
+    unsigned long long *vacc = (mode & MODE_VERTEX) ? ws.alloc<unsigned long long>(n) : nullptr;
+    unsigned long long *sacc = (mode & MODE_EDGE) ? ws.alloc<unsigned long long>(ns) : nullptr;
+    PlanCounts *pc = ws.alloc<PlanCounts>(1);
+    uint32_t *order = ws.alloc<uint32_t>(n), *seen = ws.alloc<uint32_t>(n);
+    if (ws.failed) return PB_ERR_NO_MEMORY;
+    PB_TRY(fill<uint64_t>((uint64_t *)gacc, 0, 1, s));
+    if (vacc) PB_TRY(fill<uint64_t>((uint64_t *)vacc, 0, n, s));
+    if (sacc) PB_TRY(fill<uint64_t>((uint64_t *)sacc, 0, ns, s));
+    PB_TRY(fill<uint32_t>((uint32_t *)pc, 0u, sizeof(PlanCounts) / 4, s));
+
+    // 1. rank check (one sync) -------------------------------------------------
+    if (n > 0) {
+        PB_TRY(fill<uint32_t>(seen, 0u, n, s));
+        PB_TRY(fill<uint32_t>(order, 0u, n, s));
+        hipLaunchKernelGGL(k_rank_check, dim3(grid_for(n)), dim3(256), 0, s, rank, n, order, seen, &pc->flags);
+        PB_TRY_HIP(hipGetLastError());
+        PB_TRY_HIP(hipMemcpyAsync(hpc, pc, sizeof(PlanCounts), hipMemcpyDeviceToHost, s));
+        PB_TRY_HIP(hipStreamSynchronize(s));
+        if (hpc->flags & FLAG_BAD_RANK) return PB_ERR_BAD_RANK;
+    }
+    ws.release(seen);
+
+    uint64_t wtotal = 0;
+    if (m > 0) {
+        // 2. relabel (Algorithm 1) ---------------------------------------------
+        uint32_t *isv = ws.alloc<uint32_t>(n), *vbefore = ws.alloc<uint32_t>(n + 1);
+        uint32_t *rdeg = ws.alloc<uint32_t>(n), *roff = ws.alloc<uint32_t>(n + 1);
+        uint32_t *smid = ws.alloc<uint32_t>(n);
+        if (ws.failed) return PB_ERR_NO_MEMORY;
+        hipLaunchKernelGGL(k_rank_side, dim3(grid_for(n)), dim3(256), 0, s, order, g->deg, n, g->n_u, isv, rdeg);
+        PB_TRY((scan_exclusive<uint32_t, uint32_t>(isv, vbefore, n, vbefore + n, ws)));
+        hipLaunchKernelGGL(k_smid, dim3(grid_for(n)), dim3(256), 0, s, isv, vbefore, n, g->n_u, smid);
+        PB_TRY((scan_exclusive<uint32_t, uint32_t>(rdeg, roff, n, roff + n, ws)));
+        ws.release(vbefore);
+        ws.release(rdeg);
+
+        const int b = bits_for(n - 1);
+        uint64_t *k0 = ws.alloc<uint64_t>(ns), *k1 = ws.alloc<uint64_t>(ns);
+        uint32_t *v0 = ws.alloc<uint32_t>(ns), *v1 = ws.alloc<uint32_t>(ns);
+        if (ws.failed) return PB_ERR_NO_MEMORY;
+        hipLaunchKernelGGL(k_slot_keys, dim3(grid_for(m)), dim3(256), 0, s, g->eu, g->u_adj, rank, m, g->n_u, b, k0,
+                           v0);
+        PB_TRY_HIP(hipGetLastError());
+        uint64_t *ks;
+        uint32_t *vs;
+        PB_TRY(radix_sort_pairs(k0, v0, k1, v1, ns, 2 * b, ws, &ks, &vs));
+
+        uint32_t *nbr = ws.alloc<uint32_t>(ns), *eslot = ws.alloc<uint32_t>(ns);
+        uint32_t *hideg = ws.alloc<uint32_t>(n + 1), *upoff = ws.alloc<uint32_t>(n + 1);
+        if (ws.failed) return PB_ERR_NO_MEMORY;
+        PB_TRY(fill<uint32_t>(hideg, 0u, n + 1, s));
+        hipLaunchKernelGGL(k_slots, dim3(grid_for(ns)), dim3(256), 0, s, ks, vs, ns, b, smid, roff, nbr, eslot,
+                           hideg);
+        PB_TRY((scan_exclusive<uint32_t, uint32_t>(hideg, upoff, n, upoff + n, ws)));
+        uint32_t *uprun = ws.alloc<uint32_t>(m), *uplen = ws.alloc<uint32_t>(m);
+        if (ws.failed) return PB_ERR_NO_MEMORY;
+        hipLaunchKernelGGL(k_upslots, dim3(grid_for(ns)), dim3(256), 0, s, ks, vs, ns, b, roff, upoff, eslot,
+                           uprun, uplen);
+        PB_TRY_HIP(hipGetLastError());
+        ws.release(k0);
+        ws.release(k1);
+        ws.release(v0);
+        ws.release(v1);
+        ws.release(hideg);
+
+        // 3. plan: wedges per source, bucket by distinct-endpoint bound -------
+        uint64_t *wscan = ws.alloc<uint64_t>(m + 1);
+        uint32_t *lists = ws.alloc<uint32_t>((uint64_t)NLISTS * n);
+        uint32_t *heavy_nwin = ws.alloc<uint32_t>(n);
+        uint64_t *heavy_w = ws.alloc<uint64_t>(n);
+        if (ws.failed) return PB_ERR_NO_MEMORY;
+        PB_TRY((scan_exclusive<uint32_t, uint64_t>(uplen, wscan, m, wscan + m, ws)));
+        hipLaunchKernelGGL(k_plan, dim3(grid_for(n)), dim3(256), 0, s, upoff, wscan, smid, isv, n, g->n_u,
+                           (int)opts.agg, lists, heavy_nwin, heavy_w, pc);
+        PB_TRY_HIP(hipGetLastError());
+        PB_TRY_HIP(hipMemcpyAsync(hpc, pc, sizeof(PlanCounts), hipMemcpyDeviceToHost, s));
+        PB_TRY_HIP(hipMemcpyAsync(&wtotal, wscan + m, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        PB_TRY_HIP(hipStreamSynchronize(s));
+        const PlanCounts plan = *hpc;
+
+        // heavy items, most wedges per window first
+        const uint32_t nh = plan.list[LIST_HEAVY];
+        uint2 *items = nullptr;
+        if (nh > 0) {
+            uint64_t *hk0 = ws.alloc<uint64_t>(nh), *hk1 = ws.alloc<uint64_t>(nh);
+            uint32_t *hv0 = ws.alloc<uint32_t>(nh), *hv1 = ws.alloc<uint32_t>(nh);
+            uint32_t *hsrc = ws.alloc<uint32_t>(nh), *hnw = ws.alloc<uint32_t>(nh), *hoff = ws.alloc<uint32_t>(nh + 1);
+            items = ws.alloc<uint2>(plan.items);
+            if (ws.failed) return PB_ERR_NO_MEMORY;
+            const uint32_t *heavy = lists + (uint64_t)LIST_HEAVY * n;
+            hipLaunchKernelGGL(k_heavy_keys, dim3(grid_for(nh)), dim3(256), 0, s, heavy, heavy_nwin, heavy_w, nh, hk0,
+                               hv0);
+            uint64_t *hks;
+            uint32_t *hvs;
+            PB_TRY(radix_sort_pairs(hk0, hv0, hk1, hv1, nh, 32, ws, &hks, &hvs));
+            hipLaunchKernelGGL(k_heavy_gather, dim3(grid_for(nh)), dim3(256), 0, s, hvs, heavy, heavy_nwin, nh, hsrc,
+                               hnw);
+            PB_TRY((scan_exclusive<uint32_t, uint32_t>(hnw, hoff, nh, hoff + nh, ws)));
+            hipLaunchKernelGGL(k_heavy_expand, dim3(grid_for(nh)), dim3(256), 0, s, hsrc, hnw, hoff, nh, items);
+            PB_TRY_HIP(hipGetLastError());
+        }
+
+        // 4. count ---------------------------------------------------------------
+        Ranked G{roff, nbr, upoff, uprun, uplen, smid, isv, g->n_u, (uint32_t)n};
+        Acc A{gacc, vacc, sacc, &pc->flags, mode};
+        mark(1);
+        if (nh > 0) {
+            if (opts.agg == PB_AGG_LDS_HASH)
+                hipLaunchKernelGGL((k_count_hash_win<256, 2 * HASH_WIN>), dim3(std::min(plan.items, MAX_ITEM_GRID)),
+                                   dim3(256), 0, s, G, A, (const uint2 *)items, plan.items, HASH_WIN);
+            else
+                launch_items(k_count_dense<1024, BIG_WIN>, plan.items, 1024, s, G, A, (const uint2 *)items);
+        }
+        mark(2);
+        if (plan.list[LIST_MEDIUM])
+            launch_items(k_count_hash<256, 2 * MEDIUM_D>, plan.list[LIST_MEDIUM], 256, s, G, A,
+                        (const uint32_t *)(lists + (uint64_t)LIST_MEDIUM * n));
+        if (plan.list[LIST_SMALLDENSE])
+            launch_items(k_count_dense_src<256, SMALL_WIN>, plan.list[LIST_SMALLDENSE], 256, s, G, A,
+                        (const uint32_t *)(lists + (uint64_t)LIST_SMALLDENSE * n));
+        if (plan.list[LIST_LIGHT])
+            launch_items(k_count_hash<64, 2 * LIGHT_D>, plan.list[LIST_LIGHT], 64, s, G, A,
+                        (const uint32_t *)(lists + (uint64_t)LIST_LIGHT * n));
+        PB_TRY_HIP(hipGetLastError());
+        mark(3);
+
+        // 5. outputs ---------------------------------------------------------------
+        if (vout)
+            hipLaunchKernelGGL(k_out_vertex, dim3(grid_for(n)), dim3(256), 0, s, rank, smid, vacc, n, vout);
+        if (eout) hipLaunchKernelGGL(k_out_edge, dim3(grid_for(m)), dim3(256), 0, s, eslot, sacc, m, eout);
+        if (opts.stats) {
+            pb_stats &st = *opts.stats;
+            st.wedges = wtotal;
+            st.sources = plan.sources;
+            st.sources_hash = plan.list[LIST_LIGHT] + plan.list[LIST_MEDIUM] +
+                              (opts.agg == PB_AGG_LDS_HASH ? nh : 0);
+            st.sources_dense = plan.list[LIST_SMALLDENSE] + (opts.agg == PB_AGG_LDS_HASH ? 0 : nh);
+            st.window_items = nh ? plan.items : 0;
+            const bool hash_heavy = opts.agg == PB_AGG_LDS_HASH;
+            st.wedges_hash = plan.wedges[LIST_LIGHT] + plan.wedges[LIST_MEDIUM] +
+                             (hash_heavy ? plan.wedges[LIST_HEAVY] : 0);
+            st.wedges_dense = plan.wedges[LIST_SMALLDENSE] + (hash_heavy ? 0 : plan.wedges[LIST_HEAVY]);
+        }
+    } else {
+        if (vout) PB_TRY(fill<int64_t>(vout, 0, n, s));
+    }
+    if (gout) hipLaunchKernelGGL(k_out_global, dim3(1), dim3(1), 0, s, gacc, gout);
+    PB_TRY_HIP(hipGetLastError());
+    if (opts.stats) opts.stats->workspace_bytes = ws.peak;
+    PB_TRY_HIP(hipMemcpyAsync(hpc, pc, sizeof(PlanCounts), hipMemcpyDeviceToHost, s));
+    if (timing && ev.ok) {
+        mark(4);
+        if (m == 0) {  // nothing but the outputs ran
+            for (int i = 1; i < 4; ++i) (void)hipEventRecord(ev.e[i], s);
+        }
+        PB_TRY_HIP(hipEventSynchronize(ev.e[4]));
+        float t[4] = {0, 0, 0, 0};
+        for (int i = 0; i < 4; ++i) (void)hipEventElapsedTime(&t[i], ev.e[i], ev.e[i + 1]);
+        opts.stats->ms_prepare = t[0];
+        if (opts.agg == PB_AGG_LDS_HASH) {
+            opts.stats->ms_hash = t[1] + t[2];
+        } else {
+            opts.stats->ms_dense = t[1];
+            opts.stats->ms_hash = t[2];
+        }
+        opts.stats->ms_output = t[3];
+    }
+    PB_TRY_HIP(hipStreamSynchronize(s));
+    if (hpc->flags & FLAG_INTERNAL) return PB_ERR_HIP;
+    return PB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pb_status pb_count(pb_graph *g, const uint32_t *rank, const pb_opts *opts, int64_t *global_out, int64_t *vertex_out,
+                   int64_t *edge_out, hipStream_t stream) {
+    return count_impl(g, rank, opts, global_out, vertex_out, edge_out, stream);
+}
+
+pb_status pb_count_global(pb_graph *g, const uint32_t *rank, const pb_opts *opts, int64_t *out, hipStream_t stream) {
+    if (!out) return PB_ERR_INVALID_ARG;
+    return count_impl(g, rank, opts, out, nullptr, nullptr, stream);
+}
+
+pb_status pb_count_vertex(pb_graph *g, const uint32_t *rank, const pb_opts *opts, int64_t *out, hipStream_t stream) {
+    if (!out) return PB_ERR_INVALID_ARG;
+    return count_impl(g, rank, opts, nullptr, out, nullptr, stream);
+}
+
+pb_status pb_count_edge(pb_graph *g, const uint32_t *rank, const pb_opts *opts, int64_t *out, hipStream_t stream) {
+    if (!out) return PB_ERR_INVALID_ARG;
+    return count_impl(g, rank, opts, nullptr, nullptr, out, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,427 @@
+// Graph handle (input validation, V-side CSR) and vertex orderings.
+//
+// Section 2 keeps one CSR per side; the caller supplies the U side and the
+// handle derives the V side by a stable sort of the edges by V id.
+// Section 3.1.1 defines the orderings built by pb_rank.
+#include "pb_internal.h"
+
+#include <new>
+
+using namespace pb;
+
+namespace {
+
+enum : uint32_t { BAD_OFFSETS = 1u, BAD_ID = 2u, NOT_INCREASING = 4u };
+
+constexpr int EDGE_BLOCK = 256;
+constexpr int EDGES_PER_BLOCK = 1024;
+
+__global__ void k_check_offsets(const int64_t *u_off, uint32_t n_u, uint64_t m, uint32_t *flags) {
+    for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u <= n_u;
+         u += (uint64_t)gridDim.x * blockDim.x) {
+        const int64_t o = u_off[u];
+        bool bad = o < 0 || (uint64_t)o > m;
+        if (u == 0 && o != 0) bad = true;
+        if (u == n_u && (uint64_t)o != m) bad = true;
+        if (u > 0 && u_off[u - 1] > o) bad = true;
+        if (bad) atomicOr(flags, (uint32_t)BAD_OFFSETS);
+    }
+}
+
+// Largest r in [lo, hi) with u_off[r] <= e (rows are [u_off[r], u_off[r+1])).
+__device__ inline uint32_t row_of(const int64_t *u_off, uint32_t lo, uint32_t hi, uint64_t e) {
+    while (hi - lo > 1) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if ((uint64_t)u_off[mid] <= e) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// eu[e] = the U row holding edge e; checks ids and strict increase.  Each
+// block first finds the row range covering its edges, then each thread
+// searches that (short) range.
+__global__ __launch_bounds__(EDGE_BLOCK) void k_edge_rows(const int64_t *u_off, const uint32_t *u_adj,
+                                                          uint32_t n_u, uint32_t n_v, uint64_t m,
+                                                          uint32_t *eu, uint32_t *vdeg, uint32_t *flags) {
+    __shared__ uint32_t s_lo, s_hi;
+    const uint64_t e0 = (uint64_t)blockIdx.x * EDGES_PER_BLOCK;
+    const uint64_t e1 = e0 + EDGES_PER_BLOCK < m ? e0 + EDGES_PER_BLOCK : m;
+    if (threadIdx.x == 0) {
+        s_lo = row_of(u_off, 0, n_u, e0);
+        s_hi = row_of(u_off, 0, n_u, e1 - 1) + 1;
+    }
+    __syncthreads();
+    const uint32_t lo = s_lo, hi = s_hi > lo ? s_hi : lo + 1;
+    uint32_t bad = 0;
+    for (uint64_t e = e0 + threadIdx.x; e < e1; e += EDGE_BLOCK) {
+        uint32_t r = row_of(u_off, lo, hi, e);
+        if (r >= n_u) r = n_u - 1;
+        eu[e] = r;
+        const uint32_t v = u_adj[e];
+        if (v >= n_v) bad |= BAD_ID;
+        else atomicAdd(&vdeg[v], 1u);
+        if ((int64_t)e > u_off[r] && e > 0 && u_adj[e - 1] >= v) bad |= NOT_INCREASING;
+    }
+    if (bad) atomicOr(flags, bad);
+}
+
+__global__ void k_iota_keys(const uint32_t *u_adj, uint64_t m, uint64_t *keys, uint32_t *vals) {
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        keys[e] = u_adj[e];
+        vals[e] = (uint32_t)e;
+    }
+}
+
+__global__ void k_gather_u(const uint32_t *eids, const uint32_t *eu, uint64_t m, uint32_t *v_adj) {
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m;
+         p += (uint64_t)gridDim.x * blockDim.x)
+        v_adj[p] = eu[eids[p]];
+}
+
+__global__ void k_degrees(const int64_t *u_off, const uint32_t *v_off, uint32_t n_u, uint32_t n_v,
+                          uint32_t *deg, uint32_t *max_deg) {
+    uint32_t best = 0;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < (uint64_t)n_u + n_v;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t d;
+        if (x < n_u) d = (uint32_t)(u_off[x + 1] - u_off[x]);
+        else d = v_off[x - n_u + 1] - v_off[x - n_u];
+        deg[x] = d;
+        best = d > best ? d : best;
+    }
+    for (int s = WAVE / 2; s >= 1; s >>= 1) {
+        const uint32_t o = __shfl_xor(best, s, WAVE);
+        best = o > best ? o : best;
+    }
+    if ((threadIdx.x & (WAVE - 1)) == 0) atomicMax(max_deg, best);
+}
+
+inline uint32_t grid_for(uint64_t n, uint32_t block = 256, uint32_t cap = 65536) {
+    uint64_t g = (n + block - 1) / block;
+    if (g == 0) g = 1;
+    return (uint32_t)(g > cap ? cap : g);
+}
+
+// ---------------------------------------------------------------- orderings
+
+// sums[0] = sum_{v in V} C(deg v, 2) (wedges with U endpoints, U first)
+// sums[1] = sum_{u in U} C(deg u, 2) (wedges with V endpoints, V first)
+__global__ void k_side_sums(const uint32_t *deg, uint32_t n_u, uint32_t n_v, unsigned long long *sums) {
+    unsigned long long su = 0, sv = 0;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < (uint64_t)n_u + n_v;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const unsigned long long d = deg[x];
+        const unsigned long long c = d * (d - (d > 0)) / 2;
+        if (x < n_u) sv += c; else su += c;
+    }
+    su = wave_sum(su);
+    sv = wave_sum(sv);
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        atomicAdd(&sums[0], su);
+        atomicAdd(&sums[1], sv);
+    }
+}
+
+// mode 0: U first, 1: V first, 2: decide from sums.
+__global__ void k_side_rank(uint32_t n_u, uint32_t n_v, int mode, const unsigned long long *sums,
+                            uint32_t *rank) {
+    bool u_first = mode == 0;
+    if (mode == 2) u_first = sums[0] <= sums[1];
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < (uint64_t)n_u + n_v;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t r;
+        if (u_first) r = (uint32_t)x;
+        else r = x < n_u ? (uint32_t)(n_v + x) : (uint32_t)(x - n_u);
+        rank[x] = r;
+    }
+}
+
+__device__ inline uint32_t level_key(uint32_t d) {  // floor(log2 d) + 1, 0 for d = 0
+    return d ? 32u - (uint32_t)__clz(d) : 0u;
+}
+
+// key = (descending primary key) << idbits | id
+__global__ void k_order_keys(const uint32_t *deg, uint64_t n, int approx, uint32_t max_key, int idbits,
+                             uint64_t *keys, uint32_t *vals) {
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = approx ? level_key(deg[x]) : deg[x];
+        keys[x] = ((uint64_t)(max_key - k) << idbits) | x;
+        vals[x] = (uint32_t)x;
+    }
+}
+
+__global__ void k_scatter_rank(const uint32_t *ids, uint64_t n, uint32_t *rank) {
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (uint64_t)gridDim.x * blockDim.x)
+        rank[ids[p]] = (uint32_t)p;
+}
+
+// Complement-coreness rounds.
+__global__ void k_codeg_max(const uint32_t *cur, const uint32_t *alive, uint64_t n, int approx,
+                            uint32_t *best) {
+    uint32_t b = 0;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+         x += (uint64_t)gridDim.x * blockDim.x)
+        if (alive[x]) {
+            const uint32_t k = (approx ? level_key(cur[x]) : cur[x]) + 1;  // +1: alive marker
+            b = k > b ? k : b;
+        }
+    for (int s = WAVE / 2; s >= 1; s >>= 1) {
+        const uint32_t o = __shfl_xor(b, s, WAVE);
+        b = o > b ? o : b;
+    }
+    if ((threadIdx.x & (WAVE - 1)) == 0 && b) atomicMax(best, b);
+}
+
+__global__ void k_codeg_flags(const uint32_t *cur, const uint32_t *alive, uint64_t n, int approx,
+                              const uint32_t *best, uint32_t *flag) {
+    const uint32_t top = *best;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t k = (approx ? level_key(cur[x]) : cur[x]) + 1;
+        flag[x] = alive[x] && k == top;
+    }
+}
+
+__global__ void k_codeg_assign(const uint32_t *flag, const uint32_t *pos, uint64_t n, uint32_t next,
+                               uint32_t *alive, uint32_t *rank, uint32_t *front) {
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+         x += (uint64_t)gridDim.x * blockDim.x)
+        if (flag[x]) {
+            rank[x] = next + pos[x];
+            front[pos[x]] = (uint32_t)x;
+            alive[x] = 0;
+        }
+}
+
+// One block per removed vertex: every neighbour loses one remaining neighbour.
+__global__ void k_codeg_decrement(const uint32_t *front, uint32_t nfront, const int64_t *u_off,
+                                  const uint32_t *u_adj, const uint32_t *v_off, const uint32_t *v_adj,
+                                  uint32_t n_u, uint32_t *cur) {
+    for (uint32_t i = blockIdx.x; i < nfront; i += gridDim.x) {
+        const uint32_t x = front[i];
+        if (x < n_u) {
+            for (int64_t k = u_off[x] + threadIdx.x; k < u_off[x + 1]; k += blockDim.x)
+                atomicSub(&cur[n_u + u_adj[k]], 1u);
+        } else {
+            const uint32_t v = x - n_u;
+            for (uint32_t k = v_off[v] + threadIdx.x; k < v_off[v + 1]; k += blockDim.x)
+                atomicSub(&cur[v_adj[k]], 1u);
+        }
+    }
+}
+
+pb_status rank_codeg(pb_graph *g, bool approx, uint32_t *rank, hipStream_t s) {
+    const uint64_t n = (uint64_t)g->n_u + g->n_v;
+    Workspace ws(s, 0);
+    uint32_t *cur = ws.alloc<uint32_t>(n), *alive = ws.alloc<uint32_t>(n);
+    uint32_t *flag = ws.alloc<uint32_t>(n), *pos = ws.alloc<uint32_t>(n + 1);
+    uint32_t *front = ws.alloc<uint32_t>(n), *best = ws.alloc<uint32_t>(1);
+    uint32_t *host = nullptr;
+    if (ws.failed) return PB_ERR_NO_MEMORY;
+    PB_TRY_HIP(hipHostMalloc((void **)&host, sizeof(uint32_t), hipHostMallocDefault));
+    pb_status st = PB_OK;
+    do {
+        if (hipMemcpyAsync(cur, g->deg, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s) != hipSuccess) {
+            st = PB_ERR_HIP;
+            break;
+        }
+        if ((st = fill<uint32_t>(alive, 1u, n, s)) != PB_OK) break;
+        uint32_t next = 0;
+        while (next < n) {
+            if ((st = fill<uint32_t>(best, 0u, 1, s)) != PB_OK) break;
+            hipLaunchKernelGGL(k_codeg_max, dim3(grid_for(n)), dim3(256), 0, s, cur, alive, n, (int)approx, best);
+            hipLaunchKernelGGL(k_codeg_flags, dim3(grid_for(n)), dim3(256), 0, s, cur, alive, n, (int)approx,
+                               best, flag);
+            if ((st = scan_exclusive<uint32_t, uint32_t>(flag, pos, n, pos + n, ws)) != PB_OK) break;
+            hipLaunchKernelGGL(k_codeg_assign, dim3(grid_for(n)), dim3(256), 0, s, flag, pos, n, next, alive,
+                               rank, front);
+            if (hipMemcpyAsync(host, pos + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                st = PB_ERR_HIP;
+                break;
+            }
+            const uint32_t nf = *host;
+            if (nf == 0) { st = PB_ERR_HIP; break; }  // cannot happen while vertices remain
+            hipLaunchKernelGGL(k_codeg_decrement, dim3(nf < 65536 ? nf : 65536), dim3(256), 0, s, front, nf,
+                               g->u_off, g->u_adj, g->v_off, g->v_adj, g->n_u, cur);
+            if (hipGetLastError() != hipSuccess) { st = PB_ERR_HIP; break; }
+            next += nf;
+        }
+    } while (0);
+    (void)hipStreamSynchronize(s);
+    (void)hipHostFree(host);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pb_opts_default(pb_opts *opts) {
+    if (!opts) return;
+    opts->agg = PB_AGG_AUTO;
+    opts->hub = PB_HUB_AUTO;
+    opts->workspace_cap_bytes = 0;
+    opts->wg_size = 0;
+    opts->flags = 0;
+    opts->stats = nullptr;
+}
+
+const char *pb_status_str(pb_status s) {
+    switch (s) {
+        case PB_OK: return "ok";
+        case PB_ERR_INVALID_ARG: return "invalid argument";
+        case PB_ERR_NOT_SIMPLE: return "graph not simple (a CSR row is not strictly increasing)";
+        case PB_ERR_ID_RANGE: return "vertex id or offset out of range";
+        case PB_ERR_BAD_RANK: return "rank is not a permutation of [0, n)";
+        case PB_ERR_NO_MEMORY: return "out of device memory or workspace cap";
+        case PB_ERR_OVERFLOW: return "count overflows int64";
+        case PB_ERR_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+pb_status pb_graph_create(const pb_csr *csr, hipStream_t s, pb_graph **out) {
+    if (!csr || !out) return PB_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!csr->u_off) return PB_ERR_INVALID_ARG;
+    if (csr->m > 0 && !csr->u_adj) return PB_ERR_INVALID_ARG;
+    if (csr->m >= (uint64_t(1) << 31)) return PB_ERR_INVALID_ARG;
+    if ((uint64_t)csr->n_u + csr->n_v >= 0xFFFFFFFFull) return PB_ERR_INVALID_ARG;
+    if (csr->m > (uint64_t)csr->n_u * csr->n_v) return PB_ERR_NOT_SIMPLE;
+
+    pb_graph *g = new (std::nothrow) pb_graph();
+    if (!g) return PB_ERR_NO_MEMORY;
+    g->n_u = csr->n_u;
+    g->n_v = csr->n_v;
+    g->m = csr->m;
+    g->u_off = csr->u_off;
+    g->u_adj = csr->u_adj;
+    g->last_stream = s;
+    (void)hipGetDevice(&g->device);
+    const uint64_t n = (uint64_t)g->n_u + g->n_v, m = g->m;
+
+    pb_status st = PB_OK;
+    uint32_t *hflags = nullptr;
+    {
+        Workspace ws(s, 0);
+        uint32_t *flags = ws.alloc<uint32_t>(2);  // [0] flags, [1] max degree
+        bool ok = flags && hipMalloc(&g->eu, (m ? m : 1) * sizeof(uint32_t)) == hipSuccess &&
+                  hipMalloc(&g->v_off, (g->n_v + 1) * sizeof(uint32_t)) == hipSuccess &&
+                  hipMalloc(&g->v_adj, (m ? m : 1) * sizeof(uint32_t)) == hipSuccess &&
+                  hipMalloc(&g->deg, (n ? n : 1) * sizeof(uint32_t)) == hipSuccess &&
+                  hipHostMalloc((void **)&hflags, 2 * sizeof(uint32_t), hipHostMallocDefault) == hipSuccess;
+        if (!ok) st = PB_ERR_NO_MEMORY;
+        uint32_t *vdeg = ok ? ws.alloc<uint32_t>(g->n_v + 1) : nullptr;
+        if (ok && !vdeg) st = PB_ERR_NO_MEMORY;
+        do {
+            if (st != PB_OK) break;
+            if ((st = fill<uint32_t>(flags, 0u, 2, s)) != PB_OK) break;
+            if ((st = fill<uint32_t>(vdeg, 0u, g->n_v + 1, s)) != PB_OK) break;
+            hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(g->n_u + 1ull)), dim3(256), 0, s, g->u_off, g->n_u, m,
+                               flags);
+            if (m > 0 && g->n_u > 0) {
+                hipLaunchKernelGGL(k_edge_rows, dim3(ceil_div(m, EDGES_PER_BLOCK)), dim3(EDGE_BLOCK), 0, s, g->u_off,
+                                   g->u_adj, g->n_u, g->n_v, m, g->eu, vdeg, flags);
+            }
+            if (hipGetLastError() != hipSuccess) { st = PB_ERR_HIP; break; }
+            // V-side CSR: offsets by counting, rows by a stable sort of edge ids by V id.
+            if ((st = scan_exclusive<uint32_t, uint32_t>(vdeg, g->v_off, g->n_v, g->v_off + g->n_v, ws)) != PB_OK)
+                break;
+            if (m > 0) {
+                uint64_t *k0 = ws.alloc<uint64_t>(m), *k1 = ws.alloc<uint64_t>(m);
+                uint32_t *v0 = ws.alloc<uint32_t>(m), *v1 = ws.alloc<uint32_t>(m);
+                if (ws.failed) { st = PB_ERR_NO_MEMORY; break; }
+                hipLaunchKernelGGL(k_iota_keys, dim3(grid_for(m)), dim3(256), 0, s, g->u_adj, m, k0, v0);
+                uint64_t *kr;
+                uint32_t *vr;
+                if ((st = radix_sort_pairs(k0, v0, k1, v1, m, bits_for(g->n_v ? g->n_v - 1 : 0), ws, &kr, &vr)) !=
+                    PB_OK)
+                    break;
+                hipLaunchKernelGGL(k_gather_u, dim3(grid_for(m)), dim3(256), 0, s, vr, g->eu, m, g->v_adj);
+            }
+            hipLaunchKernelGGL(k_degrees, dim3(grid_for(n)), dim3(256), 0, s, g->u_off, g->v_off, g->n_u, g->n_v,
+                               g->deg, flags + 1);
+            if (hipGetLastError() != hipSuccess) { st = PB_ERR_HIP; break; }
+            if (hipMemcpyAsync(hflags, flags, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                st = PB_ERR_HIP;
+                break;
+            }
+            if (hflags[0] & BAD_OFFSETS) st = PB_ERR_ID_RANGE;
+            else if (hflags[0] & BAD_ID) st = PB_ERR_ID_RANGE;
+            else if (hflags[0] & NOT_INCREASING) st = PB_ERR_NOT_SIMPLE;
+            g->max_deg = hflags[1];
+        } while (0);
+    }
+    if (hflags) (void)hipHostFree(hflags);
+    if (st != PB_OK) {
+        (void)hipStreamSynchronize(s);
+        pb_graph_destroy(g);
+        return st;
+    }
+    *out = g;
+    return PB_OK;
+}
+
+void pb_graph_destroy(pb_graph *g) {
+    if (!g) return;
+    (void)hipDeviceSynchronize();
+    if (g->eu) (void)hipFree(g->eu);
+    if (g->v_off) (void)hipFree(g->v_off);
+    if (g->v_adj) (void)hipFree(g->v_adj);
+    if (g->deg) (void)hipFree(g->deg);
+    delete g;
+}
+
+pb_status pb_rank(pb_graph *g, pb_rank_kind kind, uint32_t *rank, hipStream_t s) {
+    if (!g || !rank) return PB_ERR_INVALID_ARG;
+    const uint64_t n = (uint64_t)g->n_u + g->n_v;
+    if (n == 0) return PB_OK;
+    switch (kind) {
+        case PB_RANK_SIDE_AUTO:
+        case PB_RANK_SIDE_U_FIRST:
+        case PB_RANK_SIDE_V_FIRST: {
+            Workspace ws(s, 0);
+            unsigned long long *sums = ws.alloc<unsigned long long>(2);
+            if (!sums) return PB_ERR_NO_MEMORY;
+            PB_TRY(fill<uint64_t>((uint64_t *)sums, 0ull, 2, s));
+            if (kind == PB_RANK_SIDE_AUTO)
+                hipLaunchKernelGGL(k_side_sums, dim3(grid_for(n)), dim3(256), 0, s, g->deg, g->n_u, g->n_v, sums);
+            const int mode = kind == PB_RANK_SIDE_U_FIRST ? 0 : kind == PB_RANK_SIDE_V_FIRST ? 1 : 2;
+            hipLaunchKernelGGL(k_side_rank, dim3(grid_for(n)), dim3(256), 0, s, g->n_u, g->n_v, mode, sums, rank);
+            PB_TRY_HIP(hipGetLastError());
+            return PB_OK;
+        }
+        case PB_RANK_DEGREE:
+        case PB_RANK_APPROX_DEGREE: {
+            const bool approx = kind == PB_RANK_APPROX_DEGREE;
+            const uint32_t max_key = approx ? 32u : g->max_deg;
+            const int idbits = bits_for(n - 1);
+            const int nbits = idbits + bits_for(max_key);
+            Workspace ws(s, 0);
+            uint64_t *k0 = ws.alloc<uint64_t>(n), *k1 = ws.alloc<uint64_t>(n);
+            uint32_t *v0 = ws.alloc<uint32_t>(n), *v1 = ws.alloc<uint32_t>(n);
+            if (ws.failed) return PB_ERR_NO_MEMORY;
+            hipLaunchKernelGGL(k_order_keys, dim3(grid_for(n)), dim3(256), 0, s, g->deg, n, (int)approx, max_key,
+                               idbits, k0, v0);
+            PB_TRY_HIP(hipGetLastError());
+            uint64_t *kr;
+            uint32_t *vr;
+            PB_TRY(radix_sort_pairs(k0, v0, k1, v1, n, nbits, ws, &kr, &vr));
+            hipLaunchKernelGGL(k_scatter_rank, dim3(grid_for(n)), dim3(256), 0, s, vr, n, rank);
+            PB_TRY_HIP(hipGetLastError());
+            return PB_OK;
+        }
+        case PB_RANK_COMPLEMENT_CORENESS:
+            return rank_codeg(g, false, rank, s);
+        case PB_RANK_APPROX_COMPLEMENT_CORENESS:
+            return rank_codeg(g, true, rank, s);
+    }
+    return PB_ERR_INVALID_ARG;
+}
+
+}  // extern "C"

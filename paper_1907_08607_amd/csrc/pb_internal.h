@@ -1,0 +1,180 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/parbutterfly.h"
+
+namespace pb {
+
+constexpr int WAVE = 64;
+
+#define PB_TRY_HIP(expr)                                  \
+    do {                                                  \
+        hipError_t pb_e_ = (expr);                        \
+        if (pb_e_ != hipSuccess) return PB_ERR_HIP;       \
+    } while (0)
+
+#define PB_TRY(expr)                                      \
+    do {                                                  \
+        pb_status pb_s_ = (expr);                         \
+        if (pb_s_ != PB_OK) return pb_s_;                 \
+    } while (0)
+
+// Stream-ordered scratch for one library call.  Every allocation is released
+// (stream-ordered) when the Workspace goes out of scope.  `cap` bounds the
+// total bytes (0 = unbounded).
+struct Workspace {
+    hipStream_t stream;
+    uint64_t cap;
+    uint64_t used = 0;
+    uint64_t peak = 0;
+    bool failed = false;
+    std::vector<std::pair<void *, uint64_t>> ptrs;
+
+    Workspace(hipStream_t s, uint64_t cap_bytes) : stream(s), cap(cap_bytes) {}
+    Workspace(const Workspace &) = delete;
+    Workspace &operator=(const Workspace &) = delete;
+    ~Workspace() { release_all(); }
+
+    void *alloc_bytes(uint64_t bytes) {
+        if (bytes == 0) bytes = 256;
+        bytes = (bytes + 255) & ~uint64_t(255);
+        if (cap && used + bytes > cap) { failed = true; return nullptr; }
+        void *p = nullptr;
+        if (hipMallocAsync(&p, bytes, stream) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            failed = true;
+            return nullptr;
+        }
+        ptrs.push_back({p, bytes});
+        used += bytes;
+        if (used > peak) peak = used;
+        return p;
+    }
+    template <class T>
+    T *alloc(uint64_t count) { return static_cast<T *>(alloc_bytes(count * sizeof(T))); }
+
+    // Frees one allocation early (stream-ordered).
+    void release(void *p) {
+        for (size_t i = 0; i < ptrs.size(); ++i)
+            if (ptrs[i].first == p) {
+                (void)hipFreeAsync(p, stream);
+                used -= ptrs[i].second;
+                ptrs.erase(ptrs.begin() + i);
+                return;
+            }
+    }
+    void release_all() {
+        for (auto &p : ptrs) (void)hipFreeAsync(p.first, stream);
+        ptrs.clear();
+        used = 0;
+    }
+};
+
+// ---------------------------------------------------------------- primitives
+
+// out[i] = sum_{j < i} in[j] for i < n; if total != nullptr, *total (device) =
+// sum of all n.  `out` may alias `in`.
+template <class Tin, class Tout>
+pb_status scan_exclusive(const Tin *in, Tout *out, uint64_t n, Tout *total, Workspace &ws);
+
+// Stable LSD radix sort of (keys, vals) by key bits [0, nbits), 8 bits a pass.
+// Ping-pongs between (k0, v0) and (k1, v1); on return *kres / *vres point at
+// whichever pair holds the sorted result.  n < 2^32.
+pb_status radix_sort_pairs(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, uint64_t n,
+                           int nbits, Workspace &ws, uint64_t **kres, uint32_t **vres);
+
+template <class T>
+pb_status fill(T *p, T value, uint64_t n, hipStream_t s);
+
+// Number of bits needed to represent values 0..x.
+inline int bits_for(uint64_t x) {
+    int b = 0;
+    while (b < 64 && (x >> b) != 0) ++b;
+    return b;
+}
+
+inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------- device helpers
+
+__device__ inline uint64_t lanemask_lt() { return __lanemask_lt(); }
+
+template <class T>
+__device__ inline T wave_inclusive_sum(T v) {
+    const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        T t = __shfl_up(v, d, WAVE);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+template <class T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+    for (int d = WAVE / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, WAVE);
+    return v;
+}
+
+// Block-wide exclusive sum.  `s_tmp` needs THREADS / WAVE + 1 entries of
+// shared memory.  Returns the thread's exclusive prefix; *total gets the block
+// sum in every thread.  Contains __syncthreads(); call from all threads.
+template <int THREADS, class T>
+__device__ inline T block_exclusive_sum(T v, T *s_tmp, T *total) {
+    constexpr int NW = THREADS / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
+    T inc = wave_inclusive_sum(v);
+    if (lane == WAVE - 1) s_tmp[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        T x = lane < NW ? s_tmp[lane] : T(0);
+        T xi = wave_inclusive_sum(x);
+        if (lane < NW) s_tmp[lane] = xi - x;
+        if (lane == NW - 1) s_tmp[NW] = xi;
+    }
+    __syncthreads();
+    T r = s_tmp[w] + inc - v;
+    *total = s_tmp[NW];
+    __syncthreads();
+    return r;
+}
+
+template <int THREADS, class T>
+__device__ inline T block_sum(T v, T *s_tmp) {
+    constexpr int NW = THREADS / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = threadIdx.x / WAVE;
+    T s = wave_sum(v);
+    if (lane == 0) s_tmp[w] = s;
+    __syncthreads();
+    T r = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) r += s_tmp[i];
+    __syncthreads();
+    return r;
+}
+
+}  // namespace pb
+
+// ---------------------------------------------------------------- the graph handle
+
+struct pb_graph {
+    uint32_t n_u = 0, n_v = 0;
+    uint64_t m = 0;
+    int device = 0;
+    const int64_t *u_off = nullptr;  // caller-owned
+    const uint32_t *u_adj = nullptr; // caller-owned
+    uint32_t *eu = nullptr;          // m: U endpoint of each edge
+    uint32_t *v_off = nullptr;       // n_v + 1: V-side row offsets
+    uint32_t *v_adj = nullptr;       // m: U ids, increasing within a row
+    uint32_t *deg = nullptr;         // n: degree per unified id
+    uint32_t max_deg = 0;
+    hipStream_t last_stream = nullptr;
+};

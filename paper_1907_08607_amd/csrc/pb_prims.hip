@@ -1,0 +1,214 @@
+// Device-wide primitives: exclusive scan, stable LSD radix sort, fill.
+// (The paper's prefix sum and integer sort, Section 2 "Parallel primitives".)
+#include "pb_internal.h"
+
+namespace pb {
+
+// ---------------------------------------------------------------- scan
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+template <class Tin, class Tout>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const Tin *in, uint64_t n,
+                                                              Tout *partial) {
+    __shared__ Tout s_tmp[SCAN_THREADS / WAVE + 1];
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+    Tout s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        uint64_t idx = base + (uint64_t)i * SCAN_THREADS + threadIdx.x;
+        if (idx < n) s += (Tout)in[idx];
+    }
+    s = block_sum<SCAN_THREADS>(s, s_tmp);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Each thread owns SCAN_ITEMS consecutive elements.
+template <class Tin, class Tout>
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_down(const Tin *in, Tout *out, uint64_t n,
+                                                            const Tout *partial, Tout *total) {
+    __shared__ Tout s_tmp[SCAN_THREADS / WAVE + 1];
+    const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    Tout v[SCAN_ITEMS];
+    Tout s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        uint64_t idx = base + i;
+        v[i] = idx < n ? (Tout)in[idx] : Tout(0);
+        s += v[i];
+    }
+    Tout blk_total;
+    Tout pre = block_exclusive_sum<SCAN_THREADS>(s, s_tmp, &blk_total);
+    Tout off = (partial ? partial[blockIdx.x] : Tout(0)) + pre;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        uint64_t idx = base + i;
+        if (idx < n) out[idx] = off;
+        off += v[i];
+    }
+    if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+        *total = (partial ? partial[blockIdx.x] : Tout(0)) + blk_total;
+}
+
+template <class Tin, class Tout>
+pb_status scan_exclusive(const Tin *in, Tout *out, uint64_t n, Tout *total, Workspace &ws) {
+    if (n == 0) {
+        if (total) return fill<Tout>(total, Tout(0), 1, ws.stream);
+        return PB_OK;
+    }
+    const uint64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    Tout *partial = nullptr;
+    if (nb > 1) {
+        partial = ws.alloc<Tout>(nb);
+        if (!partial) return PB_ERR_NO_MEMORY;
+        hipLaunchKernelGGL((k_scan_reduce<Tin, Tout>), dim3((uint32_t)nb), dim3(SCAN_THREADS), 0,
+                           ws.stream, in, n, partial);
+        PB_TRY_HIP(hipGetLastError());
+        PB_TRY((scan_exclusive<Tout, Tout>(partial, partial, nb, nullptr, ws)));
+    }
+    hipLaunchKernelGGL((k_scan_down<Tin, Tout>), dim3((uint32_t)nb), dim3(SCAN_THREADS), 0, ws.stream,
+                       in, out, n, partial, total);
+    PB_TRY_HIP(hipGetLastError());
+    if (partial) ws.release(partial);
+    return PB_OK;
+}
+
+template pb_status scan_exclusive<uint32_t, uint32_t>(const uint32_t *, uint32_t *, uint64_t,
+                                                      uint32_t *, Workspace &);
+template pb_status scan_exclusive<uint32_t, uint64_t>(const uint32_t *, uint64_t *, uint64_t,
+                                                      uint64_t *, Workspace &);
+template pb_status scan_exclusive<uint64_t, uint64_t>(const uint64_t *, uint64_t *, uint64_t,
+                                                      uint64_t *, Workspace &);
+
+// ---------------------------------------------------------------- fill
+
+template <class T>
+__global__ void k_fill(T *p, T value, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+template <class T>
+pb_status fill(T *p, T value, uint64_t n, hipStream_t s) {
+    if (n == 0) return PB_OK;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL((k_fill<T>), dim3((uint32_t)blocks), dim3(256), 0, s, p, value, n);
+    PB_TRY_HIP(hipGetLastError());
+    return PB_OK;
+}
+
+template pb_status fill<uint32_t>(uint32_t *, uint32_t, uint64_t, hipStream_t);
+template pb_status fill<uint64_t>(uint64_t *, uint64_t, uint64_t, hipStream_t);
+template pb_status fill<int64_t>(int64_t *, int64_t, uint64_t, hipStream_t);
+
+// ---------------------------------------------------------------- radix sort
+
+constexpr int RS_THREADS = 256;
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+constexpr int RS_WAVES = RS_THREADS / WAVE;
+
+// Lanes of this wave whose (valid) digit equals this lane's digit.
+__device__ inline uint64_t match_digit(uint32_t d, bool valid) {
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool bit = (d >> b) & 1;
+        const uint64_t bal = __ballot(valid && bit);
+        m &= bit ? bal : ~bal;
+    }
+    return m;
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *keys, uint64_t n, int shift,
+                                                        uint32_t *hist, uint32_t nb) {
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const uint64_t idx = base + (uint64_t)it * RS_THREADS + threadIdx.x;
+        const bool valid = idx < n;
+        const uint32_t d = valid ? (uint32_t)(keys[idx] >> shift) & 255u : 0u;
+        const uint64_t m = match_digit(d, valid);
+        if (valid && (m & lanemask_lt()) == 0) atomicAdd(&cnt[d], (uint32_t)__popcll(m));
+    }
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *kin, const uint32_t *vin,
+                                                           uint64_t n, int shift,
+                                                           const uint32_t *hist, uint32_t nb,
+                                                           uint64_t *kout, uint32_t *vout) {
+    __shared__ uint32_t s_base[256];
+    __shared__ uint32_t s_w[RS_WAVES][256];
+    const int tid = threadIdx.x;
+    const int w = tid / WAVE;
+    s_base[tid] = hist[(uint64_t)tid * nb + blockIdx.x];
+    const uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const uint64_t idx = base + (uint64_t)it * RS_THREADS + tid;
+        const bool valid = idx < n;
+        const uint64_t k = valid ? kin[idx] : 0;
+        const uint32_t v = valid ? vin[idx] : 0;
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+#pragma unroll
+        for (int q = 0; q < RS_WAVES; ++q) s_w[q][tid] = 0;
+        __syncthreads();
+        const uint64_t m = match_digit(d, valid);
+        const uint32_t rank_in_wave = (uint32_t)__popcll(m & lanemask_lt());
+        if (valid && rank_in_wave == 0) s_w[w][d] = (uint32_t)__popcll(m);
+        __syncthreads();
+        {
+            uint32_t run = s_base[tid];
+#pragma unroll
+            for (int q = 0; q < RS_WAVES; ++q) {
+                const uint32_t c = s_w[q][tid];
+                s_w[q][tid] = run;
+                run += c;
+            }
+            s_base[tid] = run;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t dst = s_w[w][d] + rank_in_wave;
+            kout[dst] = k;
+            vout[dst] = v;
+        }
+        __syncthreads();
+    }
+}
+
+pb_status radix_sort_pairs(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, uint64_t n,
+                           int nbits, Workspace &ws, uint64_t **kres, uint32_t **vres) {
+    *kres = k0;
+    *vres = v0;
+    if (n <= 1 || nbits <= 0) return PB_OK;
+    if (n >= (uint64_t(1) << 32)) return PB_ERR_INVALID_ARG;
+    const uint32_t nb = ceil_div(n, RS_TILE);
+    uint32_t *hist = ws.alloc<uint32_t>((uint64_t)nb * 256);
+    if (!hist) return PB_ERR_NO_MEMORY;
+    uint64_t *ks = k0, *kd = k1;
+    uint32_t *vs = v0, *vd = v1;
+    for (int shift = 0; shift < nbits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_THREADS), 0, ws.stream, ks, n, shift, hist, nb);
+        PB_TRY_HIP(hipGetLastError());
+        PB_TRY((scan_exclusive<uint32_t, uint32_t>(hist, hist, (uint64_t)nb * 256, nullptr, ws)));
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RS_THREADS), 0, ws.stream, ks, vs, n, shift,
+                           hist, nb, kd, vd);
+        PB_TRY_HIP(hipGetLastError());
+        uint64_t *tk = ks; ks = kd; kd = tk;
+        uint32_t *tv = vs; vs = vd; vd = tv;
+    }
+    ws.release(hist);
+    *kres = ks;
+    *vres = vs;
+    return PB_OK;
+}
+
+}  // namespace pb

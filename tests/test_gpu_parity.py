@@ -1,0 +1,216 @@
+"""GPU parity: the HIP library against the CPU oracle, element by element.
+
+All counts are integers, so the bar is bit-exact equality.  Every test calls
+through the C ABI (the ctypes binding) on cuda:0.
+"""
+import json
+import os
+from itertools import permutations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1907_08607_amd import graphgen as gg
+
+torch = pytest.importorskip("torch")
+pb = pytest.importorskip("paper_1907_08607_amd")
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+KINDS = ["side_auto", "side_u", "side_v", "degree", "approx_degree", "codeg", "approx_codeg"]
+AGGS = ["auto", "hash", "dense"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pb.load_library()
+
+
+def gpu_counts(g, rank, agg="auto", stats=None, **kw):
+    G = pb.Graph.from_csr(g)
+    r = torch.from_numpy(np.asarray(rank, dtype=np.uint32).view(np.int32)).cuda()
+    gl, ve, ed = pb.pb_count(G, r, agg=agg, stats=stats, **kw)
+    torch.cuda.synchronize()
+    out = (int(gl.cpu()[0]), ve.cpu().numpy(), ed.cpu().numpy())
+    G.close()
+    return out
+
+
+def assert_same(got, want, what=""):
+    gl, ve, ed = got
+    wg, wv, we = want
+    assert gl == wg, f"{what}: global {gl} != {wg}"
+    bad = np.nonzero(ve != wv)[0]
+    assert bad.size == 0, f"{what}: per-vertex differs at {bad[:10]} got {ve[bad[:10]]} want {wv[bad[:10]]}"
+    bad = np.nonzero(ed != we)[0]
+    assert bad.size == 0, f"{what}: per-edge differs at {bad[:10]} got {ed[bad[:10]]} want {we[bad[:10]]}"
+
+
+def fig1():
+    with open(os.path.join(GOLDEN, "fig1_example.json")) as f:
+        d = json.load(f)
+    return d, gg.from_edges(d["n_u"], d["n_v"], d["edges_u"], d["edges_v"])
+
+
+# ------------------------------------------------------------------ worked example
+
+def test_fig1_every_order_every_aggregator():
+    d, g = fig1()
+    want = (d["global"], np.array(d["per_vertex_unified"]), np.array(d["per_edge_csr_order"]))
+    for i, perm in enumerate(permutations(range(6))):
+        rank = np.empty(6, dtype=np.uint32)
+        rank[list(perm)] = np.arange(6)
+        agg = AGGS[i % len(AGGS)]
+        stats = pb.pb_stats()
+        assert_same(gpu_counts(g, rank, agg, stats), want, f"perm {perm} {agg}")
+        assert stats.wedges == oracle.wedges(g, rank)
+
+
+def test_fig2_order_wedges():
+    d, g = fig1()
+    rank = np.empty(6, dtype=np.uint32)
+    rank[d["fig2_order_unified"]] = np.arange(6)
+    stats = pb.pb_stats()
+    gpu_counts(g, rank, "auto", stats)
+    assert stats.wedges == d["fig2_wedges_total"]
+
+
+# ------------------------------------------------------------------ ranks
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_rank_matches_reference(kind):
+    for g in (gg.workload_er_1k_planted(), gg.random_small(9, 7, 0.4, 3), gg.workload_powerlaw_50m(scale=0.002)):
+        G = pb.Graph.from_csr(g)
+        r = pb.pb_rank(G, kind).cpu().numpy().view(np.uint32)
+        assert r.tolist() == oracle.rank(g, kind).tolist(), kind
+        G.close()
+
+
+# ------------------------------------------------------------------ small graphs
+
+@pytest.mark.parametrize("seed", range(16))
+def test_tiny_random_graphs(seed):
+    rng = np.random.default_rng(seed)
+    g = gg.random_small(int(rng.integers(1, 9)), int(rng.integers(1, 9)), float(rng.uniform(0.2, 0.9)), seed)
+    want = oracle.count_bf4(g)
+    for kind in ("degree", "side_auto", "approx_codeg"):
+        for agg in AGGS:
+            assert_same(gpu_counts(g, oracle.rank(g, kind), agg), want, f"{kind} {agg}")
+    perm = rng.permutation(g.n_u + g.n_v).astype(np.uint32)
+    assert_same(gpu_counts(g, perm), want, "random perm")
+
+
+def test_empty_and_degenerate_graphs():
+    for g in (gg.from_edges(3, 4, [], []), gg.from_edges(5, 0, [], []), gg.complete(1, 9), gg.complete(9, 1),
+              gg.complete(2, 2)):
+        want = oracle.count(g)
+        for agg in AGGS:
+            assert_same(gpu_counts(g, oracle.rank(g, "degree"), agg), want, f"{g.n_u}x{g.n_v} {agg}")
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("agg", AGGS)
+def test_er_1k_planted(kind, agg):
+    g = gg.workload_er_1k_planted()
+    want = oracle.count(g)
+    rank = oracle.rank(g, kind)
+    stats = pb.pb_stats()
+    assert_same(gpu_counts(g, rank, agg, stats), want, f"{kind} {agg}")
+    assert stats.wedges == oracle.wedges(g, rank)
+    # the planted K_{20,15}: closed forms
+    _, ve, ed = want
+    assert (ed[-300:] == 266).all()
+
+
+@pytest.mark.parametrize("agg", AGGS)
+def test_complete_bipartite(agg):
+    for a, b in ((20, 15), (64, 3), (3, 200)):
+        g = gg.complete(a, b)
+        glob, ve, ed = gpu_counts(g, oracle.rank(g, "degree"), agg)
+        assert glob == (a * (a - 1) // 2) * (b * (b - 1) // 2)
+        assert (ve[:a] == (a - 1) * (b * (b - 1) // 2)).all() and (ve[a:] == (b - 1) * (a * (a - 1) // 2)).all()
+        assert (ed == (a - 1) * (b - 1)).all()
+
+
+@pytest.mark.parametrize("agg", AGGS)
+@pytest.mark.parametrize("kind", ["degree", "side_auto", "approx_degree"])
+def test_powerlaw_small(agg, kind):
+    """Chung-Lu power law at 1% of the 50M-edge workload: many tiles, skewed sources."""
+    g = gg.workload_powerlaw_50m(scale=0.01)
+    want = oracle.count(g)
+    rank = oracle.rank(g, kind)
+    stats = pb.pb_stats()
+    assert_same(gpu_counts(g, rank, agg, stats), want, f"powerlaw {kind} {agg}")
+    assert stats.wedges == oracle.wedges(g, rank)
+
+
+def test_hub_skewed_small():
+    g = gg.workload_hub_100m(scale=0.005)
+    want = oracle.count(g)
+    for kind in ("approx_codeg", "degree"):
+        assert_same(gpu_counts(g, oracle.rank(g, kind)), want, kind)
+
+
+def test_single_output_calls_agree():
+    g = gg.workload_er_1k_planted()
+    want = oracle.count(g)
+    G = pb.Graph.from_csr(g)
+    r = pb.pb_rank(G, "degree")
+    assert int(pb.pb_count_global(G, r).cpu()[0]) == want[0]
+    assert (pb.pb_count_vertex(G, r).cpu().numpy() == want[1]).all()
+    assert (pb.pb_count_edge(G, r).cpu().numpy() == want[2]).all()
+    G.close()
+
+
+def test_repeatable_bit_identical():
+    g = gg.workload_powerlaw_50m(scale=0.005)
+    rank = oracle.rank(g, "degree")
+    a = gpu_counts(g, rank)
+    b = gpu_counts(g, rank)
+    assert_same(a, b, "run-to-run")
+
+
+# ------------------------------------------------------------------ error paths
+
+def test_invalid_inputs_are_rejected():
+    g = gg.complete(3, 3)
+    off = torch.from_numpy(g.u_off).cuda()
+    adj = g.u_adj.copy()
+    adj[1] = adj[0]
+    with pytest.raises(pb.PBError) as e:
+        pb.Graph(3, 3, off, torch.from_numpy(adj.view(np.int32)).cuda())
+    assert e.value.status == -2
+    adj = g.u_adj.copy()
+    adj[4] = 7
+    with pytest.raises(pb.PBError) as e:
+        pb.Graph(3, 3, off, torch.from_numpy(adj.view(np.int32)).cuda())
+    assert e.value.status == -3
+    bad_off = g.u_off.copy()
+    bad_off[2] = 100
+    with pytest.raises(pb.PBError) as e:
+        pb.Graph(3, 3, torch.from_numpy(bad_off).cuda(), torch.from_numpy(g.u_adj.view(np.int32)).cuda())
+    assert e.value.status == -3
+    G = pb.Graph.from_csr(g)
+    bad_rank = torch.zeros(6, dtype=torch.int32, device="cuda")
+    with pytest.raises(pb.PBError) as e:
+        pb.pb_count(G, bad_rank)
+    assert e.value.status == -4
+    out_of_range = torch.arange(6, dtype=torch.int32, device="cuda") + 1
+    with pytest.raises(pb.PBError) as e:
+        pb.pb_count(G, out_of_range)
+    assert e.value.status == -4
+    G.close()
+
+
+def test_workspace_cap_too_small():
+    g = gg.workload_er_1k()
+    G = pb.Graph.from_csr(g)
+    r = pb.pb_rank(G, "degree")
+    with pytest.raises(pb.PBError) as e:
+        pb.pb_count(G, r, workspace_cap=4096)
+    assert e.value.status == -5
+    G.close()
