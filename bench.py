@@ -22,10 +22,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic bytes per wedge of the dense-window kernel when it produces all
-# three outputs: the wedge's x2 read in each of the two passes (2 x 4 B) plus
-# one int64 read-modify-write of the credited slot (16 B)
-BYTES_PER_WEDGE = 24
+# algorithmic bytes per wedge of the dense-window kernel: the wedge's x2 is
+# read once per pass (4 B); per-vertex output needs the second pass (8 B);
+# per-edge output adds one int64 read-modify-write of the credited slot (16 B)
+BYTES_PER_WEDGE = {"global": 4, "vertex": 8, "edge": 24, "all": 24}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (tests only)")
     ap.add_argument("--rank", default=None, help="ordering (default: the workload's own)")
     ap.add_argument("--agg", default="auto", choices=["auto", "hash", "dense", "sort"])
+    ap.add_argument("--outputs", default="all", choices=["all", "global", "vertex", "edge"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-target-s", type=float, default=15.0, help="CPU-baseline sample budget")
     return ap.parse_args()
@@ -61,7 +62,7 @@ def make_graph(args):
         rank = "side_auto"
     rank = args.rank or rank
     desc["rank"] = rank
-    desc["outputs"] = "global+vertex+edge"
+    desc["outputs"] = "global+vertex+edge" if args.outputs == "all" else args.outputs
     return g, desc, rank
 
 
@@ -110,10 +111,13 @@ def main():
             torch.empty(g.m, dtype=torch.int64, device="cuda"))
     stream = torch.cuda.current_stream()
 
+    want = {"all": (0, 1, 2), "global": (0,), "vertex": (1,), "edge": (2,)}[args.outputs]
+    step_outs = tuple(o if i in want else None for i, o in enumerate(outs))
+
     def step(stats):
         G = pb.Graph(g.n_u, g.n_v, off, adj, stream)
         r = pb.pb_rank(G, rank_kind, stream=stream)
-        pb.pb_count(G, r, agg=args.agg, stats=stats, outs=outs, stream=stream, timing=True)
+        pb.pb_count(G, r, agg=args.agg, stats=stats, outs=step_outs, stream=stream, timing=True)
         G.close()
 
     for i in range(args.warmup):
@@ -136,19 +140,20 @@ def main():
     value = wedges * args.steps / elapsed
     dense_ms = sum(s.ms_dense for s in stats) / len(stats)
     w_dense = stats[0].wedges_dense
-    achieved = (w_dense * BYTES_PER_WEDGE / (dense_ms * 1e-3)) / 1e9 if dense_ms > 0 else 0.0
+    bpw = BYTES_PER_WEDGE[args.outputs]
+    achieved = (w_dense * bpw / (dense_ms * 1e-3)) / 1e9 if dense_ms > 0 else 0.0
     phases = {k: round(sum(getattr(s, k) for s in stats) / len(stats), 3)
               for k in ("ms_prepare", "ms_dense", "ms_hash", "ms_output")}
     record = {
         "metric": "wedges/s", "value": value, "unit": "wedges/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-        "config": dict(desc, wedges=wedges, butterflies=int(outs[0].cpu()[0]), phases_ms=phases,
+        "config": dict(desc, wedges=wedges, butterflies=int(outs[0].cpu()[0]) if 0 in want else None, phases_ms=phases,
                        wedges_dense=w_dense, wedges_hash=stats[0].wedges_hash,
                        window_items=stats[0].window_items),
         "roofline": {"bound": "hbm", "kernel": "k_count_dense", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_wedge": BYTES_PER_WEDGE, "wedges_per_launch": w_dense,
+                     "bytes_per_wedge": bpw, "wedges_per_launch": w_dense,
                      "launch_ms": dense_ms},
         "cpu_baseline": None,
     }

@@ -127,13 +127,13 @@ enum : int { LIST_LIGHT = 0, LIST_MEDIUM = 1, LIST_HEAVY = 2, LIST_SMALLDENSE = 
 
 constexpr uint32_t LIGHT_D = 512;     // distinct bound handled by the 1-wave hash (1024 slots)
 constexpr uint32_t MEDIUM_D = 4096;   // distinct bound handled by the 256-thread hash (8192 slots)
-constexpr uint32_t SMALL_WIN = 4096;  // dense window of the 256-thread dense kernel
-constexpr uint32_t BIG_WIN = 32768;   // dense window of the 1024-thread dense kernel
+constexpr uint32_t SMALL_WIN = 4096;  // dense range of the 256-thread whole-range dense kernel
+constexpr uint32_t WIN_WORDS = 32768; // 128 KB of LDS counters in the heavy kernel
 constexpr uint32_t HASH_WIN = 4096;   // candidate window of a forced-hash heavy item
 
 struct PlanCounts {
     uint32_t list[NLISTS];
-    uint32_t items;  // heavy (source, window) items
+    uint32_t items;  // forced-hash heavy (source, window) items
     uint32_t flags;
     unsigned long long sources;
     unsigned long long wedges[NLISTS];
@@ -150,24 +150,15 @@ __global__ void k_plan(const uint32_t *upoff, const uint64_t *wscan, const uint3
         const uint32_t range = side_end - smid[r] - 1;
         const uint64_t dist = w < range ? w : range;
         int which;
-        uint32_t win = 0;
-        if (agg == PB_AGG_LDS_HASH) {
-            if (dist <= LIGHT_D) which = LIST_LIGHT;
-            else if (dist <= MEDIUM_D) which = LIST_MEDIUM;
-            else { which = LIST_HEAVY; win = HASH_WIN; }
-        } else if (agg == PB_AGG_DENSE_HIST) {
-            if (range <= SMALL_WIN) which = LIST_SMALLDENSE;
-            else { which = LIST_HEAVY; win = BIG_WIN; }
-        } else {  // AUTO
-            if (dist <= LIGHT_D) which = LIST_LIGHT;
-            else if (dist <= MEDIUM_D) which = LIST_MEDIUM;
-            else { which = LIST_HEAVY; win = BIG_WIN; }
-        }
+        if (agg == PB_AGG_DENSE_HIST) which = range <= SMALL_WIN ? LIST_SMALLDENSE : LIST_HEAVY;
+        else if (dist <= LIGHT_D) which = LIST_LIGHT;
+        else if (dist <= MEDIUM_D) which = LIST_MEDIUM;
+        else which = LIST_HEAVY;
         const uint32_t slot = atomicAdd(&pc->list[which], 1u);
         atomicAdd(&pc->wedges[which], (unsigned long long)w);
         lists[(uint64_t)which * n + slot] = (uint32_t)r;
         if (which == LIST_HEAVY) {
-            const uint32_t nw = (range + win - 1) / win;
+            const uint32_t nw = agg == PB_AGG_LDS_HASH ? (range + HASH_WIN - 1) / HASH_WIN : 1u;
             heavy_nwin[slot] = nw;
             heavy_w[slot] = w;
             atomicAdd(&pc->items, nw);
@@ -175,10 +166,9 @@ __global__ void k_plan(const uint32_t *upoff, const uint64_t *wscan, const uint3
     }
 }
 
-// Sort key for the heavy list: most wedges per window first (longest items
-// are dispatched first).
-__global__ void k_heavy_keys(const uint32_t *heavy, const uint32_t *nwin, const uint64_t *w, uint32_t nh,
-                             uint64_t *keys, uint32_t *vals) {
+// Sort key for the heavy list: most wedges per item first (longest items are
+// dispatched first).
+__global__ void k_heavy_keys(const uint32_t *nwin, const uint64_t *w, uint32_t nh, uint64_t *keys, uint32_t *vals) {
     GRID_STRIDE(i, (uint64_t)nh) {
         uint64_t per = w[i] / nwin[i];
         if (per > 0xFFFFFFFFull) per = 0xFFFFFFFFull;
@@ -195,11 +185,12 @@ __global__ void k_heavy_gather(const uint32_t *perm, const uint32_t *heavy, cons
     }
 }
 
+// forced-hash items: x = source rank, y = window index
 __global__ void k_heavy_expand(const uint32_t *src_sorted, const uint32_t *nwin_sorted, const uint32_t *ioff,
                                uint32_t nh, uint2 *items) {
     GRID_STRIDE(i, (uint64_t)nh) {
         const uint32_t o = ioff[i];
-        for (uint32_t w = 0; w < nwin_sorted[i]; ++w) items[o + w] = make_uint2(src_sorted[i], w);
+        for (uint32_t j = 0; j < nwin_sorted[i]; ++j) items[o + j] = make_uint2(src_sorted[i], j);
     }
 }
 
@@ -213,14 +204,19 @@ struct Ranked {
 struct Acc {
     unsigned long long *g;  // 1
     unsigned long long *v;  // n, by smid
-    unsigned long long *s;  // 2m, by slot
+    unsigned long long *s;  // 2m, by slot (64-bit slot credits)
+    uint32_t *s32;          // 2m, by slot, when every slot's credit fits 32 bits
     uint32_t *err;          // internal-consistency flag
     int mode;
+    __device__ void slot_add(uint32_t p, unsigned long long d) const {
+        if (s32) atomicAdd(&s32[p], (uint32_t)d);
+        else atomicAdd(&s[p], d);
+    }
 };
 
-// Smallest i in [0, len] with p[i] < v (p strictly decreasing).
-__device__ inline uint32_t first_below(const uint32_t *p, uint32_t len, uint32_t v) {
-    uint32_t lo = 0, hi = len;
+// Smallest i in [lo, len] with p[i] < v (p strictly decreasing, p[j] >= v for j < lo).
+__device__ inline uint32_t first_below(const uint32_t *p, uint32_t lo, uint32_t len, uint32_t v) {
+    uint32_t hi = len;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
         if (p[mid] < v) hi = mid; else lo = mid + 1;
@@ -228,25 +224,54 @@ __device__ inline uint32_t first_below(const uint32_t *p, uint32_t len, uint32_t
     return lo;
 }
 
-// Dense counters for the candidate window [lo, lo + size).
+// The same by galloping forward from s (cheap when the answer is near s).
+__device__ inline uint32_t gallop_below(const uint32_t *p, uint32_t s, uint32_t len, uint32_t v) {
+    if (s >= len || p[s] < v) return s;
+    uint32_t lo = s, step = 1;  // p[lo] >= v
+    while (lo + step < len && p[lo + step] >= v) {
+        lo += step;
+        step <<= 1;
+    }
+    const uint32_t hi = lo + step < len ? lo + step : len;
+    return first_below(p, lo + 1, hi, v);
+}
+
+// Dense counters for the candidate window [lo, lo + size); 16-bit counters
+// packed two to a word when `half`.
 template <int T>
 struct DenseAgg {
-    uint32_t *cnt;
+    uint32_t *w;
     uint32_t lo, size;
-    __device__ void init() const {
-        for (uint32_t i = threadIdx.x; i < size; i += T) cnt[i] = 0;
-    }
+    bool half;
     uint32_t *err;
-    __device__ void insert(uint32_t x) const {
-        if (x - lo < size) atomicAdd(&cnt[x - lo], 1u);
-        else atomicOr(err, FLAG_INTERNAL);
+    __device__ void init() const {
+        const uint32_t words = half ? (size + 1) >> 1 : size;
+        for (uint32_t i = threadIdx.x; i < words; i += T) w[i] = 0;
     }
-    __device__ uint32_t count(uint32_t x) const { return x - lo < size ? cnt[x - lo] : 1u; }
+    __device__ void insert(uint32_t x) const {
+        const uint32_t d = x - lo;
+        if (d >= size) { atomicOr(err, FLAG_INTERNAL); return; }
+        if (half) atomicAdd(&w[d >> 1], 1u << ((d & 1) << 4));
+        else atomicAdd(&w[d], 1u);
+    }
+    __device__ uint32_t count(uint32_t x) const {
+        const uint32_t d = x - lo;
+        if (d >= size) return 1u;
+        return half ? (w[d >> 1] >> ((d & 1) << 4)) & 0xFFFFu : w[d];
+    }
     template <class F>
     __device__ void for_each(F f) const {
-        for (uint32_t i = threadIdx.x; i < size; i += T) {
-            const uint32_t c = cnt[i];
-            if (c) f(lo + i, c);
+        if (half) {
+            for (uint32_t i = threadIdx.x; 2 * i < size; i += T) {
+                const uint32_t v = w[i];
+                if (v & 0xFFFFu) f(lo + 2 * i, v & 0xFFFFu);
+                if (v >> 16) f(lo + 2 * i + 1, v >> 16);
+            }
+        } else {
+            for (uint32_t i = threadIdx.x; i < size; i += T) {
+                const uint32_t c = w[i];
+                if (c) f(lo + i, c);
+            }
         }
     }
 };
@@ -292,19 +317,63 @@ struct HashAgg {
     }
 };
 
+// Which part [a, a + cnt) of run k (up-slot k, run N(y)[0, pos) at nbr[start])
+// an item covers, in each pass.
+struct FullRange {
+    __device__ void operator()(const Ranked &, int, uint32_t, uint32_t, uint32_t pos, uint32_t &a,
+                               uint32_t &cnt) const {
+        a = 0;
+        cnt = pos;
+    }
+};
+
+// Candidate window [lo, hi): both ends by binary search.
+struct SearchRange {
+    uint32_t lo, hi;
+    __device__ void operator()(const Ranked &G, int, uint32_t, uint32_t start, uint32_t pos, uint32_t &a,
+                               uint32_t &cnt) const {
+        a = first_below(G.nbr + start, 0, pos, hi);
+        cnt = first_below(G.nbr + start, a, pos, lo) - a;
+    }
+};
+
+// Windows of one source taken from the highest ids down: each run's part in
+// the window starts where its part in the previous window ended (cursor `cur`,
+// one per up-slot), and ends at the first entry below lo, found by galloping
+// from the cursor.  Pass 1 stores the end in `nxt`; pass 2 (or pass 1 when
+// there is no pass 2) advances the cursor.
+struct CursorRange {
+    uint32_t *cur, *nxt;
+    uint32_t lo;
+    bool first, two_pass;
+    __device__ void operator()(const Ranked &G, int pass, uint32_t k, uint32_t start, uint32_t pos, uint32_t &a,
+                               uint32_t &cnt) const {
+        const uint32_t s = first ? 0u : cur[k];
+        uint32_t e;
+        if (pass == 1) {
+            e = gallop_below(G.nbr + start, s, pos, lo);
+            if (two_pass) nxt[k] = e; else cur[k] = e;
+        } else {
+            e = nxt[k];
+            cur[k] = e;
+        }
+        a = s;
+        cnt = e - s;
+    }
+};
+
 template <int T>
 struct RunShared {
-    uint32_t off[T];
-    uint32_t begin[T];
+    uint32_t off[T];    // flat start of each non-empty run part (compacted)
+    uint32_t begin[T];  // slot of its first wedge
+    uint32_t kidx[T];   // its up-slot index
     unsigned long long sum[T];
-    uint32_t tmp[T / WAVE + 1];
     unsigned long long tmp64[T / WAVE + 1];
 };
 
-// Largest i with off[i] <= f among i < T (off non-decreasing, off[0] = 0).
-template <int T>
-__device__ inline uint32_t run_of(const uint32_t *off, uint32_t f) {
-    uint32_t lo = 0, hi = T;
+// Largest i in [lo, n) with off[i] <= f (off strictly increasing, off[lo] <= f).
+__device__ inline uint32_t last_le(const uint32_t *off, uint32_t lo, uint32_t n, uint32_t f) {
+    uint32_t hi = n;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
         if (off[mid] <= f) lo = mid; else hi = mid;
@@ -312,71 +381,127 @@ __device__ inline uint32_t run_of(const uint32_t *off, uint32_t f) {
     return lo;
 }
 
-// One work item: source r, candidate x2 window [lo, hi).  Pass 1 retrieves the
-// wedges (Algorithm 2) into the aggregator (GET-FREQ); the endpoint step adds
-// C(R,2) per pair (total, and both endpoints for per-vertex); pass 2 walks the
-// wedges again and adds R-1 to each center / both edges (Algorithms 3, 4).
-template <int T, class Agg>
-__device__ void count_item(const Ranked &G, const Acc &A, uint32_t r, uint32_t lo, uint32_t hi, const Agg &agg,
+// One work item: source r and the part of each of its runs that `range`
+// selects.  Pass 1 retrieves the wedges (Algorithm 2) into the aggregator
+// (GET-FREQ); the endpoint step adds C(R,2) per pair (total, and both
+// endpoints for per-vertex); pass 2 walks the wedges again and adds R-1 to
+// each center / both edges (Algorithms 3, 4).
+//
+// Up-slots are taken T at a time; the non-empty run parts are compacted and
+// laid end to end (block scan).  Each wave walks that flat sequence U*64
+// wedges at a time with lane-consecutive wedges, so the reads of x2 and the
+// per-edge credit atomics are coalesced.  For each 64 wedges the wave keeps the
+// (at most 64) runs they touch one per lane, and a lane finds its run with a
+// 6-step shuffle search.
+template <int T, int U, class Agg, class Range>
+__device__ void count_item(const Ranked &G, const Acc &A, uint32_t r, const Agg &agg, const Range &range,
                            RunShared<T> &sh) {
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
     const uint32_t k0 = G.upoff[r], k1 = G.upoff[r + 1];
-    const uint32_t side_end = G.isv[r] ? G.n : G.n_u;
-    const bool windowed = !(lo == G.smid[r] + 1 && hi == side_end);
     agg.init();
     __syncthreads();
     const int passes = (A.mode & (MODE_VERTEX | MODE_EDGE)) ? 2 : 1;
+    const bool edge = A.mode & MODE_EDGE;
     for (int pass = 1; pass <= passes; ++pass) {
         for (uint32_t c = k0; c < k1; c += T) {
             const uint32_t k = c + tid;
             uint32_t a = 0, cnt = 0, start = 0;
             if (k < k1) {
                 start = G.uprun[k];
-                const uint32_t len = G.uplen[k];
-                if (windowed) {
-                    a = first_below(G.nbr + start, len, hi);
-                    cnt = first_below(G.nbr + start, len, lo) - a;
-                } else {
-                    cnt = len;
-                }
+                range(G, pass, k, start, G.uplen[k], a, cnt);
             }
-            uint32_t total;
-            const uint32_t off = block_exclusive_sum<T>(cnt, sh.tmp, &total);
-            sh.off[tid] = off;
-            sh.begin[tid] = start + a;
-            if (pass == 2) sh.sum[tid] = 0;
+            // one scan gives both the flat offset (low 32 bits) and the
+            // compacted index (high 32 bits) of every non-empty part
+            const unsigned long long packed = ((unsigned long long)(cnt > 0) << 32) | cnt;
+            unsigned long long tot64;
+            const unsigned long long pre = block_exclusive_sum<T>(packed, sh.tmp64, &tot64);
+            const uint32_t total = (uint32_t)tot64, nne = (uint32_t)(tot64 >> 32);
+            if (cnt > 0) {
+                const uint32_t ci = (uint32_t)(pre >> 32);
+                sh.off[ci] = (uint32_t)pre;
+                sh.begin[ci] = start + a;
+                sh.kidx[ci] = k;
+                if (pass == 2) sh.sum[ci] = 0;
+            }
             __syncthreads();
-            for (uint32_t f = tid; f < total; f += T) {
-                const uint32_t i = run_of<T>(sh.off, f);
-                const uint32_t p = sh.begin[i] + (f - sh.off[i]);
-                const uint32_t x2 = G.nbr[p];
+            // runs i0 .. i0+63 held one per lane: o = flat start, bg = slot
+            uint32_t i0 = 0, o = 0, bg = 0, o_end = 0;
+            for (uint32_t wb = wv * (U * WAVE); wb < total; wb += T * U) {
+                uint32_t pidx[U], rel[U], xs[U];
+                bool ok[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t base = wb + u * WAVE;
+                    ok[u] = base + lane < total;
+                    rel[u] = WAVE;
+                    pidx[u] = 0;
+                    if (base < total) {  // wave-uniform
+                        const uint32_t last = base + WAVE - 1 < total ? base + WAVE - 1 : total - 1;
+                        if (last >= o_end) {
+                            // reload: the 64 runs from the one holding `base`
+                            // always cover [base, base + 64)
+                            i0 = last_le(sh.off, i0, nne, base);
+                            const uint32_t kk = i0 + lane;
+                            o = kk < nne ? sh.off[kk] : 0xFFFFFFFFu;
+                            bg = kk < nne ? sh.begin[kk] : 0u;
+                            o_end = i0 + WAVE < nne ? sh.off[i0 + WAVE] : total;
+                        }
+                        const uint32_t f = base + lane;
+                        uint32_t lo = 0;
+#pragma unroll
+                        for (int step = WAVE / 2; step >= 1; step >>= 1) {
+                            const uint32_t cand = lo + step;
+                            if (__shfl(o, cand, WAVE) <= f) lo = cand;
+                        }
+                        const uint32_t ro = __shfl(o, lo, WAVE), rb = __shfl(bg, lo, WAVE);
+                        pidx[u] = rb + (f - ro);
+                        if (ok[u]) rel[u] = i0 + lo;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (ok[u]) xs[u] = G.nbr[pidx[u]];
                 if (pass == 1) {
-                    agg.insert(x2);
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (ok[u]) agg.insert(xs[u]);
                 } else {
-                    const uint32_t d = agg.count(x2) - 1;
-                    if (d) {
-                        if (A.mode & MODE_EDGE) atomicAdd(&A.s[p], (unsigned long long)d);
-                        atomicAdd(&sh.sum[i], (unsigned long long)d);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        if (wb + u * WAVE >= total) break;  // wave-uniform
+                        uint32_t d = ok[u] ? agg.count(xs[u]) - 1 : 0u;
+                        if (d && edge) A.slot_add(pidx[u], d);
+                        // segmented sum of d over lanes of the same run (runs are
+                        // lane-contiguous); d < 2^22 so 64 of them fit 32 bits
+#pragma unroll
+                        for (int sft = 1; sft < WAVE; sft <<= 1) {
+                            const uint32_t t = __shfl_down(d, sft, WAVE);
+                            const uint32_t tr = __shfl_down(rel[u], sft, WAVE);
+                            if (lane + sft < WAVE && tr == rel[u]) d += t;
+                        }
+                        const uint32_t prev = __shfl_up(rel[u], 1, WAVE);
+                        if (ok[u] && d && (lane == 0 || prev != rel[u]))
+                            atomicAdd(&sh.sum[rel[u]], (unsigned long long)d);
                     }
                 }
             }
             __syncthreads();
-            if (pass == 2 && k < k1) {
-                const unsigned long long s = sh.sum[tid];
-                if (s) {
-                    const uint32_t up = G.roff[r] + (k - k0);  // slot (r -> y)
-                    if (A.mode & MODE_VERTEX) atomicAdd(&A.v[G.nbr[up]], s);
-                    if (A.mode & MODE_EDGE) atomicAdd(&A.s[up], s);
+            if (pass == 2 && tid < nne) {
+                const unsigned long long sm = sh.sum[tid];
+                if (sm) {
+                    const uint32_t up = G.roff[r] + (sh.kidx[tid] - k0);  // slot (r -> y)
+                    if (A.mode & MODE_VERTEX) atomicAdd(&A.v[G.nbr[up]], sm);
+                    if (edge) A.slot_add(up, sm);
                 }
             }
+            __syncthreads();
         }
         if (pass == 1) {
-            __syncthreads();
             unsigned long long local = 0;
             const bool vert = A.mode & MODE_VERTEX;
-            agg.for_each([&](uint32_t key, uint32_t c) {
-                if (c >= 2) {
-                    const unsigned long long t = (unsigned long long)c * (c - 1) / 2;
+            agg.for_each([&](uint32_t key, uint32_t cc) {
+                if (cc >= 2) {
+                    const unsigned long long t = (unsigned long long)cc * (cc - 1) / 2;
                     local += t;
                     if (vert) atomicAdd(&A.v[key], t);
                 }
@@ -392,62 +517,72 @@ __device__ void count_item(const Ranked &G, const Acc &A, uint32_t r, uint32_t l
     __syncthreads();
 }
 
-template <int T, int CAP>
+template <int T, int U, int CAP>
 __global__ __launch_bounds__(T) void k_count_hash(Ranked G, Acc A, const uint32_t *list, uint32_t count) {
     __shared__ uint32_t keys[CAP];
     __shared__ uint32_t cnts[CAP];
     __shared__ RunShared<T> sh;
     HashAgg<T, CAP> agg{keys, cnts, A.err};
-    for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
-        const uint32_t r = list[i];
-        count_item<T>(G, A, r, G.smid[r] + 1, G.isv[r] ? G.n : G.n_u, agg, sh);
-    }
+    for (uint32_t i = blockIdx.x; i < count; i += gridDim.x)
+        count_item<T, U>(G, A, list[i], agg, FullRange{}, sh);
 }
 
-// Hash over a candidate window of at most CAP/2 ids (forced hash on heavy sources).
-template <int T, int CAP>
-__global__ __launch_bounds__(T) void k_count_hash_win(Ranked G, Acc A, const uint2 *items, uint32_t count,
-                                                       uint32_t win) {
+// Hash over a candidate window of at most CAP/2 ids (forced hash on heavy
+// sources); the window's part of each run is found by binary search.
+template <int T, int U, int CAP>
+__global__ __launch_bounds__(T) void k_count_hash_win(Ranked G, Acc A, const uint2 *items, uint32_t count) {
     __shared__ uint32_t keys[CAP];
     __shared__ uint32_t cnts[CAP];
     __shared__ RunShared<T> sh;
     HashAgg<T, CAP> agg{keys, cnts, A.err};
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
         const uint2 it = items[i];
-        const uint32_t r = it.x;
+        const uint32_t r = it.x, w = it.y;
         const uint32_t side_end = G.isv[r] ? G.n : G.n_u;
-        const uint32_t lo = G.smid[r] + 1 + it.y * win;
-        const uint32_t hi = side_end - lo > win ? lo + win : side_end;
-        count_item<T>(G, A, r, lo, hi, agg, sh);
+        const uint32_t lo = G.smid[r] + 1 + w * HASH_WIN;
+        const uint32_t hi = side_end - lo > HASH_WIN ? lo + HASH_WIN : side_end;
+        count_item<T, U>(G, A, r, agg, SearchRange{lo, hi}, sh);
     }
 }
 
-template <int T, int WIN>
-__global__ __launch_bounds__(T) void k_count_dense(Ranked G, Acc A, const uint2 *items, uint32_t count) {
-    __shared__ uint32_t cnt[WIN];
+// Heavy sources: one workgroup per source sweeps the source's candidate range
+// from the top in windows that fit 128 KB of LDS counters (65536 ids with
+// 16-bit counters when the source has fewer than 65536 up-neighbours, since
+// R(x1, x2) <= deg_x1(x1); else 32768 ids).
+template <int T, int U>
+__global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32_t *list, uint32_t *cur, uint32_t *nxt,
+                                                   uint32_t count) {
+    __shared__ uint32_t words[WIN_WORDS];
     __shared__ RunShared<T> sh;
+    const bool two_pass = A.mode & (MODE_VERTEX | MODE_EDGE);
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
-        const uint2 it = items[i];
-        const uint32_t r = it.x;
-        const uint32_t side_end = G.isv[r] ? G.n : G.n_u;
-        const uint32_t lo = G.smid[r] + 1 + it.y * WIN;
-        const uint32_t hi = side_end - lo > (uint32_t)WIN ? lo + WIN : side_end;
-        DenseAgg<T> agg{cnt, lo, hi - lo, A.err};
-        count_item<T>(G, A, r, lo, hi, agg, sh);
+        const uint32_t r = list[i];
+        const bool half = G.upoff[r + 1] - G.upoff[r] <= 0xFFFFu;
+        const uint32_t ws = half ? 2 * WIN_WORDS : WIN_WORDS;
+        const uint32_t lo_min = G.smid[r] + 1;
+        uint32_t hi = G.isv[r] ? G.n : G.n_u;
+        bool first = true;
+        while (hi > lo_min) {
+            const uint32_t lo = hi - lo_min > ws ? hi - ws : lo_min;
+            DenseAgg<T> agg{words, lo, hi - lo, half, A.err};
+            count_item<T, U>(G, A, r, agg, CursorRange{cur, nxt, lo, first, two_pass}, sh);
+            hi = lo;
+            first = false;
+        }
     }
 }
 
-// Whole-range dense counting for sources whose candidate range fits WIN.
-template <int T, int WIN>
+// Whole-range dense counting for sources whose candidate range fits WINSZ.
+template <int T, int U, int WINSZ>
 __global__ __launch_bounds__(T) void k_count_dense_src(Ranked G, Acc A, const uint32_t *list, uint32_t count) {
-    __shared__ uint32_t cnt[WIN];
+    __shared__ uint32_t words[WINSZ];
     __shared__ RunShared<T> sh;
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
         const uint32_t r = list[i];
         const uint32_t side_end = G.isv[r] ? G.n : G.n_u;
         const uint32_t lo = G.smid[r] + 1;
-        DenseAgg<T> agg{cnt, lo, side_end - lo, A.err};
-        count_item<T>(G, A, r, lo, side_end, agg, sh);
+        DenseAgg<T> agg{words, lo, side_end - lo, false, A.err};
+        count_item<T, U>(G, A, r, agg, FullRange{}, sh);
     }
 }
 
@@ -460,8 +595,13 @@ __global__ void k_out_vertex(const uint32_t *rank, const uint32_t *smid, const u
     GRID_STRIDE(x, n) out[x] = (int64_t)v[smid[rank[x]]];
 }
 
-__global__ void k_out_edge(const uint32_t *eslot, const unsigned long long *s, uint64_t m, int64_t *out) {
-    GRID_STRIDE(e, m) out[e] = (int64_t)(s[eslot[2 * e]] + s[eslot[2 * e + 1]]);
+__global__ void k_out_edge(const uint32_t *eslot, const unsigned long long *s, const uint32_t *s32, uint64_t m,
+                           int64_t *out) {
+    if (s32) {
+        GRID_STRIDE(e, m) out[e] = (int64_t)s32[eslot[2 * e]] + (int64_t)s32[eslot[2 * e + 1]];
+    } else {
+        GRID_STRIDE(e, m) out[e] = (int64_t)(s[eslot[2 * e]] + s[eslot[2 * e + 1]]);
+    }
 }
 
 constexpr uint32_t MAX_ITEM_GRID = 1u << 20;
@@ -517,13 +657,18 @@ pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, 
     // Accumulators first so an empty graph still writes zeros.
     unsigned long long *gacc = ws.alloc<unsigned long long>(1);
     unsigned long long *vacc = (mode & MODE_VERTEX) ? ws.alloc<unsigned long long>(n) : nullptr;
-    unsigned long long *sacc = (mode & MODE_EDGE) ? ws.alloc<unsigned long long>(ns) : nullptr;
+    // A slot's credit is at most deg(y) * deg(x2) (one R-1 <= deg(x2)-1 per
+    // neighbour of y), so 32-bit slot counters are exact when max_deg^2 < 2^32.
+    const bool slot32 = (uint64_t)g->max_deg * g->max_deg < (uint64_t(1) << 32);
+    unsigned long long *sacc = (mode & MODE_EDGE) && !slot32 ? ws.alloc<unsigned long long>(ns) : nullptr;
+    uint32_t *sacc32 = (mode & MODE_EDGE) && slot32 ? ws.alloc<uint32_t>(ns) : nullptr;
     PlanCounts *pc = ws.alloc<PlanCounts>(1);
     uint32_t *order = ws.alloc<uint32_t>(n), *seen = ws.alloc<uint32_t>(n);
     if (ws.failed) return PB_ERR_NO_MEMORY;
     PB_TRY(fill<uint64_t>((uint64_t *)gacc, 0, 1, s));
     if (vacc) PB_TRY(fill<uint64_t>((uint64_t *)vacc, 0, n, s));
     if (sacc) PB_TRY(fill<uint64_t>((uint64_t *)sacc, 0, ns, s));
+    if (sacc32) PB_TRY(fill<uint32_t>(sacc32, 0u, ns, s));
     PB_TRY(fill<uint32_t>((uint32_t *)pc, 0u, sizeof(PlanCounts) / 4, s));
 
     // 1. rank check (one sync) -------------------------------------------------
@@ -596,48 +741,55 @@ pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, 
         PB_TRY_HIP(hipStreamSynchronize(s));
         const PlanCounts plan = *hpc;
 
-        // heavy items, most wedges per window first
+        // heavy sources, most wedges first (forced hash: their windows)
         const uint32_t nh = plan.list[LIST_HEAVY];
+        const bool hash_heavy = opts.agg == PB_AGG_LDS_HASH;
         uint2 *items = nullptr;
+        uint32_t *hsrc = nullptr, *cur = nullptr, *nxt = nullptr;
         if (nh > 0) {
             uint64_t *hk0 = ws.alloc<uint64_t>(nh), *hk1 = ws.alloc<uint64_t>(nh);
             uint32_t *hv0 = ws.alloc<uint32_t>(nh), *hv1 = ws.alloc<uint32_t>(nh);
-            uint32_t *hsrc = ws.alloc<uint32_t>(nh), *hnw = ws.alloc<uint32_t>(nh), *hoff = ws.alloc<uint32_t>(nh + 1);
-            items = ws.alloc<uint2>(plan.items);
+            uint32_t *hnw = ws.alloc<uint32_t>(nh), *hoff = ws.alloc<uint32_t>(nh + 1);
+            hsrc = ws.alloc<uint32_t>(nh);
+            if (hash_heavy) items = ws.alloc<uint2>(plan.items);
+            else {
+                cur = ws.alloc<uint32_t>(m);
+                nxt = ws.alloc<uint32_t>(m);
+            }
             if (ws.failed) return PB_ERR_NO_MEMORY;
             const uint32_t *heavy = lists + (uint64_t)LIST_HEAVY * n;
-            hipLaunchKernelGGL(k_heavy_keys, dim3(grid_for(nh)), dim3(256), 0, s, heavy, heavy_nwin, heavy_w, nh, hk0,
-                               hv0);
+            hipLaunchKernelGGL(k_heavy_keys, dim3(grid_for(nh)), dim3(256), 0, s, heavy_nwin, heavy_w, nh, hk0, hv0);
             uint64_t *hks;
             uint32_t *hvs;
             PB_TRY(radix_sort_pairs(hk0, hv0, hk1, hv1, nh, 32, ws, &hks, &hvs));
             hipLaunchKernelGGL(k_heavy_gather, dim3(grid_for(nh)), dim3(256), 0, s, hvs, heavy, heavy_nwin, nh, hsrc,
                                hnw);
-            PB_TRY((scan_exclusive<uint32_t, uint32_t>(hnw, hoff, nh, hoff + nh, ws)));
-            hipLaunchKernelGGL(k_heavy_expand, dim3(grid_for(nh)), dim3(256), 0, s, hsrc, hnw, hoff, nh, items);
+            if (hash_heavy) {
+                PB_TRY((scan_exclusive<uint32_t, uint32_t>(hnw, hoff, nh, hoff + nh, ws)));
+                hipLaunchKernelGGL(k_heavy_expand, dim3(grid_for(nh)), dim3(256), 0, s, hsrc, hnw, hoff, nh, items);
+            }
             PB_TRY_HIP(hipGetLastError());
         }
 
         // 4. count ---------------------------------------------------------------
         Ranked G{roff, nbr, upoff, uprun, uplen, smid, isv, g->n_u, (uint32_t)n};
-        Acc A{gacc, vacc, sacc, &pc->flags, mode};
+        Acc A{gacc, vacc, sacc, sacc32, &pc->flags, mode};
         mark(1);
         if (nh > 0) {
-            if (opts.agg == PB_AGG_LDS_HASH)
-                hipLaunchKernelGGL((k_count_hash_win<256, 2 * HASH_WIN>), dim3(std::min(plan.items, MAX_ITEM_GRID)),
-                                   dim3(256), 0, s, G, A, (const uint2 *)items, plan.items, HASH_WIN);
+            if (hash_heavy)
+                launch_items(k_count_hash_win<256, 4, 2 * HASH_WIN>, plan.items, 256, s, G, A, (const uint2 *)items);
             else
-                launch_items(k_count_dense<1024, BIG_WIN>, plan.items, 1024, s, G, A, (const uint2 *)items);
+                launch_items(k_count_heavy<1024, 4>, nh, 1024, s, G, A, (const uint32_t *)hsrc, cur, nxt);
         }
         mark(2);
         if (plan.list[LIST_MEDIUM])
-            launch_items(k_count_hash<256, 2 * MEDIUM_D>, plan.list[LIST_MEDIUM], 256, s, G, A,
+            launch_items(k_count_hash<256, 4, 2 * MEDIUM_D>, plan.list[LIST_MEDIUM], 256, s, G, A,
                         (const uint32_t *)(lists + (uint64_t)LIST_MEDIUM * n));
         if (plan.list[LIST_SMALLDENSE])
-            launch_items(k_count_dense_src<256, SMALL_WIN>, plan.list[LIST_SMALLDENSE], 256, s, G, A,
+            launch_items(k_count_dense_src<256, 4, SMALL_WIN>, plan.list[LIST_SMALLDENSE], 256, s, G, A,
                         (const uint32_t *)(lists + (uint64_t)LIST_SMALLDENSE * n));
         if (plan.list[LIST_LIGHT])
-            launch_items(k_count_hash<64, 2 * LIGHT_D>, plan.list[LIST_LIGHT], 64, s, G, A,
+            launch_items(k_count_hash<64, 4, 2 * LIGHT_D>, plan.list[LIST_LIGHT], 64, s, G, A,
                         (const uint32_t *)(lists + (uint64_t)LIST_LIGHT * n));
         PB_TRY_HIP(hipGetLastError());
         mark(3);
@@ -645,7 +797,7 @@ pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, 
         // 5. outputs ---------------------------------------------------------------
         if (vout)
             hipLaunchKernelGGL(k_out_vertex, dim3(grid_for(n)), dim3(256), 0, s, rank, smid, vacc, n, vout);
-        if (eout) hipLaunchKernelGGL(k_out_edge, dim3(grid_for(m)), dim3(256), 0, s, eslot, sacc, m, eout);
+        if (eout) hipLaunchKernelGGL(k_out_edge, dim3(grid_for(m)), dim3(256), 0, s, eslot, sacc, sacc32, m, eout);
         if (opts.stats) {
             pb_stats &st = *opts.stats;
             st.wedges = wtotal;
@@ -654,7 +806,6 @@ pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, 
                               (opts.agg == PB_AGG_LDS_HASH ? nh : 0);
             st.sources_dense = plan.list[LIST_SMALLDENSE] + (opts.agg == PB_AGG_LDS_HASH ? 0 : nh);
             st.window_items = nh ? plan.items : 0;
-            const bool hash_heavy = opts.agg == PB_AGG_LDS_HASH;
             st.wedges_hash = plan.wedges[LIST_LIGHT] + plan.wedges[LIST_MEDIUM] +
                              (hash_heavy ? plan.wedges[LIST_HEAVY] : 0);
             st.wedges_dense = plan.wedges[LIST_SMALLDENSE] + (hash_heavy ? 0 : plan.wedges[LIST_HEAVY]);
