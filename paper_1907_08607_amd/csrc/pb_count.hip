@@ -130,6 +130,8 @@ constexpr uint32_t MEDIUM_D = 4096;   // distinct bound handled by the 256-threa
 constexpr uint32_t SMALL_WIN = 4096;  // dense range of the 256-thread whole-range dense kernel
 constexpr uint32_t WIN_WORDS = 32768; // 128 KB of LDS counters in the heavy kernel
 constexpr uint32_t HASH_WIN = 4096;   // candidate window of a forced-hash heavy item
+constexpr uint32_t SORT_LIGHT_W = 512;  // wedges sorted by the 1-wave sort kernel
+constexpr uint32_t SORT_W = 2048;       // wedges sorted by the 256-thread sort kernels
 
 struct PlanCounts {
     uint32_t list[NLISTS];
@@ -151,6 +153,7 @@ __global__ void k_plan(const uint32_t *upoff, const uint64_t *wscan, const uint3
         const uint64_t dist = w < range ? w : range;
         int which;
         if (agg == PB_AGG_DENSE_HIST) which = range <= SMALL_WIN ? LIST_SMALLDENSE : LIST_HEAVY;
+        else if (agg == PB_AGG_RADIX_SORT) which = w <= SORT_LIGHT_W ? LIST_LIGHT : w <= SORT_W ? LIST_MEDIUM : LIST_HEAVY;
         else if (dist <= LIGHT_D) which = LIST_LIGHT;
         else if (dist <= MEDIUM_D) which = LIST_MEDIUM;
         else which = LIST_HEAVY;
@@ -177,11 +180,12 @@ __global__ void k_heavy_keys(const uint32_t *nwin, const uint64_t *w, uint32_t n
     }
 }
 
-__global__ void k_heavy_gather(const uint32_t *perm, const uint32_t *heavy, const uint32_t *nwin, uint32_t nh,
-                               uint32_t *src_sorted, uint32_t *nwin_sorted) {
+__global__ void k_heavy_gather(const uint32_t *perm, const uint32_t *heavy, const uint32_t *nwin, const uint64_t *w,
+                               uint32_t nh, uint32_t *src_sorted, uint32_t *nwin_sorted, uint64_t *w_sorted) {
     GRID_STRIDE(i, (uint64_t)nh) {
         src_sorted[i] = heavy[perm[i]];
         nwin_sorted[i] = nwin[perm[i]];
+        w_sorted[i] = w[perm[i]];
     }
 }
 
@@ -208,6 +212,7 @@ struct Acc {
     uint32_t *s32;          // 2m, by slot, when every slot's credit fits 32 bits
     uint32_t *err;          // internal-consistency flag
     int mode;
+    __device__ int passes() const { return (mode & (MODE_VERTEX | MODE_EDGE)) ? 2 : 1; }
     __device__ void slot_add(uint32_t p, unsigned long long d) const {
         if (s32) atomicAdd(&s32[p], (uint32_t)d);
         else atomicAdd(&s[p], d);
@@ -254,6 +259,7 @@ struct DenseAgg {
         if (half) atomicAdd(&w[d >> 1], 1u << ((d & 1) << 4));
         else atomicAdd(&w[d], 1u);
     }
+    __device__ bool finalize() const { return true; }
     __device__ uint32_t count(uint32_t x) const {
         const uint32_t d = x - lo;
         if (d >= size) return 1u;
@@ -300,6 +306,7 @@ struct HashAgg {
         }
         atomicOr(err, FLAG_INTERNAL);
     }
+    __device__ bool finalize() const { return true; }
     __device__ uint32_t count(uint32_t x) const {
         uint32_t h = slot(x);
         for (int probe = 0; probe < CAP; ++probe) {
@@ -314,6 +321,120 @@ struct HashAgg {
             const uint32_t k = keys[i];
             if (k != EMPTY) f(k, cnts[i]);
         }
+    }
+};
+
+// Block-wide stable LSD radix sort of n 64-bit keys in LDS, 4 bits a pass
+// over bits [0, nbits) (nbits a multiple of 8, so the result ends in `a`).
+// Thread t owns the contiguous keys [t*S, (t+1)*S); its per-digit counts live
+// in column t of cnt[16][T]; one block scan over cnt (digit-major) turns them
+// into stable destinations.  Needs 16*T counters and T/WAVE+1 scan words.
+template <int T>
+__device__ void block_radix_sort(uint64_t *a, uint64_t *b, uint32_t n, int nbits, uint32_t *cnt, uint32_t *tmp) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t S = (n + T - 1) / T;
+    const uint32_t beg = tid * S < n ? tid * S : n, end = beg + S < n ? beg + S : n;
+    for (int shift = 0; shift < nbits; shift += 4) {
+#pragma unroll
+        for (int d = 0; d < 16; ++d) cnt[d * T + tid] = 0;
+        __syncthreads();
+        for (uint32_t i = beg; i < end; ++i) cnt[((a[i] >> shift) & 15u) * T + tid] += 1;
+        __syncthreads();
+        uint32_t v[16], sum = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            v[j] = cnt[16 * tid + j];
+            sum += v[j];
+        }
+        uint32_t total;
+        uint32_t run = block_exclusive_sum<T>(sum, tmp, &total);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            cnt[16 * tid + j] = run;
+            run += v[j];
+        }
+        __syncthreads();
+        for (uint32_t i = beg; i < end; ++i) {
+            const uint64_t key = a[i];
+            const uint32_t slot = ((key >> shift) & 15u) * T + tid;
+            b[cnt[slot]] = key;
+            cnt[slot] += 1;
+        }
+        __syncthreads();
+        uint64_t *t = a;
+        a = b;
+        b = t;
+    }
+}
+
+// Sort-based aggregation (GET-FREQ by sorting, Section 3.1.2): the wedges'
+// keys x2 - lo are appended to an LDS buffer, radix-sorted, and each run of
+// equal keys gives one endpoint pair and its count R.  A window of width 1
+// needs no keys (every wedge has the same x2).  Over CAP keys the item is
+// refused (finalize() returns false) and the caller narrows the window.
+template <int T, int CAP>
+struct SortAgg {
+    uint64_t *a, *b;   // CAP keys each; after finalize b holds the distinct keys
+    uint32_t *cnt;     // 16*T >= CAP: sort counters, then the count of each distinct key
+    uint32_t *start;   // CAP: first sorted position of each distinct key
+    uint32_t *meta;    // [0] keys appended, [1] distinct keys
+    uint32_t *tmp;     // T/WAVE + 1
+    uint32_t lo, width;
+    __device__ void init() const {
+        if (threadIdx.x == 0) { meta[0] = 0; meta[1] = 0; }
+    }
+    __device__ void insert(uint32_t x) const {
+        const uint64_t act = __ballot(1);
+        const uint32_t lane = threadIdx.x & (WAVE - 1);
+        const uint32_t leader = __ffsll((unsigned long long)act) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&meta[0], (uint32_t)__popcll(act));
+        base = __shfl(base, leader, WAVE);
+        const uint32_t idx = base + (uint32_t)__popcll(act & lanemask_lt());
+        if (width > 1 && idx < CAP) a[idx] = x - lo;
+    }
+    __device__ bool finalize() const {
+        __syncthreads();
+        const uint32_t n = meta[0];
+        __syncthreads();  // everyone has n before anyone may return and re-init
+        if (width == 1) {  // one candidate: R = number of wedges
+            if (threadIdx.x == 0 && n) { b[0] = 0; cnt[0] = n; meta[1] = 1; }
+            __syncthreads();
+            return true;
+        }
+        if (n > CAP) return false;  // every thread read the same n
+        int bits = 0;
+        while (bits < 32 && ((width - 1) >> bits)) ++bits;
+        bits = (bits + 7) & ~7;
+        block_radix_sort<T>(a, b, n, bits, cnt, tmp);
+        // distinct keys: thread-contiguous segments, flags scanned
+        const uint32_t tid = threadIdx.x, S = (n + T - 1) / T;
+        const uint32_t beg = tid * S < n ? tid * S : n, end = beg + S < n ? beg + S : n;
+        uint32_t heads = 0;
+        for (uint32_t i = beg; i < end; ++i) heads += (i == 0 || a[i] != a[i - 1]);
+        uint32_t nu;
+        uint32_t u = block_exclusive_sum<T>(heads, tmp, &nu);
+        for (uint32_t i = beg; i < end; ++i)
+            if (i == 0 || a[i] != a[i - 1]) { b[u] = a[i]; start[u] = i; ++u; }
+        __syncthreads();
+        for (uint32_t j = tid; j < nu; j += T) cnt[j] = (j + 1 < nu ? start[j + 1] : n) - start[j];
+        if (tid == 0) meta[1] = nu;
+        __syncthreads();
+        return true;
+    }
+    __device__ uint32_t count(uint32_t x) const {
+        const uint64_t key = width > 1 ? (uint64_t)(x - lo) : 0;
+        uint32_t l = 0, h = meta[1];
+        while (h - l > 1) {
+            const uint32_t mid = (l + h) >> 1;
+            if (b[mid] <= key) l = mid; else h = mid;
+        }
+        return cnt[l];
+    }
+    template <class F>
+    __device__ void for_each(F f) const {
+        const uint32_t nu = meta[1];
+        for (uint32_t j = threadIdx.x; j < nu; j += T) f(lo + (uint32_t)b[j], cnt[j]);
     }
 };
 
@@ -394,14 +515,14 @@ __device__ inline uint32_t last_le(const uint32_t *off, uint32_t lo, uint32_t n,
 // (at most 64) runs they touch one per lane, and a lane finds its run with a
 // 6-step shuffle search.
 template <int T, int U, class Agg, class Range>
-__device__ void count_item(const Ranked &G, const Acc &A, uint32_t r, const Agg &agg, const Range &range,
-                           RunShared<T> &sh) {
+__device__ bool count_item(const Ranked &G, const Acc &A, uint32_t r, const Agg &agg, const Range &range,
+                           RunShared<T> &sh, int passes) {
     const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
     const uint32_t k0 = G.upoff[r], k1 = G.upoff[r + 1];
     agg.init();
     __syncthreads();
-    const int passes = (A.mode & (MODE_VERTEX | MODE_EDGE)) ? 2 : 1;
     const bool edge = A.mode & MODE_EDGE;
+    const bool credit = A.mode & (MODE_VERTEX | MODE_EDGE);
     for (int pass = 1; pass <= passes; ++pass) {
         for (uint32_t c = k0; c < k1; c += T) {
             const uint32_t k = c + tid;
@@ -426,7 +547,8 @@ __device__ void count_item(const Ranked &G, const Acc &A, uint32_t r, const Agg 
             __syncthreads();
             // runs i0 .. i0+63 held one per lane: o = flat start, bg = slot
             uint32_t i0 = 0, o = 0, bg = 0, o_end = 0;
-            for (uint32_t wb = wv * (U * WAVE); wb < total; wb += T * U) {
+            const uint32_t walk = pass == 1 || credit ? total : 0u;
+            for (uint32_t wb = wv * (U * WAVE); wb < walk; wb += T * U) {
                 uint32_t pidx[U], rel[U], xs[U];
                 bool ok[U];
 #pragma unroll
@@ -497,6 +619,7 @@ __device__ void count_item(const Ranked &G, const Acc &A, uint32_t r, const Agg 
             __syncthreads();
         }
         if (pass == 1) {
+            if (!agg.finalize()) return false;  // (uniform) capacity exceeded: caller retries
             unsigned long long local = 0;
             const bool vert = A.mode & MODE_VERTEX;
             agg.for_each([&](uint32_t key, uint32_t cc) {
@@ -515,6 +638,7 @@ __device__ void count_item(const Ranked &G, const Acc &A, uint32_t r, const Agg 
         }
     }
     __syncthreads();
+    return true;
 }
 
 template <int T, int U, int CAP>
@@ -524,7 +648,7 @@ __global__ __launch_bounds__(T) void k_count_hash(Ranked G, Acc A, const uint32_
     __shared__ RunShared<T> sh;
     HashAgg<T, CAP> agg{keys, cnts, A.err};
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x)
-        count_item<T, U>(G, A, list[i], agg, FullRange{}, sh);
+        count_item<T, U>(G, A, list[i], agg, FullRange{}, sh, A.passes());
 }
 
 // Hash over a candidate window of at most CAP/2 ids (forced hash on heavy
@@ -541,7 +665,7 @@ __global__ __launch_bounds__(T) void k_count_hash_win(Ranked G, Acc A, const uin
         const uint32_t side_end = G.isv[r] ? G.n : G.n_u;
         const uint32_t lo = G.smid[r] + 1 + w * HASH_WIN;
         const uint32_t hi = side_end - lo > HASH_WIN ? lo + HASH_WIN : side_end;
-        count_item<T, U>(G, A, r, agg, SearchRange{lo, hi}, sh);
+        count_item<T, U>(G, A, r, agg, SearchRange{lo, hi}, sh, A.passes());
     }
 }
 
@@ -565,9 +689,65 @@ __global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32
         while (hi > lo_min) {
             const uint32_t lo = hi - lo_min > ws ? hi - ws : lo_min;
             DenseAgg<T> agg{words, lo, hi - lo, half, A.err};
-            count_item<T, U>(G, A, r, agg, CursorRange{cur, nxt, lo, first, two_pass}, sh);
+            count_item<T, U>(G, A, r, agg, CursorRange{cur, nxt, lo, first, two_pass}, sh, A.passes());
             hi = lo;
             first = false;
+        }
+    }
+}
+
+template <int T, int CAP>
+struct SortShared {
+    uint64_t a[CAP], b[CAP];
+    uint32_t cnt[16 * T];
+    uint32_t start[CAP];
+    uint32_t meta[2];
+    uint32_t tmp[T / WAVE + 1];
+};
+
+// Sort aggregation of whole sources with at most CAP wedges.
+template <int T, int U, int CAP>
+__global__ __launch_bounds__(T) void k_count_sort(Ranked G, Acc A, const uint32_t *list, uint32_t count) {
+    static_assert(16 * T >= CAP, "count array too small");
+    __shared__ SortShared<T, CAP> ss;
+    __shared__ RunShared<T> sh;
+    for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const uint32_t r = list[i];
+        const uint32_t lo = G.smid[r] + 1, side_end = G.isv[r] ? G.n : G.n_u;
+        SortAgg<T, CAP> agg{ss.a, ss.b, ss.cnt, ss.start, ss.meta, ss.tmp, lo, side_end - lo};
+        if (!count_item<T, U>(G, A, r, agg, FullRange{}, sh, A.passes())) atomicOr(A.err, FLAG_INTERNAL);
+    }
+}
+
+// Sort aggregation of larger sources: windows of the candidate range from the
+// top, each first tried at a width that should hold about CAP/2 wedges and
+// halved while its wedges exceed CAP.  The cursors only advance once a window
+// has been counted (two passes always, so a refused window leaves them as
+// they were).
+template <int T, int U, int CAP>
+__global__ __launch_bounds__(T) void k_count_sort_heavy(Ranked G, Acc A, const uint32_t *list, const uint64_t *wsrc,
+                                                        uint32_t *cur, uint32_t *nxt, uint32_t count) {
+    static_assert(16 * T >= CAP, "count array too small");
+    __shared__ SortShared<T, CAP> ss;
+    __shared__ RunShared<T> sh;
+    for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const uint32_t r = list[i];
+        const uint32_t lo_min = G.smid[r] + 1;
+        uint32_t hi = G.isv[r] ? G.n : G.n_u;
+        const uint64_t w = wsrc[i] ? wsrc[i] : 1;
+        uint64_t guess = (uint64_t)(hi - lo_min) * (CAP / 2) / w;
+        uint32_t width = guess < 1 ? 1u : guess > hi - lo_min ? hi - lo_min : (uint32_t)guess;
+        bool first = true;
+        while (hi > lo_min) {
+            const uint32_t lo = hi - lo_min > width ? hi - width : lo_min;
+            SortAgg<T, CAP> agg{ss.a, ss.b, ss.cnt, ss.start, ss.meta, ss.tmp, lo, hi - lo};
+            if (!count_item<T, U>(G, A, r, agg, CursorRange{cur, nxt, lo, first, true}, sh, 2)) {
+                width = (hi - lo) / 2 ? (hi - lo) / 2 : 1u;
+                continue;
+            }
+            hi = lo;
+            first = false;
+            width = width < 0x40000000u ? 2 * width : width;  // try wider again
         }
     }
 }
@@ -582,7 +762,7 @@ __global__ __launch_bounds__(T) void k_count_dense_src(Ranked G, Acc A, const ui
         const uint32_t side_end = G.isv[r] ? G.n : G.n_u;
         const uint32_t lo = G.smid[r] + 1;
         DenseAgg<T> agg{words, lo, side_end - lo, false, A.err};
-        count_item<T, U>(G, A, r, agg, FullRange{}, sh);
+        count_item<T, U>(G, A, r, agg, FullRange{}, sh, A.passes());
     }
 }
 
@@ -621,7 +801,6 @@ pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, 
     if (opts_in) opts = *opts_in;
     if ((int)opts.agg < PB_AGG_AUTO || (int)opts.agg > PB_AGG_RADIX_SORT) return PB_ERR_INVALID_ARG;
     if ((int)opts.hub < PB_HUB_AUTO || (int)opts.hub > PB_HUB_FORCE) return PB_ERR_INVALID_ARG;
-    if (opts.agg == PB_AGG_RADIX_SORT) return PB_ERR_INVALID_ARG;  // not available in this build
     const int mode = (gout ? MODE_GLOBAL : 0) | (vout ? MODE_VERTEX : 0) | (eout ? MODE_EDGE : 0);
     const uint64_t n = (uint64_t)g->n_u + g->n_v, m = g->m, ns = 2 * m;
     // per-chunk wedge offsets are 32-bit: 1024 runs of at most max_deg each
@@ -744,13 +923,16 @@ pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, 
         // heavy sources, most wedges first (forced hash: their windows)
         const uint32_t nh = plan.list[LIST_HEAVY];
         const bool hash_heavy = opts.agg == PB_AGG_LDS_HASH;
+        const bool sort = opts.agg == PB_AGG_RADIX_SORT;
         uint2 *items = nullptr;
         uint32_t *hsrc = nullptr, *cur = nullptr, *nxt = nullptr;
+        uint64_t *hw = nullptr;
         if (nh > 0) {
             uint64_t *hk0 = ws.alloc<uint64_t>(nh), *hk1 = ws.alloc<uint64_t>(nh);
             uint32_t *hv0 = ws.alloc<uint32_t>(nh), *hv1 = ws.alloc<uint32_t>(nh);
             uint32_t *hnw = ws.alloc<uint32_t>(nh), *hoff = ws.alloc<uint32_t>(nh + 1);
             hsrc = ws.alloc<uint32_t>(nh);
+            hw = ws.alloc<uint64_t>(nh);
             if (hash_heavy) items = ws.alloc<uint2>(plan.items);
             else {
                 cur = ws.alloc<uint32_t>(m);
@@ -762,8 +944,8 @@ pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, 
             uint64_t *hks;
             uint32_t *hvs;
             PB_TRY(radix_sort_pairs(hk0, hv0, hk1, hv1, nh, 32, ws, &hks, &hvs));
-            hipLaunchKernelGGL(k_heavy_gather, dim3(grid_for(nh)), dim3(256), 0, s, hvs, heavy, heavy_nwin, nh, hsrc,
-                               hnw);
+            hipLaunchKernelGGL(k_heavy_gather, dim3(grid_for(nh)), dim3(256), 0, s, hvs, heavy, heavy_nwin, heavy_w, nh,
+                               hsrc, hnw, hw);
             if (hash_heavy) {
                 PB_TRY((scan_exclusive<uint32_t, uint32_t>(hnw, hoff, nh, hoff + nh, ws)));
                 hipLaunchKernelGGL(k_heavy_expand, dim3(grid_for(nh)), dim3(256), 0, s, hsrc, hnw, hoff, nh, items);
@@ -778,17 +960,26 @@ pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, 
         if (nh > 0) {
             if (hash_heavy)
                 launch_items(k_count_hash_win<256, 4, 2 * HASH_WIN>, plan.items, 256, s, G, A, (const uint2 *)items);
+            else if (sort)
+                launch_items(k_count_sort_heavy<256, 4, SORT_W>, nh, 256, s, G, A, (const uint32_t *)hsrc,
+                             (const uint64_t *)hw, cur, nxt);
             else
                 launch_items(k_count_heavy<1024, 4>, nh, 1024, s, G, A, (const uint32_t *)hsrc, cur, nxt);
         }
         mark(2);
-        if (plan.list[LIST_MEDIUM])
+        if (plan.list[LIST_MEDIUM] && sort)
+            launch_items(k_count_sort<256, 4, SORT_W>, plan.list[LIST_MEDIUM], 256, s, G, A,
+                         (const uint32_t *)(lists + (uint64_t)LIST_MEDIUM * n));
+        else if (plan.list[LIST_MEDIUM])
             launch_items(k_count_hash<256, 4, 2 * MEDIUM_D>, plan.list[LIST_MEDIUM], 256, s, G, A,
                         (const uint32_t *)(lists + (uint64_t)LIST_MEDIUM * n));
         if (plan.list[LIST_SMALLDENSE])
             launch_items(k_count_dense_src<256, 4, SMALL_WIN>, plan.list[LIST_SMALLDENSE], 256, s, G, A,
                         (const uint32_t *)(lists + (uint64_t)LIST_SMALLDENSE * n));
-        if (plan.list[LIST_LIGHT])
+        if (plan.list[LIST_LIGHT] && sort)
+            launch_items(k_count_sort<64, 4, SORT_LIGHT_W>, plan.list[LIST_LIGHT], 64, s, G, A,
+                         (const uint32_t *)(lists + (uint64_t)LIST_LIGHT * n));
+        else if (plan.list[LIST_LIGHT])
             launch_items(k_count_hash<64, 4, 2 * LIGHT_D>, plan.list[LIST_LIGHT], 64, s, G, A,
                         (const uint32_t *)(lists + (uint64_t)LIST_LIGHT * n));
         PB_TRY_HIP(hipGetLastError());
@@ -802,13 +993,15 @@ pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, 
             pb_stats &st = *opts.stats;
             st.wedges = wtotal;
             st.sources = plan.sources;
-            st.sources_hash = plan.list[LIST_LIGHT] + plan.list[LIST_MEDIUM] +
-                              (opts.agg == PB_AGG_LDS_HASH ? nh : 0);
-            st.sources_dense = plan.list[LIST_SMALLDENSE] + (opts.agg == PB_AGG_LDS_HASH ? 0 : nh);
+            st.sources_hash = sort ? 0 : plan.list[LIST_LIGHT] + plan.list[LIST_MEDIUM] + (hash_heavy ? nh : 0);
+            st.sources_dense = plan.list[LIST_SMALLDENSE] + (hash_heavy || sort ? 0 : nh);
             st.window_items = nh ? plan.items : 0;
-            st.wedges_hash = plan.wedges[LIST_LIGHT] + plan.wedges[LIST_MEDIUM] +
-                             (hash_heavy ? plan.wedges[LIST_HEAVY] : 0);
-            st.wedges_dense = plan.wedges[LIST_SMALLDENSE] + (hash_heavy ? 0 : plan.wedges[LIST_HEAVY]);
+            const uint64_t wl = plan.wedges[LIST_LIGHT] + plan.wedges[LIST_MEDIUM];
+            const uint32_t sl = plan.list[LIST_LIGHT] + plan.list[LIST_MEDIUM];
+            st.wedges_hash = sort ? 0 : wl + (hash_heavy ? plan.wedges[LIST_HEAVY] : 0);
+            st.wedges_dense = plan.wedges[LIST_SMALLDENSE] + (hash_heavy || sort ? 0 : plan.wedges[LIST_HEAVY]);
+            st.wedges_sort = sort ? wl + plan.wedges[LIST_HEAVY] : 0;
+            st.sources_sort = sort ? sl + nh : 0;
         }
     } else {
         if (vout) PB_TRY(fill<int64_t>(vout, 0, n, s));
@@ -828,6 +1021,8 @@ pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, 
         opts.stats->ms_prepare = t[0];
         if (opts.agg == PB_AGG_LDS_HASH) {
             opts.stats->ms_hash = t[1] + t[2];
+        } else if (opts.agg == PB_AGG_RADIX_SORT) {
+            opts.stats->ms_sort = t[1] + t[2];
         } else {
             opts.stats->ms_dense = t[1];
             opts.stats->ms_hash = t[2];

@@ -1,0 +1,69 @@
+"""Writes the expected values for the full-size parity tests.
+
+Calls only the CPU oracle (oracle/) and the seeded input generators; no value
+here comes from the GPU library.  For each workload it records the CSR hash
+(so a test can confirm it regenerated the same graph), the butterfly total,
+SHA-256 digests of the per-vertex and per-edge int64 arrays (little endian),
+the wedge count of the workload's ordering, and a sample of single values.
+
+    python tests/golden/make_golden.py powerlaw_50m hub_100m
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_1907_08607_amd import graphgen as gg  # noqa: E402
+
+WORKLOADS = {
+    "powerlaw_50m": (lambda: gg.workload_powerlaw_50m(seed=2), "degree",
+                     "Chung-Lu power law, |U|=2M, |V|=500k, m=50M, exponent 2.1, max weight 50k, seed 2"),
+    "hub_100m": (lambda: gg.workload_hub_100m(seed=3), "approx_codeg",
+                 "hub-skewed, |U|=20M, |V|=100k, m=100M, V power law 1.8 up to 1M, U geometric mean 5, seed 3"),
+}
+
+
+def digest(a: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<i8").tobytes()).hexdigest()
+
+
+def make(name: str) -> dict:
+    make_graph, rank_kind, desc = WORKLOADS[name]
+    t = time.time()
+    g = make_graph()
+    print(f"{name}: generated in {time.time() - t:.1f}s", flush=True)
+    t = time.time()
+    glob, vert, edge = oracle.count(g)
+    print(f"{name}: oracle counts in {time.time() - t:.1f}s", flush=True)
+    t = time.time()
+    rank = oracle.rank(g, rank_kind)
+    wedges = oracle.wedges(g, rank)
+    print(f"{name}: ranking + wedges in {time.time() - t:.1f}s", flush=True)
+    rng = np.random.default_rng(12345)
+    vs = sorted(set(rng.integers(0, g.n, 64).tolist()) | {int(np.argmax(vert))})
+    es = sorted(set(rng.integers(0, g.m, 64).tolist()) | {int(np.argmax(edge))})
+    return {
+        "workload": name, "description": desc, "csr_sha256": g.sha256(),
+        "n_u": g.n_u, "n_v": g.n_v, "m": g.m, "rank": rank_kind, "rank_sha256": digest(rank.astype(np.int64)),
+        "wedges": wedges, "global": glob, "vertex_sha256": digest(vert), "edge_sha256": digest(edge),
+        "vertex_sum": int(vert.sum()), "edge_sum": int(edge.sum()),
+        "vertex_samples": {str(x): int(vert[x]) for x in vs},
+        "edge_samples": {str(e): int(edge[e]) for e in es},
+        "made_by": "tests/golden/make_golden.py (oracle/orc_count, orc_rank, orc_wedges)",
+    }
+
+
+if __name__ == "__main__":
+    for name in sys.argv[1:] or list(WORKLOADS):
+        d = make(name)
+        with open(os.path.join(HERE, f"{name}.json"), "w") as f:
+            json.dump(d, f, indent=1)
+        print(json.dumps({k: d[k] for k in ("workload", "global", "wedges", "m")}), flush=True)

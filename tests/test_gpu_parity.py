@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 KINDS = ["side_auto", "side_u", "side_v", "degree", "approx_degree", "codeg", "approx_codeg"]
-AGGS = ["auto", "hash", "dense"]
+AGGS = ["auto", "hash", "dense", "sort"]
 
 
 @pytest.fixture(scope="module", autouse=True)
