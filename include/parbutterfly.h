@@ -138,13 +138,30 @@ typedef struct {
 /* opts.flags bits */
 #define PB_FLAG_TIMING 1u
 
+/* Per-bucket choices of the AUTO aggregation policy.  Sources are bucketed by
+ * the bound min(W(x1), candidate range) on their distinct endpoints (W = the
+ * source's wedges): light (<= light_max, at most 512), medium (<= medium_max,
+ * at most 4096) and heavy (the rest).  Each bucket names its aggregator:
+ * light and medium take PB_AGG_LDS_HASH, PB_AGG_RADIX_SORT or
+ * PB_AGG_DENSE_HIST; heavy takes any of the three.  pb_autotune fills one
+ * from timed runs; opts.tuning = NULL uses the built-in table (hash, hash,
+ * dense; 512; 4096). */
 typedef struct {
-    pb_agg agg;
+    uint32_t light_max;
+    uint32_t medium_max;
+    pb_agg light_agg;
+    pb_agg medium_agg;
+    pb_agg heavy_agg;
+} pb_tuning;
+
+typedef struct {
+    pb_agg agg;                   /* AUTO: per-bucket table; others: forced for every source */
     pb_hub_mode hub;
     uint64_t workspace_cap_bytes; /* 0: no cap beyond the device's free memory */
     uint32_t wg_size;             /* reserved, 0 */
     uint32_t flags;               /* PB_FLAG_* bits, 0 for none */
     pb_stats *stats;              /* optional host pointer, filled by the call */
+    const pb_tuning *tuning;      /* optional: the AUTO table, NULL = built-in */
 } pb_opts;
 
 typedef struct pb_graph pb_graph;
@@ -199,6 +216,33 @@ pb_status pb_count_vertex(pb_graph *g, const uint32_t *rank, const pb_opts *opts
 /* Per-edge counts alone (Algorithm 4, COUNT-E). */
 pb_status pb_count_edge(pb_graph *g, const uint32_t *rank, const pb_opts *opts, int64_t *out,
                         hipStream_t stream);
+
+/* Batched counting: `count` independent graphs in one pass of the pipeline.
+ * The batch is counted as the disjoint union of the graphs (no wedge spans two
+ * graphs), so relabelling, planning and each counting kernel run as single
+ * launches over the work items of every graph; counts are identical to
+ * counting each graph alone.  graphs[i] and ranks[i] (device, n_i entries, a
+ * permutation of [0, n_i)) as for pb_count; each output array is a host array
+ * of `count` device pointers (or NULL when that output is not wanted; at
+ * least one wanted): global_outs[i] -> int64[1], vertex_outs[i] ->
+ * int64[n_i], edge_outs[i] -> int64[m_i].  opts->stats, if given, sums the
+ * batch.  Synchronises `stream` like pb_count.
+ * Errors: INVALID_ARG (also when the summed sizes exceed the pb_count limits),
+ * BAD_RANK, NO_MEMORY, HIP. */
+pb_status pb_count_batched(pb_graph *const *graphs, const uint32_t *const *ranks, uint32_t count,
+                           const pb_opts *opts, int64_t *const *global_outs, int64_t *const *vertex_outs,
+                           int64_t *const *edge_outs, hipStream_t stream);
+
+/* Chooses the per-bucket aggregators (and bucket thresholds) of the AUTO
+ * policy by timing whole batched counts of the given sample graphs under each
+ * candidate, one bucket at a time (the others held at the current best),
+ * `repeats` runs each, fastest median kept.  Writes the table to *out; counts
+ * are exact under every candidate, so the table only affects speed.  The
+ * timed counts produce the global and per-edge outputs.  Synchronises
+ * `stream`.
+ * Errors: as pb_count_batched. */
+pb_status pb_autotune(pb_graph *const *graphs, const uint32_t *const *ranks, uint32_t count, const pb_opts *opts,
+                      uint32_t repeats, pb_tuning *out, hipStream_t stream);
 
 #ifdef __cplusplus
 }

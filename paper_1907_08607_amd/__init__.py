@@ -54,10 +54,20 @@ class pb_stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class pb_tuning(ctypes.Structure):
+    _fields_ = [("light_max", ctypes.c_uint32), ("medium_max", ctypes.c_uint32), ("light_agg", ctypes.c_int),
+                ("medium_agg", ctypes.c_int), ("heavy_agg", ctypes.c_int)]
+
+    def as_dict(self):
+        names = {v: k for k, v in AGGS.items()}
+        return {"light_max": self.light_max, "medium_max": self.medium_max, "light_agg": names[self.light_agg],
+                "medium_agg": names[self.medium_agg], "heavy_agg": names[self.heavy_agg]}
+
+
 class pb_opts(ctypes.Structure):
     _fields_ = [("agg", ctypes.c_int), ("hub", ctypes.c_int), ("workspace_cap_bytes", ctypes.c_uint64),
                 ("wg_size", ctypes.c_uint32), ("flags", ctypes.c_uint32),
-                ("stats", ctypes.POINTER(pb_stats))]
+                ("stats", ctypes.POINTER(pb_stats)), ("tuning", ctypes.POINTER(pb_tuning))]
 
 
 _lib = None
@@ -89,6 +99,12 @@ def load_library():
         fn = getattr(lib, name)
         fn.argtypes = [P, P, ctypes.POINTER(pb_opts), P, P]
         fn.restype = ctypes.c_int
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    lib.pb_count_batched.argtypes = [PP, PP, ctypes.c_uint32, ctypes.POINTER(pb_opts), PP, PP, PP, P]
+    lib.pb_count_batched.restype = ctypes.c_int
+    lib.pb_autotune.argtypes = [PP, PP, ctypes.c_uint32, ctypes.POINTER(pb_opts), ctypes.c_uint32,
+                                ctypes.POINTER(pb_tuning), P]
+    lib.pb_autotune.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -174,11 +190,13 @@ class Graph:
         return cls(csr.n_u, csr.n_v, off, adj, stream)
 
 
-def make_opts(agg="auto", hub="auto", workspace_cap=0, stats=None, timing=False) -> pb_opts:
+def make_opts(agg="auto", hub="auto", workspace_cap=0, stats=None, timing=False, tuning=None) -> pb_opts:
     o = pb_opts()
     load_library().pb_opts_default(ctypes.byref(o))
     if timing:
         o.flags |= PB_FLAG_TIMING
+    if tuning is not None:
+        o.tuning = ctypes.pointer(tuning)
     o.agg = AGGS[agg] if isinstance(agg, str) else int(agg)
     o.hub = HUBS[hub] if isinstance(hub, str) else int(hub)
     o.workspace_cap_bytes = int(workspace_cap)
@@ -198,7 +216,7 @@ def pb_rank(g: Graph, kind="degree", out=None, stream=None):
 
 
 def pb_count(g: Graph, rank, want_global=True, want_vertex=True, want_edge=True, agg="auto", hub="auto",
-             workspace_cap=0, stats: pb_stats | None = None, outs=None, stream=None, timing=False):
+             workspace_cap=0, stats: pb_stats | None = None, outs=None, stream=None, timing=False, tuning=None):
     """(global int64 tensor[1] or None, per-vertex int64[n] or None, per-edge int64[m] or None)."""
     torch = _torch()
     if outs is None:
@@ -206,7 +224,7 @@ def pb_count(g: Graph, rank, want_global=True, want_vertex=True, want_edge=True,
                 torch.empty(g.n, dtype=torch.int64, device="cuda") if want_vertex else None,
                 torch.empty(g.m, dtype=torch.int64, device="cuda") if want_edge else None)
     gout, vout, eout = outs
-    opts = make_opts(agg, hub, workspace_cap, stats, timing)
+    opts = make_opts(agg, hub, workspace_cap, stats, timing, tuning)
     ptr = lambda t, name: None if t is None else _dev_ptr(t, torch.int64, name)
     _check(load_library().pb_count(g.handle, _dev_ptr(rank, torch.int32, "rank"), ctypes.byref(opts),
                                    ptr(gout, "global_out"), ptr(vout, "vertex_out"), ptr(eout, "edge_out"),
@@ -233,3 +251,44 @@ def pb_count_vertex(g, rank, agg="auto", hub="auto", workspace_cap=0, stats=None
 
 def pb_count_edge(g, rank, agg="auto", hub="auto", workspace_cap=0, stats=None, stream=None):
     return _single("pb_count_edge", g, rank, g.m, agg, hub, workspace_cap, stats, stream)
+
+
+def _ptr_array(items):
+    arr = (ctypes.c_void_p * len(items))()
+    for i, x in enumerate(items):
+        arr[i] = x
+    return arr
+
+
+def pb_count_batched(graphs, ranks, want_global=True, want_vertex=False, want_edge=True, agg="auto", hub="auto",
+                     stats: pb_stats | None = None, tuning=None, outs=None, stream=None, timing=False):
+    """Counts a batch of graphs in one pass; returns per-graph (global, vertex, edge) lists."""
+    torch = _torch()
+    k = len(graphs)
+    if k != len(ranks) or k == 0:
+        raise ValueError("graphs and ranks must be non-empty and of equal length")
+    if outs is None:
+        outs = ([torch.empty(1, dtype=torch.int64, device="cuda") for _ in graphs] if want_global else None,
+                [torch.empty(g.n, dtype=torch.int64, device="cuda") for g in graphs] if want_vertex else None,
+                [torch.empty(max(g.m, 1), dtype=torch.int64, device="cuda") for g in graphs] if want_edge else None)
+    arrs = [None if o is None else _ptr_array([t.data_ptr() for t in o]) for o in outs]
+    gp = _ptr_array([g.handle.value for g in graphs])
+    rp = _ptr_array([_dev_ptr(r, torch.int32, "rank").value for r in ranks])
+    opts = make_opts(agg, hub, 0, stats, timing, tuning)
+    cast = lambda a: None if a is None else ctypes.cast(a, ctypes.POINTER(ctypes.c_void_p))
+    _check(load_library().pb_count_batched(cast(gp), cast(rp), k, ctypes.byref(opts), cast(arrs[0]), cast(arrs[1]),
+                                           cast(arrs[2]), _stream(stream)), "pb_count_batched")
+    return outs
+
+
+def pb_autotune(graphs, ranks, repeats=3, agg="auto", stream=None) -> pb_tuning:
+    """Per-bucket aggregator table for the AUTO policy, timed on these graphs."""
+    torch = _torch()
+    gp = _ptr_array([g.handle.value for g in graphs])
+    rp = _ptr_array([_dev_ptr(r, torch.int32, "rank").value for r in ranks])
+    out = pb_tuning()
+    opts = make_opts(agg)
+    cast = lambda a: ctypes.cast(a, ctypes.POINTER(ctypes.c_void_p))
+    _check(load_library().pb_autotune(cast(gp), cast(rp), len(graphs), ctypes.byref(opts), int(repeats),
+                                      ctypes.byref(out), _stream(stream)), "pb_autotune")
+    return out

@@ -123,54 +123,80 @@ __global__ void k_upslots(const uint64_t *keys, const uint32_t *vals, uint64_t n
 
 // ---------------------------------------------------------------- plan
 
-enum : int { LIST_LIGHT = 0, LIST_MEDIUM = 1, LIST_HEAVY = 2, LIST_SMALLDENSE = 3, NLISTS = 4 };
+// Work lists: every source with wedges goes to exactly one.
+enum : int {
+    L_HASH_LIGHT = 0,  // 1-wave LDS hash, distinct bound <= 512
+    L_HASH_MEDIUM,     // 256-thread LDS hash, distinct bound <= 4096
+    L_HASH_WIN,        // 256-thread LDS hash over candidate windows of HASH_WIN ids
+    L_SORT_LIGHT,      // 1-wave LDS radix sort, <= 512 wedges
+    L_SORT_MEDIUM,     // 256-thread LDS radix sort, <= 2048 wedges
+    L_SORT_HEAVY,      // 256-thread LDS radix sort over candidate windows
+    L_DENSE_HEAVY,     // 1024-thread dense LDS windows swept with cursors
+    L_DENSE_SMALL,     // 256-thread dense counters, candidate range <= 4096
+    NLISTS
+};
+constexpr int NSORTED = 3;  // lists dispatched most-wedges-first
+__host__ __device__ inline int sorted_slot(int list) {
+    return list == L_HASH_WIN ? 0 : list == L_SORT_HEAVY ? 1 : list == L_DENSE_HEAVY ? 2 : -1;
+}
 
-constexpr uint32_t LIGHT_D = 512;     // distinct bound handled by the 1-wave hash (1024 slots)
-constexpr uint32_t MEDIUM_D = 4096;   // distinct bound handled by the 256-thread hash (8192 slots)
-constexpr uint32_t SMALL_WIN = 4096;  // dense range of the 256-thread whole-range dense kernel
-constexpr uint32_t WIN_WORDS = 32768; // 128 KB of LDS counters in the heavy kernel
-constexpr uint32_t HASH_WIN = 4096;   // candidate window of a forced-hash heavy item
+constexpr uint32_t LIGHT_D = 512;       // 1-wave hash: 1024 slots
+constexpr uint32_t MEDIUM_D = 4096;     // 256-thread hash: 8192 slots
+constexpr uint32_t SMALL_WIN = 4096;    // dense range of the 256-thread whole-range dense kernel
+constexpr uint32_t WIN_WORDS = 32768;   // 128 KB of LDS counters in the heavy dense kernel
+constexpr uint32_t HASH_WIN = 4096;     // candidate window of a hash item over a heavy source
 constexpr uint32_t SORT_LIGHT_W = 512;  // wedges sorted by the 1-wave sort kernel
 constexpr uint32_t SORT_W = 2048;       // wedges sorted by the 256-thread sort kernels
 
+// Aggregator per bucket of the distinct-endpoint bound (light, medium, heavy).
+struct Policy {
+    uint32_t light_max, medium_max;
+    int agg[3];
+};
+
 struct PlanCounts {
     uint32_t list[NLISTS];
-    uint32_t items;  // forced-hash heavy (source, window) items
+    uint32_t items;  // hash (source, window) items
     uint32_t flags;
     unsigned long long sources;
     unsigned long long wedges[NLISTS];
 };
 
-__global__ void k_plan(const uint32_t *upoff, const uint64_t *wscan, const uint32_t *smid, const uint32_t *isv,
-                       uint64_t n, uint32_t n_u, int agg, uint32_t *lists, uint32_t *heavy_nwin,
-                       uint64_t *heavy_w, PlanCounts *pc) {
+__global__ void k_plan(const uint32_t *upoff, const uint64_t *wscan, const uint32_t *smid, const uint32_t *cend,
+                       uint64_t n, Policy pol, uint32_t *lists, uint32_t *nwin, uint64_t *wl, PlanCounts *pc) {
     GRID_STRIDE(r, n) {
         const uint64_t w = wscan[upoff[r + 1]] - wscan[upoff[r]];
         if (w == 0) continue;
         atomicAdd(&pc->sources, 1ull);
-        const uint32_t side_end = isv[r] ? (uint32_t)n : n_u;
-        const uint32_t range = side_end - smid[r] - 1;
+        const uint32_t range = cend[r] - smid[r] - 1;
         const uint64_t dist = w < range ? w : range;
+        const int bucket = dist <= pol.light_max ? 0 : dist <= pol.medium_max ? 1 : 2;
         int which;
-        if (agg == PB_AGG_DENSE_HIST) which = range <= SMALL_WIN ? LIST_SMALLDENSE : LIST_HEAVY;
-        else if (agg == PB_AGG_RADIX_SORT) which = w <= SORT_LIGHT_W ? LIST_LIGHT : w <= SORT_W ? LIST_MEDIUM : LIST_HEAVY;
-        else if (dist <= LIGHT_D) which = LIST_LIGHT;
-        else if (dist <= MEDIUM_D) which = LIST_MEDIUM;
-        else which = LIST_HEAVY;
+        switch (pol.agg[bucket]) {
+            case PB_AGG_LDS_HASH:  // the policy keeps light_max <= 512 and medium_max <= 4096
+                which = bucket == 0 ? L_HASH_LIGHT : bucket == 1 ? L_HASH_MEDIUM : L_HASH_WIN;
+                break;
+            case PB_AGG_RADIX_SORT:
+                which = w <= SORT_LIGHT_W ? L_SORT_LIGHT : w <= SORT_W ? L_SORT_MEDIUM : L_SORT_HEAVY;
+                break;
+            default:
+                which = range <= SMALL_WIN ? L_DENSE_SMALL : L_DENSE_HEAVY;
+                break;
+        }
         const uint32_t slot = atomicAdd(&pc->list[which], 1u);
         atomicAdd(&pc->wedges[which], (unsigned long long)w);
         lists[(uint64_t)which * n + slot] = (uint32_t)r;
-        if (which == LIST_HEAVY) {
-            const uint32_t nw = agg == PB_AGG_LDS_HASH ? (range + HASH_WIN - 1) / HASH_WIN : 1u;
-            heavy_nwin[slot] = nw;
-            heavy_w[slot] = w;
-            atomicAdd(&pc->items, nw);
+        const int sk = sorted_slot(which);
+        if (sk >= 0) {
+            const uint32_t nw = which == L_HASH_WIN ? (range + HASH_WIN - 1) / HASH_WIN : 1u;
+            nwin[(uint64_t)sk * n + slot] = nw;
+            wl[(uint64_t)sk * n + slot] = w;
+            if (which == L_HASH_WIN) atomicAdd(&pc->items, nw);
         }
     }
 }
 
-// Sort key for the heavy list: most wedges per item first (longest items are
-// dispatched first).
+// Sort key: most wedges per item first (longest items are dispatched first).
 __global__ void k_heavy_keys(const uint32_t *nwin, const uint64_t *w, uint32_t nh, uint64_t *keys, uint32_t *vals) {
     GRID_STRIDE(i, (uint64_t)nh) {
         uint64_t per = w[i] / nwin[i];
@@ -189,7 +215,7 @@ __global__ void k_heavy_gather(const uint32_t *perm, const uint32_t *heavy, cons
     }
 }
 
-// forced-hash items: x = source rank, y = window index
+// hash items: x = source rank, y = window index
 __global__ void k_heavy_expand(const uint32_t *src_sorted, const uint32_t *nwin_sorted, const uint32_t *ioff,
                                uint32_t nh, uint2 *items) {
     GRID_STRIDE(i, (uint64_t)nh) {
@@ -198,15 +224,44 @@ __global__ void k_heavy_expand(const uint32_t *src_sorted, const uint32_t *nwin_
     }
 }
 
+// Largest j < ng with base[j] <= x (base non-decreasing, base[0] <= x).
+template <class T>
+__device__ inline uint32_t graph_of(const T *base, uint32_t ng, T x) {
+    uint32_t lo = 0, hi = ng;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (base[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Candidate range end of each rank (its own side of its own graph) and, for a
+// batch, the graph of each rank.  Ranks are graph-blocked in a batch, so a
+// graph's U (V) vertices hold a contiguous block of side-major ids.
+__global__ void k_cend(const uint32_t *isv, uint64_t n, uint32_t n_u, uint32_t ng, const uint32_t *rbase,
+                       const uint32_t *ubase, const uint32_t *vbase, uint32_t *cend, uint32_t *gid) {
+    GRID_STRIDE(r, n) {
+        if (ng <= 1) {
+            cend[r] = isv[r] ? (uint32_t)n : n_u;
+        } else {
+            const uint32_t j = graph_of<uint32_t>(rbase, ng, (uint32_t)r);
+            gid[r] = j;
+            cend[r] = isv[r] ? n_u + vbase[j + 1] : ubase[j + 1];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- counting
 
 struct Ranked {
-    const uint32_t *roff, *nbr, *upoff, *uprun, *uplen, *smid, *isv;
+    const uint32_t *roff, *nbr, *upoff, *uprun, *uplen, *smid;
+    const uint32_t *cend;  // per rank: end of its candidate id range (its side of its graph)
+    const uint32_t *gid;   // per rank: its graph in a batch (null: one graph)
     uint32_t n_u, n;
 };
 
 struct Acc {
-    unsigned long long *g;  // 1
+    unsigned long long *g;  // one per graph
     unsigned long long *v;  // n, by smid
     unsigned long long *s;  // 2m, by slot (64-bit slot credits)
     uint32_t *s32;          // 2m, by slot, when every slot's credit fits 32 bits
@@ -631,7 +686,7 @@ __device__ bool count_item(const Ranked &G, const Acc &A, uint32_t r, const Agg 
             });
             const unsigned long long tot = block_sum<T>(local, sh.tmp64);
             if (tid == 0 && tot) {
-                if (A.mode & MODE_GLOBAL) atomicAdd(A.g, tot);
+                if (A.mode & MODE_GLOBAL) atomicAdd(&A.g[G.gid ? G.gid[r] : 0u], tot);
                 if (vert) atomicAdd(&A.v[G.smid[r]], tot);
             }
             __syncthreads();
@@ -662,7 +717,7 @@ __global__ __launch_bounds__(T) void k_count_hash_win(Ranked G, Acc A, const uin
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
         const uint2 it = items[i];
         const uint32_t r = it.x, w = it.y;
-        const uint32_t side_end = G.isv[r] ? G.n : G.n_u;
+        const uint32_t side_end = G.cend[r];
         const uint32_t lo = G.smid[r] + 1 + w * HASH_WIN;
         const uint32_t hi = side_end - lo > HASH_WIN ? lo + HASH_WIN : side_end;
         count_item<T, U>(G, A, r, agg, SearchRange{lo, hi}, sh, A.passes());
@@ -684,7 +739,7 @@ __global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32
         const bool half = G.upoff[r + 1] - G.upoff[r] <= 0xFFFFu;
         const uint32_t ws = half ? 2 * WIN_WORDS : WIN_WORDS;
         const uint32_t lo_min = G.smid[r] + 1;
-        uint32_t hi = G.isv[r] ? G.n : G.n_u;
+        uint32_t hi = G.cend[r];
         bool first = true;
         while (hi > lo_min) {
             const uint32_t lo = hi - lo_min > ws ? hi - ws : lo_min;
@@ -713,7 +768,7 @@ __global__ __launch_bounds__(T) void k_count_sort(Ranked G, Acc A, const uint32_
     __shared__ RunShared<T> sh;
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
         const uint32_t r = list[i];
-        const uint32_t lo = G.smid[r] + 1, side_end = G.isv[r] ? G.n : G.n_u;
+        const uint32_t lo = G.smid[r] + 1, side_end = G.cend[r];
         SortAgg<T, CAP> agg{ss.a, ss.b, ss.cnt, ss.start, ss.meta, ss.tmp, lo, side_end - lo};
         if (!count_item<T, U>(G, A, r, agg, FullRange{}, sh, A.passes())) atomicOr(A.err, FLAG_INTERNAL);
     }
@@ -733,7 +788,7 @@ __global__ __launch_bounds__(T) void k_count_sort_heavy(Ranked G, Acc A, const u
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
         const uint32_t r = list[i];
         const uint32_t lo_min = G.smid[r] + 1;
-        uint32_t hi = G.isv[r] ? G.n : G.n_u;
+        uint32_t hi = G.cend[r];
         const uint64_t w = wsrc[i] ? wsrc[i] : 1;
         uint64_t guess = (uint64_t)(hi - lo_min) * (CAP / 2) / w;
         uint32_t width = guess < 1 ? 1u : guess > hi - lo_min ? hi - lo_min : (uint32_t)guess;
@@ -759,7 +814,7 @@ __global__ __launch_bounds__(T) void k_count_dense_src(Ranked G, Acc A, const ui
     __shared__ RunShared<T> sh;
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
         const uint32_t r = list[i];
-        const uint32_t side_end = G.isv[r] ? G.n : G.n_u;
+        const uint32_t side_end = G.cend[r];
         const uint32_t lo = G.smid[r] + 1;
         DenseAgg<T> agg{words, lo, side_end - lo, false, A.err};
         count_item<T, U>(G, A, r, agg, FullRange{}, sh, A.passes());
@@ -768,19 +823,55 @@ __global__ __launch_bounds__(T) void k_count_dense_src(Ranked G, Acc A, const ui
 
 // ---------------------------------------------------------------- outputs
 
-__global__ void k_out_global(const unsigned long long *g, int64_t *out) { *out = (int64_t)*g; }
+struct CoreOut {
+    int64_t *gout, *vout, *eout;                          // one graph
+    int64_t *const *gouts, *const *vouts, *const *eouts;  // a batch: device arrays of per-graph pointers
+};
+
+// Batch layout (device arrays of ng + 1 entries): graph j owns U ids
+// [ubase[j], ubase[j+1]), V-local ids [vbase[j], vbase[j+1]), edges
+// [ebase[j], ebase[j+1]) and ranks [rbase[j], rbase[j+1]).
+struct BatchLayout {
+    uint32_t ng;
+    const uint32_t *ubase, *vbase, *rbase;
+    const uint64_t *ebase;
+};
+
+__global__ void k_out_global(const unsigned long long *g, uint32_t ng, CoreOut out) {
+    GRID_STRIDE(j, (uint64_t)ng) {
+        if (out.gouts) out.gouts[j][0] = (int64_t)g[j];
+        else out.gout[0] = (int64_t)g[0];
+    }
+}
 
 __global__ void k_out_vertex(const uint32_t *rank, const uint32_t *smid, const unsigned long long *v, uint64_t n,
-                             int64_t *out) {
-    GRID_STRIDE(x, n) out[x] = (int64_t)v[smid[rank[x]]];
+                             uint32_t n_u, BatchLayout bl, CoreOut out) {
+    GRID_STRIDE(x, n) {
+        const int64_t val = v ? (int64_t)v[smid[rank[x]]] : 0;
+        if (!out.vouts) {
+            out.vout[x] = val;
+        } else if (x < n_u) {
+            const uint32_t j = graph_of<uint32_t>(bl.ubase, bl.ng, (uint32_t)x);
+            out.vouts[j][x - bl.ubase[j]] = val;
+        } else {
+            const uint32_t xv = (uint32_t)(x - n_u);
+            const uint32_t j = graph_of<uint32_t>(bl.vbase, bl.ng, xv);
+            out.vouts[j][(bl.ubase[j + 1] - bl.ubase[j]) + (xv - bl.vbase[j])] = val;
+        }
+    }
 }
 
 __global__ void k_out_edge(const uint32_t *eslot, const unsigned long long *s, const uint32_t *s32, uint64_t m,
-                           int64_t *out) {
-    if (s32) {
-        GRID_STRIDE(e, m) out[e] = (int64_t)s32[eslot[2 * e]] + (int64_t)s32[eslot[2 * e + 1]];
-    } else {
-        GRID_STRIDE(e, m) out[e] = (int64_t)(s[eslot[2 * e]] + s[eslot[2 * e + 1]]);
+                           BatchLayout bl, CoreOut out) {
+    GRID_STRIDE(e, m) {
+        const int64_t val = s32 ? (int64_t)s32[eslot[2 * e]] + (int64_t)s32[eslot[2 * e + 1]]
+                                : (int64_t)(s[eslot[2 * e]] + s[eslot[2 * e + 1]]);
+        if (!out.eouts) {
+            out.eout[e] = val;
+        } else {
+            const uint32_t j = graph_of<uint64_t>(bl.ebase, bl.ng, e);
+            out.eouts[j][e - bl.ebase[j]] = val;
+        }
     }
 }
 
@@ -792,24 +883,54 @@ void launch_items(K kernel, uint32_t count, uint32_t threads, hipStream_t s, Arg
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), 0, s, args..., count);
 }
 
-pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, int64_t *gout, int64_t *vout,
-                     int64_t *eout, hipStream_t s) {
-    if (!g || !rank) return PB_ERR_INVALID_ARG;
-    if (!gout && !vout && !eout) return PB_ERR_INVALID_ARG;
-    pb_opts opts;
-    pb_opts_default(&opts);
-    if (opts_in) opts = *opts_in;
-    if ((int)opts.agg < PB_AGG_AUTO || (int)opts.agg > PB_AGG_RADIX_SORT) return PB_ERR_INVALID_ARG;
-    if ((int)opts.hub < PB_HUB_AUTO || (int)opts.hub > PB_HUB_FORCE) return PB_ERR_INVALID_ARG;
-    const int mode = (gout ? MODE_GLOBAL : 0) | (vout ? MODE_VERTEX : 0) | (eout ? MODE_EDGE : 0);
-    const uint64_t n = (uint64_t)g->n_u + g->n_v, m = g->m, ns = 2 * m;
+// ---------------------------------------------------------------- the counting pipeline
+
+// Everything the pipeline reads, in unified-id space (one graph, or the
+// disjoint union of a batch).
+struct CoreIn {
+    uint64_t n;
+    uint32_t n_u;
+    uint64_t m;
+    const uint32_t *eu;    // m: U endpoint (unified id) of each edge
+    const uint32_t *ev;    // m: V endpoint (V-local id)
+    const uint32_t *deg;   // n
+    const uint32_t *rank;  // n
+    uint32_t max_deg;
+    BatchLayout bl;        // ng = 1 for one graph
+};
+
+bool policy_from(const pb_opts &o, Policy *p) {
+    *p = Policy{LIGHT_D, MEDIUM_D, {PB_AGG_LDS_HASH, PB_AGG_LDS_HASH, PB_AGG_DENSE_HIST}};
+    if (o.agg == PB_AGG_AUTO) {
+        if (!o.tuning) return true;
+        const pb_tuning &t = *o.tuning;
+        const pb_agg a[3] = {t.light_agg, t.medium_agg, t.heavy_agg};
+        for (int i = 0; i < 3; ++i)
+            if (a[i] != PB_AGG_LDS_HASH && a[i] != PB_AGG_DENSE_HIST && a[i] != PB_AGG_RADIX_SORT) return false;
+        if (t.light_max > LIGHT_D || t.medium_max > MEDIUM_D || t.light_max > t.medium_max) return false;
+        *p = Policy{t.light_max, t.medium_max, {a[0], a[1], a[2]}};
+        return true;
+    }
+    if (o.agg != PB_AGG_LDS_HASH && o.agg != PB_AGG_DENSE_HIST && o.agg != PB_AGG_RADIX_SORT) return false;
+    p->agg[0] = p->agg[1] = p->agg[2] = o.agg;
+    return true;
+}
+
+// Runs framework steps 2-4 (Section 3.1) on `in`.  `list_ms`, if given,
+// receives the time of each work list's kernel (NLISTS entries).
+pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_opts &opts, const Policy &pol,
+                     hipStream_t s, float *list_ms) {
+    const uint64_t n = in.n, m = in.m, ns = 2 * m;
+    const uint32_t ng = in.bl.ng;
     // per-chunk wedge offsets are 32-bit: 1024 runs of at most max_deg each
-    if ((uint64_t)g->max_deg * 1024 >= (uint64_t(1) << 32)) return PB_ERR_INVALID_ARG;
+    if ((uint64_t)in.max_deg * 1024 >= (uint64_t(1) << 32)) return PB_ERR_INVALID_ARG;
     if (opts.stats) *opts.stats = pb_stats{};
 
-    const bool timing = (opts.flags & PB_FLAG_TIMING) && opts.stats;
+    const bool timing = ((opts.flags & PB_FLAG_TIMING) && opts.stats) || list_ms;
+    // events: [0] start, [1] plan done, [2 + i] after list i, [2 + NLISTS] end
+    constexpr int NEV = NLISTS + 3;
     struct Events {
-        hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+        hipEvent_t e[NEV] = {};
         bool ok = false;
         ~Events() {
             for (auto &x : e)
@@ -834,17 +955,17 @@ pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, 
     } host_free{hpc};
 
     // Accumulators first so an empty graph still writes zeros.
-    unsigned long long *gacc = ws.alloc<unsigned long long>(1);
+    unsigned long long *gacc = ws.alloc<unsigned long long>(ng);
     unsigned long long *vacc = (mode & MODE_VERTEX) ? ws.alloc<unsigned long long>(n) : nullptr;
-    // A slot's credit is at most deg(y) * deg(x2) (one R-1 <= deg(x2)-1 per
-    // neighbour of y), so 32-bit slot counters are exact when max_deg^2 < 2^32.
-    const bool slot32 = (uint64_t)g->max_deg * g->max_deg < (uint64_t(1) << 32);
+    // A slot's credit is at most b(e) <= (deg(y) - 1)(deg(x2) - 1), so 32-bit
+    // slot counters are exact when max_deg^2 < 2^32.
+    const bool slot32 = (uint64_t)in.max_deg * in.max_deg < (uint64_t(1) << 32);
     unsigned long long *sacc = (mode & MODE_EDGE) && !slot32 ? ws.alloc<unsigned long long>(ns) : nullptr;
     uint32_t *sacc32 = (mode & MODE_EDGE) && slot32 ? ws.alloc<uint32_t>(ns) : nullptr;
     PlanCounts *pc = ws.alloc<PlanCounts>(1);
     uint32_t *order = ws.alloc<uint32_t>(n), *seen = ws.alloc<uint32_t>(n);
     if (ws.failed) return PB_ERR_NO_MEMORY;
-    PB_TRY(fill<uint64_t>((uint64_t *)gacc, 0, 1, s));
+    PB_TRY(fill<uint64_t>((uint64_t *)gacc, 0, ng, s));
     if (vacc) PB_TRY(fill<uint64_t>((uint64_t *)vacc, 0, n, s));
     if (sacc) PB_TRY(fill<uint64_t>((uint64_t *)sacc, 0, ns, s));
     if (sacc32) PB_TRY(fill<uint32_t>(sacc32, 0u, ns, s));
@@ -854,7 +975,7 @@ pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, 
     if (n > 0) {
         PB_TRY(fill<uint32_t>(seen, 0u, n, s));
         PB_TRY(fill<uint32_t>(order, 0u, n, s));
-        hipLaunchKernelGGL(k_rank_check, dim3(grid_for(n)), dim3(256), 0, s, rank, n, order, seen, &pc->flags);
+        hipLaunchKernelGGL(k_rank_check, dim3(grid_for(n)), dim3(256), 0, s, in.rank, n, order, seen, &pc->flags);
         PB_TRY_HIP(hipGetLastError());
         PB_TRY_HIP(hipMemcpyAsync(hpc, pc, sizeof(PlanCounts), hipMemcpyDeviceToHost, s));
         PB_TRY_HIP(hipStreamSynchronize(s));
@@ -863,16 +984,21 @@ pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, 
     ws.release(seen);
 
     uint64_t wtotal = 0;
+    PlanCounts plan{};
+    uint32_t *smid = nullptr, *eslot = nullptr;
     if (m > 0) {
         // 2. relabel (Algorithm 1) ---------------------------------------------
         uint32_t *isv = ws.alloc<uint32_t>(n), *vbefore = ws.alloc<uint32_t>(n + 1);
         uint32_t *rdeg = ws.alloc<uint32_t>(n), *roff = ws.alloc<uint32_t>(n + 1);
-        uint32_t *smid = ws.alloc<uint32_t>(n);
+        uint32_t *cend = ws.alloc<uint32_t>(n), *gid = ng > 1 ? ws.alloc<uint32_t>(n) : nullptr;
+        smid = ws.alloc<uint32_t>(n);
         if (ws.failed) return PB_ERR_NO_MEMORY;
-        hipLaunchKernelGGL(k_rank_side, dim3(grid_for(n)), dim3(256), 0, s, order, g->deg, n, g->n_u, isv, rdeg);
+        hipLaunchKernelGGL(k_rank_side, dim3(grid_for(n)), dim3(256), 0, s, order, in.deg, n, in.n_u, isv, rdeg);
         PB_TRY((scan_exclusive<uint32_t, uint32_t>(isv, vbefore, n, vbefore + n, ws)));
-        hipLaunchKernelGGL(k_smid, dim3(grid_for(n)), dim3(256), 0, s, isv, vbefore, n, g->n_u, smid);
+        hipLaunchKernelGGL(k_smid, dim3(grid_for(n)), dim3(256), 0, s, isv, vbefore, n, in.n_u, smid);
         PB_TRY((scan_exclusive<uint32_t, uint32_t>(rdeg, roff, n, roff + n, ws)));
+        hipLaunchKernelGGL(k_cend, dim3(grid_for(n)), dim3(256), 0, s, isv, n, in.n_u, ng, in.bl.rbase, in.bl.ubase,
+                           in.bl.vbase, cend, gid);
         ws.release(vbefore);
         ws.release(rdeg);
 
@@ -880,14 +1006,15 @@ pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, 
         uint64_t *k0 = ws.alloc<uint64_t>(ns), *k1 = ws.alloc<uint64_t>(ns);
         uint32_t *v0 = ws.alloc<uint32_t>(ns), *v1 = ws.alloc<uint32_t>(ns);
         if (ws.failed) return PB_ERR_NO_MEMORY;
-        hipLaunchKernelGGL(k_slot_keys, dim3(grid_for(m)), dim3(256), 0, s, g->eu, g->u_adj, rank, m, g->n_u, b, k0,
+        hipLaunchKernelGGL(k_slot_keys, dim3(grid_for(m)), dim3(256), 0, s, in.eu, in.ev, in.rank, m, in.n_u, b, k0,
                            v0);
         PB_TRY_HIP(hipGetLastError());
         uint64_t *ks;
         uint32_t *vs;
         PB_TRY(radix_sort_pairs(k0, v0, k1, v1, ns, 2 * b, ws, &ks, &vs));
 
-        uint32_t *nbr = ws.alloc<uint32_t>(ns), *eslot = ws.alloc<uint32_t>(ns);
+        uint32_t *nbr = ws.alloc<uint32_t>(ns);
+        eslot = ws.alloc<uint32_t>(ns);
         uint32_t *hideg = ws.alloc<uint32_t>(n + 1), *upoff = ws.alloc<uint32_t>(n + 1);
         if (ws.failed) return PB_ERR_NO_MEMORY;
         PB_TRY(fill<uint32_t>(hideg, 0u, n + 1, s));
@@ -904,133 +1031,285 @@ pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, 
         ws.release(v0);
         ws.release(v1);
         ws.release(hideg);
+        ws.release(isv);
 
         // 3. plan: wedges per source, bucket by distinct-endpoint bound -------
         uint64_t *wscan = ws.alloc<uint64_t>(m + 1);
         uint32_t *lists = ws.alloc<uint32_t>((uint64_t)NLISTS * n);
-        uint32_t *heavy_nwin = ws.alloc<uint32_t>(n);
-        uint64_t *heavy_w = ws.alloc<uint64_t>(n);
+        uint32_t *nwin = ws.alloc<uint32_t>((uint64_t)NSORTED * n);
+        uint64_t *wl = ws.alloc<uint64_t>((uint64_t)NSORTED * n);
         if (ws.failed) return PB_ERR_NO_MEMORY;
         PB_TRY((scan_exclusive<uint32_t, uint64_t>(uplen, wscan, m, wscan + m, ws)));
-        hipLaunchKernelGGL(k_plan, dim3(grid_for(n)), dim3(256), 0, s, upoff, wscan, smid, isv, n, g->n_u,
-                           (int)opts.agg, lists, heavy_nwin, heavy_w, pc);
+        hipLaunchKernelGGL(k_plan, dim3(grid_for(n)), dim3(256), 0, s, upoff, wscan, smid, cend, n, pol, lists, nwin,
+                           wl, pc);
         PB_TRY_HIP(hipGetLastError());
         PB_TRY_HIP(hipMemcpyAsync(hpc, pc, sizeof(PlanCounts), hipMemcpyDeviceToHost, s));
         PB_TRY_HIP(hipMemcpyAsync(&wtotal, wscan + m, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
         PB_TRY_HIP(hipStreamSynchronize(s));
-        const PlanCounts plan = *hpc;
+        plan = *hpc;
+        ws.release(wscan);
+        auto list_of = [&](int l) { return (const uint32_t *)(lists + (uint64_t)l * n); };
 
-        // heavy sources, most wedges first (forced hash: their windows)
-        const uint32_t nh = plan.list[LIST_HEAVY];
-        const bool hash_heavy = opts.agg == PB_AGG_LDS_HASH;
-        const bool sort = opts.agg == PB_AGG_RADIX_SORT;
+        // most-wedges-first order for the window lists
+        const uint32_t *sorted_src[NSORTED] = {nullptr, nullptr, nullptr};
+        const uint64_t *sorted_w[NSORTED] = {nullptr, nullptr, nullptr};
         uint2 *items = nullptr;
-        uint32_t *hsrc = nullptr, *cur = nullptr, *nxt = nullptr;
-        uint64_t *hw = nullptr;
-        if (nh > 0) {
+        uint32_t *cur = nullptr, *nxt = nullptr;
+        for (int l = 0; l < NLISTS; ++l) {
+            const int sk = sorted_slot(l);
+            const uint32_t nh = plan.list[l];
+            if (sk < 0 || nh == 0) continue;
             uint64_t *hk0 = ws.alloc<uint64_t>(nh), *hk1 = ws.alloc<uint64_t>(nh);
             uint32_t *hv0 = ws.alloc<uint32_t>(nh), *hv1 = ws.alloc<uint32_t>(nh);
-            uint32_t *hnw = ws.alloc<uint32_t>(nh), *hoff = ws.alloc<uint32_t>(nh + 1);
-            hsrc = ws.alloc<uint32_t>(nh);
-            hw = ws.alloc<uint64_t>(nh);
-            if (hash_heavy) items = ws.alloc<uint2>(plan.items);
-            else {
-                cur = ws.alloc<uint32_t>(m);
-                nxt = ws.alloc<uint32_t>(m);
-            }
+            uint32_t *hnw = ws.alloc<uint32_t>(nh), *hsrc = ws.alloc<uint32_t>(nh);
+            uint64_t *hw = ws.alloc<uint64_t>(nh);
             if (ws.failed) return PB_ERR_NO_MEMORY;
-            const uint32_t *heavy = lists + (uint64_t)LIST_HEAVY * n;
-            hipLaunchKernelGGL(k_heavy_keys, dim3(grid_for(nh)), dim3(256), 0, s, heavy_nwin, heavy_w, nh, hk0, hv0);
+            const uint32_t *nw = nwin + (uint64_t)sk * n;
+            const uint64_t *w = wl + (uint64_t)sk * n;
+            hipLaunchKernelGGL(k_heavy_keys, dim3(grid_for(nh)), dim3(256), 0, s, nw, w, nh, hk0, hv0);
             uint64_t *hks;
             uint32_t *hvs;
             PB_TRY(radix_sort_pairs(hk0, hv0, hk1, hv1, nh, 32, ws, &hks, &hvs));
-            hipLaunchKernelGGL(k_heavy_gather, dim3(grid_for(nh)), dim3(256), 0, s, hvs, heavy, heavy_nwin, heavy_w, nh,
-                               hsrc, hnw, hw);
-            if (hash_heavy) {
+            hipLaunchKernelGGL(k_heavy_gather, dim3(grid_for(nh)), dim3(256), 0, s, hvs, list_of(l), nw, w, nh, hsrc,
+                               hnw, hw);
+            if (l == L_HASH_WIN) {
+                uint32_t *hoff = ws.alloc<uint32_t>(nh + 1);
+                items = ws.alloc<uint2>(plan.items);
+                if (ws.failed) return PB_ERR_NO_MEMORY;
                 PB_TRY((scan_exclusive<uint32_t, uint32_t>(hnw, hoff, nh, hoff + nh, ws)));
                 hipLaunchKernelGGL(k_heavy_expand, dim3(grid_for(nh)), dim3(256), 0, s, hsrc, hnw, hoff, nh, items);
+            } else if (!cur) {
+                cur = ws.alloc<uint32_t>(m);
+                nxt = ws.alloc<uint32_t>(m);
+                if (ws.failed) return PB_ERR_NO_MEMORY;
             }
             PB_TRY_HIP(hipGetLastError());
+            sorted_src[sk] = hsrc;
+            sorted_w[sk] = hw;
         }
 
         // 4. count ---------------------------------------------------------------
-        Ranked G{roff, nbr, upoff, uprun, uplen, smid, isv, g->n_u, (uint32_t)n};
+        Ranked G{roff, nbr, upoff, uprun, uplen, smid, cend, gid, in.n_u, (uint32_t)n};
         Acc A{gacc, vacc, sacc, sacc32, &pc->flags, mode};
         mark(1);
-        if (nh > 0) {
-            if (hash_heavy)
-                launch_items(k_count_hash_win<256, 4, 2 * HASH_WIN>, plan.items, 256, s, G, A, (const uint2 *)items);
-            else if (sort)
-                launch_items(k_count_sort_heavy<256, 4, SORT_W>, nh, 256, s, G, A, (const uint32_t *)hsrc,
-                             (const uint64_t *)hw, cur, nxt);
-            else
-                launch_items(k_count_heavy<1024, 4>, nh, 1024, s, G, A, (const uint32_t *)hsrc, cur, nxt);
-        }
-        mark(2);
-        if (plan.list[LIST_MEDIUM] && sort)
-            launch_items(k_count_sort<256, 4, SORT_W>, plan.list[LIST_MEDIUM], 256, s, G, A,
-                         (const uint32_t *)(lists + (uint64_t)LIST_MEDIUM * n));
-        else if (plan.list[LIST_MEDIUM])
-            launch_items(k_count_hash<256, 4, 2 * MEDIUM_D>, plan.list[LIST_MEDIUM], 256, s, G, A,
-                        (const uint32_t *)(lists + (uint64_t)LIST_MEDIUM * n));
-        if (plan.list[LIST_SMALLDENSE])
-            launch_items(k_count_dense_src<256, 4, SMALL_WIN>, plan.list[LIST_SMALLDENSE], 256, s, G, A,
-                        (const uint32_t *)(lists + (uint64_t)LIST_SMALLDENSE * n));
-        if (plan.list[LIST_LIGHT] && sort)
-            launch_items(k_count_sort<64, 4, SORT_LIGHT_W>, plan.list[LIST_LIGHT], 64, s, G, A,
-                         (const uint32_t *)(lists + (uint64_t)LIST_LIGHT * n));
-        else if (plan.list[LIST_LIGHT])
-            launch_items(k_count_hash<64, 4, 2 * LIGHT_D>, plan.list[LIST_LIGHT], 64, s, G, A,
-                        (const uint32_t *)(lists + (uint64_t)LIST_LIGHT * n));
-        PB_TRY_HIP(hipGetLastError());
-        mark(3);
-
-        // 5. outputs ---------------------------------------------------------------
-        if (vout)
-            hipLaunchKernelGGL(k_out_vertex, dim3(grid_for(n)), dim3(256), 0, s, rank, smid, vacc, n, vout);
-        if (eout) hipLaunchKernelGGL(k_out_edge, dim3(grid_for(m)), dim3(256), 0, s, eslot, sacc, sacc32, m, eout);
-        if (opts.stats) {
-            pb_stats &st = *opts.stats;
-            st.wedges = wtotal;
-            st.sources = plan.sources;
-            st.sources_hash = sort ? 0 : plan.list[LIST_LIGHT] + plan.list[LIST_MEDIUM] + (hash_heavy ? nh : 0);
-            st.sources_dense = plan.list[LIST_SMALLDENSE] + (hash_heavy || sort ? 0 : nh);
-            st.window_items = nh ? plan.items : 0;
-            const uint64_t wl = plan.wedges[LIST_LIGHT] + plan.wedges[LIST_MEDIUM];
-            const uint32_t sl = plan.list[LIST_LIGHT] + plan.list[LIST_MEDIUM];
-            st.wedges_hash = sort ? 0 : wl + (hash_heavy ? plan.wedges[LIST_HEAVY] : 0);
-            st.wedges_dense = plan.wedges[LIST_SMALLDENSE] + (hash_heavy || sort ? 0 : plan.wedges[LIST_HEAVY]);
-            st.wedges_sort = sort ? wl + plan.wedges[LIST_HEAVY] : 0;
-            st.sources_sort = sort ? sl + nh : 0;
+        for (int l = 0; l < NLISTS; ++l) {
+            const uint32_t c = plan.list[l];
+            if (c) {
+                switch (l) {
+                    case L_DENSE_HEAVY:
+                        launch_items(k_count_heavy<1024, 4>, c, 1024, s, G, A, sorted_src[2], cur, nxt);
+                        break;
+                    case L_SORT_HEAVY:
+                        launch_items(k_count_sort_heavy<256, 4, SORT_W>, c, 256, s, G, A, sorted_src[1], sorted_w[1],
+                                     cur, nxt);
+                        break;
+                    case L_HASH_WIN:
+                        launch_items(k_count_hash_win<256, 4, 2 * HASH_WIN>, plan.items, 256, s, G, A,
+                                     (const uint2 *)items);
+                        break;
+                    case L_HASH_MEDIUM:
+                        launch_items(k_count_hash<256, 4, 2 * MEDIUM_D>, c, 256, s, G, A, list_of(l));
+                        break;
+                    case L_HASH_LIGHT:
+                        launch_items(k_count_hash<64, 4, 2 * LIGHT_D>, c, 64, s, G, A, list_of(l));
+                        break;
+                    case L_SORT_MEDIUM:
+                        launch_items(k_count_sort<256, 4, SORT_W>, c, 256, s, G, A, list_of(l));
+                        break;
+                    case L_SORT_LIGHT:
+                        launch_items(k_count_sort<64, 4, SORT_LIGHT_W>, c, 64, s, G, A, list_of(l));
+                        break;
+                    case L_DENSE_SMALL:
+                        launch_items(k_count_dense_src<256, 4, SMALL_WIN>, c, 256, s, G, A, list_of(l));
+                        break;
+                }
+                PB_TRY_HIP(hipGetLastError());
+            }
+            mark(2 + l);
         }
     } else {
-        if (vout) PB_TRY(fill<int64_t>(vout, 0, n, s));
+        for (int l = 0; l < NLISTS; ++l) mark(1 + l);
+        mark(1 + NLISTS);
     }
-    if (gout) hipLaunchKernelGGL(k_out_global, dim3(1), dim3(1), 0, s, gacc, gout);
+
+    // 5. outputs -------------------------------------------------------------------
+    if (mode & MODE_VERTEX)
+        hipLaunchKernelGGL(k_out_vertex, dim3(grid_for(n)), dim3(256), 0, s, in.rank, smid, m ? vacc : nullptr, n,
+                           in.n_u, in.bl, out);
+    if ((mode & MODE_EDGE) && m)
+        hipLaunchKernelGGL(k_out_edge, dim3(grid_for(m)), dim3(256), 0, s, eslot, sacc, sacc32, m, in.bl, out);
+    if (mode & MODE_GLOBAL) hipLaunchKernelGGL(k_out_global, dim3(grid_for(ng)), dim3(256), 0, s, gacc, ng, out);
     PB_TRY_HIP(hipGetLastError());
-    if (opts.stats) opts.stats->workspace_bytes = ws.peak;
+    mark(2 + NLISTS);
     PB_TRY_HIP(hipMemcpyAsync(hpc, pc, sizeof(PlanCounts), hipMemcpyDeviceToHost, s));
-    if (timing && ev.ok) {
-        mark(4);
-        if (m == 0) {  // nothing but the outputs ran
-            for (int i = 1; i < 4; ++i) (void)hipEventRecord(ev.e[i], s);
-        }
-        PB_TRY_HIP(hipEventSynchronize(ev.e[4]));
-        float t[4] = {0, 0, 0, 0};
-        for (int i = 0; i < 4; ++i) (void)hipEventElapsedTime(&t[i], ev.e[i], ev.e[i + 1]);
-        opts.stats->ms_prepare = t[0];
-        if (opts.agg == PB_AGG_LDS_HASH) {
-            opts.stats->ms_hash = t[1] + t[2];
-        } else if (opts.agg == PB_AGG_RADIX_SORT) {
-            opts.stats->ms_sort = t[1] + t[2];
-        } else {
-            opts.stats->ms_dense = t[1];
-            opts.stats->ms_hash = t[2];
-        }
-        opts.stats->ms_output = t[3];
-    }
     PB_TRY_HIP(hipStreamSynchronize(s));
     if (hpc->flags & FLAG_INTERNAL) return PB_ERR_HIP;
+
+    float t[NEV - 1] = {};
+    if (timing && ev.ok)
+        for (int i = 0; i + 1 < NEV; ++i) (void)hipEventElapsedTime(&t[i], ev.e[i], ev.e[i + 1]);
+    if (list_ms)
+        for (int l = 0; l < NLISTS; ++l) list_ms[l] = t[1 + l];
+    if (opts.stats) {
+        pb_stats &st = *opts.stats;
+        st.wedges = wtotal;
+        st.sources = plan.sources;
+        st.sources_hash = plan.list[L_HASH_LIGHT] + plan.list[L_HASH_MEDIUM] + plan.list[L_HASH_WIN];
+        st.sources_dense = plan.list[L_DENSE_HEAVY] + plan.list[L_DENSE_SMALL];
+        st.sources_sort = plan.list[L_SORT_LIGHT] + plan.list[L_SORT_MEDIUM] + plan.list[L_SORT_HEAVY];
+        st.window_items = plan.items + plan.list[L_DENSE_HEAVY] + plan.list[L_SORT_HEAVY];
+        st.wedges_hash = plan.wedges[L_HASH_LIGHT] + plan.wedges[L_HASH_MEDIUM] + plan.wedges[L_HASH_WIN];
+        st.wedges_dense = plan.wedges[L_DENSE_HEAVY] + plan.wedges[L_DENSE_SMALL];
+        st.wedges_sort = plan.wedges[L_SORT_LIGHT] + plan.wedges[L_SORT_MEDIUM] + plan.wedges[L_SORT_HEAVY];
+        st.workspace_bytes = ws.peak;
+        if (timing && ev.ok) {
+            st.ms_prepare = t[0];
+            st.ms_hash = t[1 + L_HASH_LIGHT] + t[1 + L_HASH_MEDIUM] + t[1 + L_HASH_WIN];
+            st.ms_dense = t[1 + L_DENSE_HEAVY] + t[1 + L_DENSE_SMALL];
+            st.ms_sort = t[1 + L_SORT_LIGHT] + t[1 + L_SORT_MEDIUM] + t[1 + L_SORT_HEAVY];
+            st.ms_output = t[1 + NLISTS];
+        }
+    }
+    return PB_OK;
+}
+
+pb_status check_opts(const pb_opts *opts_in, pb_opts *opts, Policy *pol) {
+    pb_opts_default(opts);
+    if (opts_in) *opts = *opts_in;
+    if ((int)opts->agg < PB_AGG_AUTO || (int)opts->agg > PB_AGG_RADIX_SORT) return PB_ERR_INVALID_ARG;
+    if ((int)opts->hub < PB_HUB_AUTO || (int)opts->hub > PB_HUB_FORCE) return PB_ERR_INVALID_ARG;
+    if (!policy_from(*opts, pol)) return PB_ERR_INVALID_ARG;
+    return PB_OK;
+}
+
+pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, int64_t *gout, int64_t *vout,
+                     int64_t *eout, hipStream_t s) {
+    if (!g || !rank) return PB_ERR_INVALID_ARG;
+    if (!gout && !vout && !eout) return PB_ERR_INVALID_ARG;
+    pb_opts opts;
+    Policy pol;
+    PB_TRY(check_opts(opts_in, &opts, &pol));
+    const int mode = (gout ? MODE_GLOBAL : 0) | (vout ? MODE_VERTEX : 0) | (eout ? MODE_EDGE : 0);
+    CoreIn in{(uint64_t)g->n_u + g->n_v, g->n_u, g->m, g->eu, g->u_adj, g->deg, rank, g->max_deg,
+              BatchLayout{1, nullptr, nullptr, nullptr, nullptr}};
+    CoreOut out{gout, vout, eout, nullptr, nullptr, nullptr};
+    return count_core(in, out, mode, opts, pol, s, nullptr);
+}
+
+// ---------------------------------------------------------------- batches
+
+struct GraphDesc {
+    const uint32_t *eu, *uadj, *deg, *rank;
+    uint32_t n_u, n_v;
+    uint64_t m;
+    uint32_t ubase, vbase, rbase;
+    uint64_t ebase;
+};
+
+__global__ void k_union_edges(const GraphDesc *gd, const uint64_t *ebase, uint32_t ng, uint64_t m, uint32_t *eu,
+                              uint32_t *ev) {
+    GRID_STRIDE(e, m) {
+        const uint32_t j = graph_of<uint64_t>(ebase, ng, e);
+        const GraphDesc &d = gd[j];
+        const uint64_t le = e - d.ebase;
+        eu[e] = d.ubase + d.eu[le];
+        ev[e] = d.vbase + d.uadj[le];
+    }
+}
+
+// deg and rank of the union; rank of graph j's vertex = rbase[j] + its rank in j
+__global__ void k_union_vertices(const GraphDesc *gd, const uint32_t *ubase, const uint32_t *vbase, uint32_t ng,
+                                 uint64_t n, uint32_t n_u, uint32_t *deg, uint32_t *rank, uint32_t *flags) {
+    GRID_STRIDE(x, n) {
+        uint32_t j, local;
+        if (x < n_u) {
+            j = graph_of<uint32_t>(ubase, ng, (uint32_t)x);
+            local = (uint32_t)x - ubase[j];
+        } else {
+            const uint32_t xv = (uint32_t)(x - n_u);
+            j = graph_of<uint32_t>(vbase, ng, xv);
+            local = gd[j].n_u + (xv - vbase[j]);
+        }
+        const GraphDesc &d = gd[j];
+        deg[x] = d.deg[local];
+        const uint32_t r = d.rank[local];
+        if (r >= d.n_u + d.n_v) atomicOr(flags, FLAG_BAD_RANK);
+        rank[x] = d.rbase + (r < d.n_u + d.n_v ? r : 0u);
+    }
+}
+
+struct BatchBuild {
+    CoreIn in;
+    CoreOut out;
+    int mode;
+};
+
+// Lays out the batch as one disjoint union (device arrays in `ws`).
+pb_status build_batch(pb_graph *const *gs, const uint32_t *const *ranks, uint32_t count, int64_t *const *gouts,
+                      int64_t *const *vouts, int64_t *const *eouts, Workspace &ws, hipStream_t s, BatchBuild *bb) {
+    if (!gs || !ranks || count == 0) return PB_ERR_INVALID_ARG;
+    if (!gouts && !vouts && !eouts) return PB_ERR_INVALID_ARG;
+    std::vector<GraphDesc> gd(count);
+    std::vector<uint32_t> ub(count + 1), vb(count + 1), rb(count + 1);
+    std::vector<uint64_t> eb(count + 1);
+    uint64_t U = 0, V = 0, M = 0, N = 0;
+    uint32_t max_deg = 0;
+    for (uint32_t j = 0; j < count; ++j) {
+        const pb_graph *g = gs[j];
+        if (!g || !ranks[j]) return PB_ERR_INVALID_ARG;
+        if ((gouts && !gouts[j]) || (vouts && !vouts[j]) || (eouts && !eouts[j] && g->m)) return PB_ERR_INVALID_ARG;
+        ub[j] = (uint32_t)U;
+        vb[j] = (uint32_t)V;
+        rb[j] = (uint32_t)N;
+        eb[j] = M;
+        gd[j] = GraphDesc{g->eu, g->u_adj, g->deg, ranks[j], g->n_u, g->n_v, g->m, (uint32_t)U, (uint32_t)V,
+                          (uint32_t)N, M};
+        U += g->n_u;
+        V += g->n_v;
+        M += g->m;
+        N += (uint64_t)g->n_u + g->n_v;
+        max_deg = std::max(max_deg, g->max_deg);
+        if (N >= 0xFFFFFFFFull || M >= (uint64_t(1) << 31)) return PB_ERR_INVALID_ARG;
+    }
+    ub[count] = (uint32_t)U;
+    vb[count] = (uint32_t)V;
+    rb[count] = (uint32_t)N;
+    eb[count] = M;
+
+    GraphDesc *d_gd = ws.alloc<GraphDesc>(count);
+    uint32_t *d_ub = ws.alloc<uint32_t>(count + 1), *d_vb = ws.alloc<uint32_t>(count + 1);
+    uint32_t *d_rb = ws.alloc<uint32_t>(count + 1);
+    uint64_t *d_eb = ws.alloc<uint64_t>(count + 1);
+    int64_t **d_outs[3] = {nullptr, nullptr, nullptr};
+    int64_t *const *h_outs[3] = {gouts, vouts, eouts};
+    for (int k = 0; k < 3; ++k)
+        if (h_outs[k]) d_outs[k] = ws.alloc<int64_t *>(count);
+    uint32_t *eu = ws.alloc<uint32_t>(M), *ev = ws.alloc<uint32_t>(M);
+    uint32_t *deg = ws.alloc<uint32_t>(N), *rank = ws.alloc<uint32_t>(N), *flags = ws.alloc<uint32_t>(1);
+    if (ws.failed) return PB_ERR_NO_MEMORY;
+    // host -> device copies of the layout (pageable sources: the copy completes
+    // before the call returns)
+    PB_TRY_HIP(hipMemcpyAsync(d_gd, gd.data(), count * sizeof(GraphDesc), hipMemcpyHostToDevice, s));
+    PB_TRY_HIP(hipMemcpyAsync(d_ub, ub.data(), (count + 1) * 4, hipMemcpyHostToDevice, s));
+    PB_TRY_HIP(hipMemcpyAsync(d_vb, vb.data(), (count + 1) * 4, hipMemcpyHostToDevice, s));
+    PB_TRY_HIP(hipMemcpyAsync(d_rb, rb.data(), (count + 1) * 4, hipMemcpyHostToDevice, s));
+    PB_TRY_HIP(hipMemcpyAsync(d_eb, eb.data(), (count + 1) * 8, hipMemcpyHostToDevice, s));
+    for (int k = 0; k < 3; ++k)
+        if (h_outs[k])
+            PB_TRY_HIP(hipMemcpyAsync(d_outs[k], h_outs[k], count * sizeof(int64_t *), hipMemcpyHostToDevice, s));
+    PB_TRY(fill<uint32_t>(flags, 0u, 1, s));
+    if (M) hipLaunchKernelGGL(k_union_edges, dim3(grid_for(M)), dim3(256), 0, s, d_gd, d_eb, count, M, eu, ev);
+    if (N)
+        hipLaunchKernelGGL(k_union_vertices, dim3(grid_for(N)), dim3(256), 0, s, d_gd, d_ub, d_vb, count, N,
+                           (uint32_t)U, deg, rank, flags);
+    PB_TRY_HIP(hipGetLastError());
+    uint32_t hflag = 0;
+    PB_TRY_HIP(hipMemcpyAsync(&hflag, flags, 4, hipMemcpyDeviceToHost, s));
+    PB_TRY_HIP(hipStreamSynchronize(s));
+    if (hflag & FLAG_BAD_RANK) return PB_ERR_BAD_RANK;
+    bb->mode = (gouts ? MODE_GLOBAL : 0) | (vouts ? MODE_VERTEX : 0) | (eouts ? MODE_EDGE : 0);
+    bb->in = CoreIn{N, (uint32_t)U, M, eu, ev, deg, rank, max_deg, BatchLayout{count, d_ub, d_vb, d_rb, d_eb}};
+    bb->out = CoreOut{nullptr, nullptr, nullptr, d_outs[0], d_outs[1], d_outs[2]};
     return PB_OK;
 }
 
@@ -1056,6 +1335,98 @@ pb_status pb_count_vertex(pb_graph *g, const uint32_t *rank, const pb_opts *opts
 pb_status pb_count_edge(pb_graph *g, const uint32_t *rank, const pb_opts *opts, int64_t *out, hipStream_t stream) {
     if (!out) return PB_ERR_INVALID_ARG;
     return count_impl(g, rank, opts, nullptr, nullptr, out, stream);
+}
+
+pb_status pb_count_batched(pb_graph *const *graphs, const uint32_t *const *ranks, uint32_t count, const pb_opts *opts_in,
+                           int64_t *const *global_outs, int64_t *const *vertex_outs, int64_t *const *edge_outs,
+                           hipStream_t stream) {
+    if (!graphs || !ranks || count == 0) return PB_ERR_INVALID_ARG;
+    pb_opts opts;
+    Policy pol;
+    PB_TRY(check_opts(opts_in, &opts, &pol));
+    Workspace ws(stream, 0);
+    BatchBuild bb;
+    PB_TRY(build_batch(graphs, ranks, count, global_outs, vertex_outs, edge_outs, ws, stream, &bb));
+    return count_core(bb.in, bb.out, bb.mode, opts, pol, stream, nullptr);
+}
+
+pb_status pb_autotune(pb_graph *const *graphs, const uint32_t *const *ranks, uint32_t count, const pb_opts *opts_in,
+                      uint32_t repeats, pb_tuning *out, hipStream_t stream) {
+    if (!out || !graphs || !ranks || count == 0) return PB_ERR_INVALID_ARG;
+    pb_opts opts;
+    Policy pol;
+    PB_TRY(check_opts(opts_in, &opts, &pol));
+    opts.agg = PB_AGG_AUTO;
+    opts.stats = nullptr;
+    if (repeats == 0) repeats = 1;
+    // scratch outputs for the timed counts: global and per-edge of every graph
+    Workspace ws(stream, 0);
+    uint64_t mtot = 0;
+    for (uint32_t j = 0; j < count; ++j) {
+        if (!graphs || !graphs[j]) return PB_ERR_INVALID_ARG;
+        mtot += graphs[j]->m;
+    }
+    int64_t *gbuf = ws.alloc<int64_t>(count), *ebuf = ws.alloc<int64_t>(mtot ? mtot : 1);
+    if (ws.failed) return PB_ERR_NO_MEMORY;
+    std::vector<int64_t *> gp(count), ep(count);
+    uint64_t off = 0;
+    for (uint32_t j = 0; j < count; ++j) {
+        gp[j] = gbuf + j;
+        ep[j] = ebuf + off;
+        off += graphs[j]->m;
+    }
+    BatchBuild bb;
+    PB_TRY(build_batch(graphs, ranks, count, gp.data(), nullptr, ep.data(), ws, stream, &bb));
+
+    Policy best = Policy{LIGHT_D, MEDIUM_D, {PB_AGG_LDS_HASH, PB_AGG_LDS_HASH, PB_AGG_DENSE_HIST}};
+    auto time_policy = [&](const Policy &p, float *ms) -> pb_status {
+        std::vector<float> runs;
+        for (uint32_t rep = 0; rep < repeats; ++rep) {
+            float lm[NLISTS];
+            PB_TRY(count_core(bb.in, bb.out, bb.mode, opts, p, stream, lm));
+            float tot = 0;
+            for (float x : lm) tot += x;
+            runs.push_back(tot);
+        }
+        std::sort(runs.begin(), runs.end());
+        *ms = runs[runs.size() / 2];
+        return PB_OK;
+    };
+    float best_ms;
+    PB_TRY(time_policy(best, &best_ms));
+    // one bucket at a time: its aggregator, then its threshold
+    const int choices[3][3] = {{PB_AGG_LDS_HASH, PB_AGG_RADIX_SORT, PB_AGG_DENSE_HIST},
+                               {PB_AGG_LDS_HASH, PB_AGG_RADIX_SORT, PB_AGG_DENSE_HIST},
+                               {PB_AGG_DENSE_HIST, PB_AGG_LDS_HASH, PB_AGG_RADIX_SORT}};
+    for (int bkt = 0; bkt < 3; ++bkt)
+        for (int c : choices[bkt]) {
+            if (c == best.agg[bkt]) continue;
+            Policy p = best;
+            p.agg[bkt] = c;
+            float ms;
+            PB_TRY(time_policy(p, &ms));
+            if (ms < best_ms) { best = p; best_ms = ms; }
+        }
+    const uint32_t light_opts[] = {64, 128, 256, 512};
+    for (uint32_t lm : light_opts) {
+        if (lm == best.light_max) continue;
+        Policy p = best;
+        p.light_max = lm;
+        float ms;
+        PB_TRY(time_policy(p, &ms));
+        if (ms < best_ms) { best = p; best_ms = ms; }
+    }
+    const uint32_t medium_opts[] = {1024, 2048, 4096};
+    for (uint32_t mm : medium_opts) {
+        if (mm == best.medium_max || mm < best.light_max) continue;
+        Policy p = best;
+        p.medium_max = mm;
+        float ms;
+        PB_TRY(time_policy(p, &ms));
+        if (ms < best_ms) { best = p; best_ms = ms; }
+    }
+    *out = pb_tuning{best.light_max, best.medium_max, (pb_agg)best.agg[0], (pb_agg)best.agg[1], (pb_agg)best.agg[2]};
+    return PB_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,106 @@
+"""GPU parity of the batched path: each graph of a batch counted in one pass
+must equal the oracle and the same graph counted alone."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1907_08607_amd import graphgen as gg
+
+torch = pytest.importorskip("torch")
+pb = pytest.importorskip("paper_1907_08607_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pb.load_library()
+
+
+def small_batch(seed=0, count=24):
+    """Uneven graphs in the shape of the batched workload, scaled down, plus
+    degenerate members (no edges, complete, a single edge)."""
+    rng = np.random.default_rng(seed)
+    gs = []
+    for i in range(count):
+        n_u = int(np.exp(rng.uniform(np.log(8), np.log(600))))
+        n_v = int(np.exp(rng.uniform(np.log(8), np.log(600))))
+        m = int(np.exp(rng.uniform(np.log(16), np.log(20_000))))
+        m = max(1, min(m, n_u * n_v // 4))
+        gs.append(gg.batch_graph(n_u, n_v, m, seed * 1000 + i))
+    gs += [gg.from_edges(5, 7, [], []), gg.complete(12, 9), gg.from_edges(1, 1, [0], [0])]
+    return gs
+
+
+def to_gpu(gs, kind="degree"):
+    Gs = [pb.Graph.from_csr(g) for g in gs]
+    ranks = [torch.from_numpy(oracle.rank(g, kind).view(np.int32)).cuda() for g in gs]
+    return Gs, ranks
+
+
+@pytest.mark.parametrize("agg", ["auto", "hash", "dense", "sort"])
+def test_batch_matches_oracle(agg):
+    gs = small_batch(1)
+    Gs, ranks = to_gpu(gs)
+    stats = pb.pb_stats()
+    gl, ve, ed = pb.pb_count_batched(Gs, ranks, True, True, True, agg=agg, stats=stats)
+    torch.cuda.synchronize()
+    wtot = 0
+    for i, g in enumerate(gs):
+        want = oracle.count(g)
+        assert int(gl[i].cpu()[0]) == want[0], i
+        assert (ve[i].cpu().numpy() == want[1]).all(), i
+        if g.m:
+            assert (ed[i].cpu().numpy()[:g.m] == want[2]).all(), i
+        wtot += oracle.wedges(g, oracle.rank(g, "degree"))
+    assert stats.wedges == wtot
+
+
+def test_batch_equals_single_counts():
+    gs = small_batch(2, 16)
+    Gs, ranks = to_gpu(gs, "approx_codeg")
+    gl, _, ed = pb.pb_count_batched(Gs, ranks, True, False, True)
+    for i, (G, r) in enumerate(zip(Gs, ranks)):
+        g1, _, e1 = pb.pb_count(G, r, True, False, True)
+        assert int(g1.cpu()[0]) == int(gl[i].cpu()[0])
+        if G.m:
+            assert torch.equal(e1.cpu(), ed[i].cpu()[:G.m])
+
+
+def test_batch_rejects_a_bad_rank():
+    gs = small_batch(3, 4)
+    Gs, ranks = to_gpu(gs)
+    ranks[2] = ranks[2].clone()
+    ranks[2][0] = ranks[2][1]
+    with pytest.raises(pb.PBError) as e:
+        pb.pb_count_batched(Gs, ranks)
+    assert e.value.status == -4
+    ranks[2] = torch.full_like(ranks[2], gs[2].n_u + gs[2].n_v)  # outside its own graph's range
+    with pytest.raises(pb.PBError) as e:
+        pb.pb_count_batched(Gs, ranks)
+    assert e.value.status == -4
+
+
+def test_autotune_table_is_valid_and_exact():
+    gs = small_batch(4, 20)
+    Gs, ranks = to_gpu(gs)
+    t = pb.pb_autotune(Gs, ranks, repeats=1)
+    d = t.as_dict()
+    assert d["light_max"] <= 512 and d["medium_max"] <= 4096 and d["light_max"] <= d["medium_max"]
+    assert d["light_agg"] in ("hash", "sort", "dense") and d["heavy_agg"] in ("hash", "sort", "dense")
+    gl, ve, ed = pb.pb_count_batched(Gs, ranks, True, True, True, tuning=t)
+    for i, g in enumerate(gs):
+        want = oracle.count(g)
+        assert int(gl[i].cpu()[0]) == want[0]
+        assert (ve[i].cpu().numpy() == want[1]).all()
+    # a hand-written table that mixes all three aggregators
+    mix = pb.pb_tuning(64, 1024, pb.AGGS["sort"], pb.AGGS["dense"], pb.AGGS["hash"])
+    g = gg.workload_powerlaw_50m(scale=0.005)
+    G = pb.Graph.from_csr(g)
+    r = torch.from_numpy(oracle.rank(g, "degree").view(np.int32)).cuda()
+    gl1, ve1, ed1 = pb.pb_count(G, r, tuning=mix)
+    want = oracle.count(g)
+    assert int(gl1.cpu()[0]) == want[0]
+    assert (ve1.cpu().numpy() == want[1]).all() and (ed1.cpu().numpy() == want[2]).all()
