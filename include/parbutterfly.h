@@ -244,6 +244,66 @@ pb_status pb_count_batched(pb_graph *const *graphs, const uint32_t *const *ranks
 pb_status pb_autotune(pb_graph *const *graphs, const uint32_t *const *ranks, uint32_t count, const pb_opts *opts,
                       uint32_t repeats, pb_tuning *out, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: counting queries against graphs kept resident on the device.
+ *
+ * A server holds a pool of resident graphs (with their rankings) admitted
+ * against an HBM budget, a queue of requests, and `slots` worker threads, each
+ * with its own stream.  A free slot takes the oldest queued request together
+ * with up to max_batch - 1 later requests of the same output kinds whose
+ * estimated device scratch still fits the budget next to the batches already
+ * in flight, and counts them with one batched pass (pb_count_batched).
+ * Requests that arrive while batches are running wait for the next free slot
+ * and memory; batches on different slots overlap on the device.  Results are
+ * identical to counting each request alone.
+ */
+typedef struct pb_server pb_server;
+
+typedef struct {
+    uint64_t hbm_budget_bytes; /* resident pool + in-flight scratch; 0 = the device's free memory */
+    uint32_t slots;            /* concurrent batches (worker threads / streams), >= 1 */
+    uint32_t max_batch;        /* requests per batch, >= 1 */
+    pb_agg agg;                /* aggregation policy of every batch */
+    const pb_tuning *tuning;   /* optional AUTO table (copied) */
+} pb_server_config;
+
+enum { PB_WANT_GLOBAL = 1, PB_WANT_VERTEX = 2, PB_WANT_EDGE = 4 };
+
+typedef struct {
+    uint64_t request_id;
+    int32_t status;  /* pb_status of its batch */
+    uint32_t batch;  /* requests in its batch */
+    double submit_s; /* seconds since the server started */
+    double start_s;  /* its batch started */
+    double done_s;   /* its batch finished; latency = done_s - submit_s */
+} pb_completion;
+
+/* Starts the worker slots.  Errors: INVALID_ARG, NO_MEMORY, HIP. */
+pb_status pb_server_create(const pb_server_config *config, pb_server **out);
+
+/* Adds a resident graph: `g` and `rank` (device, n entries) stay owned by the
+ * caller and must outlive the server.  Its resident footprint (caller CSR,
+ * derived arrays, rank) is charged to the budget; NO_MEMORY when the pool
+ * would exceed it.  *graph_id receives its index. */
+pb_status pb_server_add_graph(pb_server *srv, pb_graph *g, const uint32_t *rank, uint32_t *graph_id);
+
+/* Queues a request for graph `graph_id`; `want` is a PB_WANT_* mask and the
+ * matching outputs (device, caller-owned, sized as for pb_count) must stay
+ * valid until the request completes.  Returns at once; *request_id receives
+ * its id.  NO_MEMORY when the request alone could never fit the budget. */
+pb_status pb_server_submit(pb_server *srv, uint32_t graph_id, uint32_t want, int64_t *global_out,
+                           int64_t *vertex_out, int64_t *edge_out, uint64_t *request_id);
+
+/* Moves up to `max` completed requests into out[] (oldest completion first);
+ * *count receives how many.  Never blocks. */
+pb_status pb_server_poll(pb_server *srv, pb_completion *out, uint32_t max, uint32_t *count);
+
+/* Blocks until every submitted request has completed. */
+pb_status pb_server_drain(pb_server *srv);
+
+/* Drains, stops the slots and frees the server (NULL is ignored). */
+void pb_server_destroy(pb_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -292,3 +292,89 @@ def pb_autotune(graphs, ranks, repeats=3, agg="auto", stream=None) -> pb_tuning:
     _check(load_library().pb_autotune(cast(gp), cast(rp), len(graphs), ctypes.byref(opts), int(repeats),
                                       ctypes.byref(out), _stream(stream)), "pb_autotune")
     return out
+
+
+# ---------------------------------------------------------------- serving
+
+WANT = {"global": 1, "vertex": 2, "edge": 4}
+
+
+class pb_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("slots", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("agg", ctypes.c_int), ("tuning", ctypes.POINTER(pb_tuning))]
+
+
+class pb_completion(ctypes.Structure):
+    _fields_ = [("request_id", ctypes.c_uint64), ("status", ctypes.c_int32), ("batch", ctypes.c_uint32),
+                ("submit_s", ctypes.c_double), ("start_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
+def _load_server_api():
+    lib = load_library()
+    if getattr(lib, "_server_api", False):
+        return lib
+    P = ctypes.c_void_p
+    lib.pb_server_create.argtypes = [ctypes.POINTER(pb_server_config), ctypes.POINTER(P)]
+    lib.pb_server_create.restype = ctypes.c_int
+    lib.pb_server_add_graph.argtypes = [P, P, P, ctypes.POINTER(ctypes.c_uint32)]
+    lib.pb_server_add_graph.restype = ctypes.c_int
+    lib.pb_server_submit.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, P, P, P, ctypes.POINTER(ctypes.c_uint64)]
+    lib.pb_server_submit.restype = ctypes.c_int
+    lib.pb_server_poll.argtypes = [P, ctypes.POINTER(pb_completion), ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]
+    lib.pb_server_poll.restype = ctypes.c_int
+    lib.pb_server_drain.argtypes = [P]
+    lib.pb_server_drain.restype = ctypes.c_int
+    lib.pb_server_destroy.argtypes = [P]
+    lib.pb_server_destroy.restype = None
+    lib._server_api = True
+    return lib
+
+
+class Server:
+    """Resident-graph counting server (continuous batching over worker slots)."""
+
+    def __init__(self, hbm_budget=0, slots=2, max_batch=64, agg="auto", tuning=None):
+        lib = _load_server_api()
+        self._tuning = tuning
+        cfg = pb_server_config(int(hbm_budget), int(slots), int(max_batch), AGGS[agg] if isinstance(agg, str) else agg,
+                               ctypes.pointer(tuning) if tuning is not None else None)
+        h = ctypes.c_void_p()
+        _check(lib.pb_server_create(ctypes.byref(cfg), ctypes.byref(h)), "pb_server_create")
+        self._h = h
+        self._keep = []  # graphs, ranks and output tensors the server references
+
+    def add_graph(self, g: Graph, rank) -> int:
+        torch = _torch()
+        gid = ctypes.c_uint32()
+        _check(_load_server_api().pb_server_add_graph(self._h, g.handle, _dev_ptr(rank, torch.int32, "rank"),
+                                                      ctypes.byref(gid)), "pb_server_add_graph")
+        self._keep.append((g, rank))
+        return gid.value
+
+    def submit(self, graph_id: int, want: int, gout=None, vout=None, eout=None) -> int:
+        rid = ctypes.c_uint64()
+        p = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+        _check(_load_server_api().pb_server_submit(self._h, int(graph_id), int(want), p(gout), p(vout), p(eout),
+                                                   ctypes.byref(rid)), "pb_server_submit")
+        self._keep.append((gout, vout, eout))
+        return rid.value
+
+    def poll(self, max_items=4096):
+        buf = (pb_completion * max_items)()
+        n = ctypes.c_uint32()
+        _check(_load_server_api().pb_server_poll(self._h, buf, max_items, ctypes.byref(n)), "pb_server_poll")
+        return [buf[i] for i in range(n.value)]
+
+    def drain(self):
+        _check(_load_server_api().pb_server_drain(self._h), "pb_server_drain")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _load_server_api().pb_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

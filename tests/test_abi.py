@@ -80,3 +80,22 @@ def test_bad_opts_rejected(lib):
     t = pb.pb_tuning(4096, 512, 1, 1, 2)  # light_max above the light kernel's capacity
     o = pb.make_opts(tuning=t)
     assert lib.pb_count(fake, fake, ctypes.byref(o), fake, None, None, None) == -1
+
+
+def test_server_argument_checks(lib):
+    import paper_1907_08607_amd as pb
+    lib = pb._load_server_api()
+    h = ctypes.c_void_p()
+    assert lib.pb_server_create(None, ctypes.byref(h)) == -1
+    cfg = pb.pb_server_config(0, 0, 8, 0, None)  # no slots
+    assert lib.pb_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
+    cfg = pb.pb_server_config(0, 2, 0, 0, None)  # empty batches
+    assert lib.pb_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
+    cfg = pb.pb_server_config(0, 2, 8, 7, None)  # unknown aggregator
+    assert lib.pb_server_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
+    rid = ctypes.c_uint64()
+    assert lib.pb_server_submit(None, 0, 1, None, None, None, ctypes.byref(rid)) == -1
+    n = ctypes.c_uint32()
+    assert lib.pb_server_poll(None, None, 0, ctypes.byref(n)) == -1
+    assert lib.pb_server_drain(None) == -1
+    lib.pb_server_destroy(None)

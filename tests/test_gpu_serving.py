@@ -1,0 +1,109 @@
+"""GPU: the serving runtime returns, for every request, exactly what the same
+query returns alone, while requests are batched and overlap on the device."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1907_08607_amd import graphgen as gg
+
+torch = pytest.importorskip("torch")
+pb = pytest.importorskip("paper_1907_08607_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    pb.load_library()
+
+
+def pool(count=30, seed=7):
+    rng = np.random.default_rng(seed)
+    gs = []
+    for i in range(count):
+        n_u = int(np.exp(rng.uniform(np.log(16), np.log(800))))
+        n_v = int(np.exp(rng.uniform(np.log(16), np.log(800))))
+        m = max(1, min(int(np.exp(rng.uniform(np.log(32), np.log(30_000)))), n_u * n_v // 4))
+        gs.append(gg.batch_graph(n_u, n_v, m, 5000 + i))
+    gs.append(gg.workload_powerlaw_50m(scale=0.004))
+    return gs
+
+
+def run_trace(srv, Gs, gids, trace):
+    outs = []
+    for gi, want in trace:
+        G = Gs[gi]
+        o = (torch.full((1,), -1, dtype=torch.int64, device="cuda") if want & 1 else None,
+             torch.full((G.n,), -1, dtype=torch.int64, device="cuda") if want & 2 else None,
+             torch.full((max(G.m, 1),), -1, dtype=torch.int64, device="cuda") if want & 4 else None)
+        srv.submit(gids[gi], want, *o)
+        outs.append(o)
+    srv.drain()
+    return outs
+
+
+def test_serving_results_equal_alone_and_in_the_mix():
+    gs = pool()
+    Gs = [pb.Graph.from_csr(g) for g in gs]
+    ranks = [pb.pb_rank(G, "degree") for G in Gs]
+    srv = pb.Server(slots=3, max_batch=8)
+    gids = [srv.add_graph(G, r) for G, r in zip(Gs, ranks)]
+    rng = np.random.default_rng(11)
+    trace = [(int(rng.integers(0, len(gs))), int(rng.choice([1, 2, 4, 5, 7]))) for _ in range(160)]
+    outs = run_trace(srv, Gs, gids, trace)
+    comps = srv.poll()
+    assert len(comps) == len(trace)
+    assert all(c.status == 0 for c in comps)
+    assert max(c.batch for c in comps) > 1  # requests were batched
+    assert all(c.done_s >= c.start_s >= c.submit_s for c in comps)
+    alone = {}
+    for (gi, want), (go, vo, eo) in zip(trace, outs):
+        if gi not in alone:
+            a = pb.pb_count(Gs[gi], ranks[gi])
+            torch.cuda.synchronize()
+            alone[gi] = [t.cpu() for t in a]
+        ag, av, ae = alone[gi]
+        if go is not None:
+            assert torch.equal(go.cpu(), ag)
+        if vo is not None:
+            assert torch.equal(vo.cpu(), av)
+        if eo is not None and Gs[gi].m:
+            assert torch.equal(eo.cpu()[:Gs[gi].m], ae)
+    for gi in list(alone)[:6]:  # and against the oracle
+        want = oracle.count(gs[gi])
+        assert int(alone[gi][0][0]) == want[0]
+        assert (alone[gi][2].numpy() == want[2]).all()
+    srv.close()
+
+
+def test_admission_by_footprint():
+    gs = pool(6, 9)
+    Gs = [pb.Graph.from_csr(g) for g in gs]
+    ranks = [pb.pb_rank(G, "degree") for G in Gs]
+    # a budget that holds the pool but no scratch: every request is refused
+    resident = sum(8 * (G.n_u + 1) + 4 * G.m + 8 * G.m + 4 * (G.n_v + 1) + 8 * G.n for G in Gs)
+    srv = pb.Server(hbm_budget=resident + 1024, slots=2, max_batch=4)
+    gids = [srv.add_graph(G, r) for G, r in zip(Gs, ranks)]
+    with pytest.raises(pb.PBError) as e:
+        srv.submit(gids[0], 1, torch.empty(1, dtype=torch.int64, device="cuda"))
+    assert e.value.status == -5
+    srv.close()
+    # a pool larger than the budget is refused at admission
+    srv = pb.Server(hbm_budget=1 << 16, slots=1, max_batch=1)
+    with pytest.raises(pb.PBError) as e:
+        for G, r in zip(Gs, ranks):
+            srv.add_graph(G, r)
+    assert e.value.status == -5
+    srv.close()
+    # a budget that fits one request's scratch at a time still serves everything
+    one = max(128 * G.m + 112 * G.n + (1 << 16) for G in Gs)
+    srv = pb.Server(hbm_budget=resident + one + 4096, slots=3, max_batch=8)
+    gids = [srv.add_graph(G, r) for G, r in zip(Gs, ranks)]
+    outs = run_trace(srv, Gs, gids, [(i % len(Gs), 1) for i in range(20)])
+    comps = srv.poll()
+    assert len(comps) == 20 and all(c.status == 0 for c in comps)
+    for i, (go, _, _) in enumerate(outs):
+        assert int(go.cpu()[0]) == oracle.count(gs[i % len(gs)], False, False)[0]
+    srv.close()
