@@ -515,23 +515,46 @@ struct SearchRange {
 
 // Windows of one source taken from the highest ids down: each run's part in
 // the window starts where its part in the previous window ended (cursor `cur`,
-// one per up-slot), and ends at the first entry below lo, found by galloping
-// from the cursor.  Pass 1 stores the end in `nxt`; pass 2 (or pass 1 when
-// there is no pass 2) advances the cursor.
+// one per up-slot) and ends at the first entry below lo.  The value at the
+// cursor is kept beside it (`cval`, 0 once the run is used up), so a run with
+// nothing in the window is recognised without reading the run; otherwise the
+// end is found by galloping from the cursor.  Pass 1 stores the new cursor and
+// its value in nxt/nval; pass 2 (or pass 1 when there is no pass 2) commits
+// them, so a refused window leaves the cursors as they were.
 struct CursorRange {
-    uint32_t *cur, *nxt;
+    uint32_t *cur, *nxt, *cval, *nval;
     uint32_t lo;
     bool first, two_pass;
     __device__ void operator()(const Ranked &G, int pass, uint32_t k, uint32_t start, uint32_t pos, uint32_t &a,
                                uint32_t &cnt) const {
-        const uint32_t s = first ? 0u : cur[k];
+        const uint32_t *p = G.nbr + start;
+        uint32_t s, v;
+        if (first) {
+            s = 0;
+            v = pos ? p[0] : 0u;
+        } else {
+            s = cur[k];
+            v = cval[k];
+        }
         uint32_t e;
         if (pass == 1) {
-            e = gallop_below(G.nbr + start, s, pos, lo);
-            if (two_pass) nxt[k] = e; else cur[k] = e;
+            e = s;
+            uint32_t ev = v;
+            if (s < pos && v >= lo) {
+                e = gallop_below(p, s, pos, lo);
+                ev = e < pos ? p[e] : 0u;
+            }
+            if (two_pass) {
+                nxt[k] = e;
+                nval[k] = ev;
+            } else {
+                cur[k] = e;
+                cval[k] = ev;
+            }
         } else {
             e = nxt[k];
             cur[k] = e;
+            cval[k] = nval[k];
         }
         a = s;
         cnt = e - s;
@@ -569,14 +592,157 @@ __device__ inline uint32_t last_le(const uint32_t *off, uint32_t lo, uint32_t n,
 // per-edge credit atomics are coalesced.  For each 64 wedges the wave keeps the
 // (at most 64) runs they touch one per lane, and a lane finds its run with a
 // 6-step shuffle search.
+// Lays the non-empty run parts of this thread's run (a, cnt at slot start)
+// end to end over the block: sh.off/begin/kidx get the compacted table;
+// returns (total wedges, parts).  Zeroes the parts' run sums.
+template <int T>
+__device__ inline void compact_runs(uint32_t k, uint32_t start, uint32_t a, uint32_t cnt, RunShared<T> &sh,
+                                    uint32_t *total, uint32_t *nne) {
+    // one scan gives both the flat offset (low 32 bits) and the compacted
+    // index (high 32 bits) of every non-empty part
+    const unsigned long long packed = ((unsigned long long)(cnt > 0) << 32) | cnt;
+    unsigned long long tot64;
+    const unsigned long long pre = block_exclusive_sum<T>(packed, sh.tmp64, &tot64);
+    *total = (uint32_t)tot64;
+    *nne = (uint32_t)(tot64 >> 32);
+    if (cnt > 0) {
+        const uint32_t ci = (uint32_t)(pre >> 32);
+        sh.off[ci] = (uint32_t)pre;
+        sh.begin[ci] = start + a;
+        sh.kidx[ci] = k;
+        sh.sum[ci] = 0;
+    }
+    __syncthreads();
+}
+
+// Walks the compacted wedge sequence of one chunk (see count_item): pass 1
+// inserts each x2 into the aggregator; pass 2 credits R-1 to the slot
+// (y -> x2) and sums it per run into sh.sum.
+template <int T, int U, class Agg>
+__device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, RunShared<T> &sh, int pass,
+                                 uint32_t total, uint32_t nne) {
+    const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+    const bool edge = A.mode & MODE_EDGE;
+    // runs i0 .. i0+63 held one per lane: o = flat start, bg = slot
+    uint32_t i0 = 0, o = 0, bg = 0, o_end = 0;
+    for (uint32_t wb = wv * (U * WAVE); wb < total; wb += T * U) {
+        uint32_t pidx[U], rel[U], xs[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t base = wb + u * WAVE;
+            ok[u] = base + lane < total;
+            rel[u] = WAVE;
+            pidx[u] = 0;
+            if (base < total) {  // wave-uniform
+                const uint32_t last = base + WAVE - 1 < total ? base + WAVE - 1 : total - 1;
+                if (last >= o_end) {
+                    // reload: the 64 runs from the one holding `base` always
+                    // cover [base, base + 64)
+                    i0 = last_le(sh.off, i0, nne, base);
+                    const uint32_t kk = i0 + lane;
+                    o = kk < nne ? sh.off[kk] : 0xFFFFFFFFu;
+                    bg = kk < nne ? sh.begin[kk] : 0u;
+                    o_end = i0 + WAVE < nne ? sh.off[i0 + WAVE] : total;
+                }
+                const uint32_t f = base + lane;
+                uint32_t lo = 0;
+#pragma unroll
+                for (int step = WAVE / 2; step >= 1; step >>= 1) {
+                    const uint32_t cand = lo + step;
+                    if (__shfl(o, cand, WAVE) <= f) lo = cand;
+                }
+                const uint32_t ro = __shfl(o, lo, WAVE), rb = __shfl(bg, lo, WAVE);
+                pidx[u] = rb + (f - ro);
+                if (ok[u]) rel[u] = i0 + lo;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (ok[u]) xs[u] = G.nbr[pidx[u]];
+        if (pass == 1) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (ok[u]) agg.insert(xs[u]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (wb + u * WAVE >= total) break;  // wave-uniform
+                uint32_t d = ok[u] ? agg.count(xs[u]) - 1 : 0u;
+                if (d && edge) A.slot_add(pidx[u], d);
+                // segmented sum of d over lanes of the same run (runs are
+                // lane-contiguous); d < 2^22 so 64 of them fit 32 bits
+#pragma unroll
+                for (int sft = 1; sft < WAVE; sft <<= 1) {
+                    const uint32_t t = __shfl_down(d, sft, WAVE);
+                    const uint32_t tr = __shfl_down(rel[u], sft, WAVE);
+                    if (lane + sft < WAVE && tr == rel[u]) d += t;
+                }
+                const uint32_t prev = __shfl_up(rel[u], 1, WAVE);
+                if (ok[u] && d && (lane == 0 || prev != rel[u])) atomicAdd(&sh.sum[rel[u]], (unsigned long long)d);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Pass-2 run sums of one chunk: the center credit (per-vertex) and the credit
+// of the slot (r -> y) (per-edge).
+template <int T>
+__device__ inline void flush_runs(const Ranked &G, const Acc &A, uint32_t r, uint32_t k0, RunShared<T> &sh,
+                                  uint32_t nne) {
+    const uint32_t tid = threadIdx.x;
+    if (tid < nne) {
+        const unsigned long long sm = sh.sum[tid];
+        if (sm) {
+            const uint32_t up = G.roff[r] + (sh.kidx[tid] - k0);  // slot (r -> y)
+            if (A.mode & MODE_VERTEX) atomicAdd(&A.v[G.nbr[up]], sm);
+            if (A.mode & MODE_EDGE) A.slot_add(up, sm);
+        }
+    }
+    __syncthreads();
+}
+
+// The endpoint step after pass 1: C(R,2) per pair into the total and, for
+// per-vertex counts, into both endpoints.
+template <int T, class Agg>
+__device__ inline void endpoint_credit(const Ranked &G, const Acc &A, uint32_t r, const Agg &agg, RunShared<T> &sh) {
+    unsigned long long local = 0;
+    const bool vert = A.mode & MODE_VERTEX;
+    agg.for_each([&](uint32_t key, uint32_t cc) {
+        if (cc >= 2) {
+            const unsigned long long t = (unsigned long long)cc * (cc - 1) / 2;
+            local += t;
+            if (vert) atomicAdd(&A.v[key], t);
+        }
+    });
+    const unsigned long long tot = block_sum<T>(local, sh.tmp64);
+    if (threadIdx.x == 0 && tot) {
+        if (A.mode & MODE_GLOBAL) atomicAdd(&A.g[G.gid ? G.gid[r] : 0u], tot);
+        if (vert) atomicAdd(&A.v[G.smid[r]], tot);
+    }
+    __syncthreads();
+}
+
+// One work item: source r and the part of each of its runs that `range`
+// selects.  Pass 1 retrieves the wedges (Algorithm 2) into the aggregator
+// (GET-FREQ); the endpoint step adds C(R,2) per pair (total, and both
+// endpoints for per-vertex); pass 2 walks the wedges again and adds R-1 to
+// each center / both edges (Algorithms 3, 4).
+//
+// Up-slots are taken T at a time; the non-empty run parts are compacted and
+// laid end to end (block scan).  Each wave walks that flat sequence U*64
+// wedges at a time with lane-consecutive wedges, so the reads of x2 and the
+// per-edge credit atomics are coalesced.  For each 64 wedges the wave keeps the
+// (at most 64) runs they touch one per lane, and a lane finds its run with a
+// 6-step shuffle search.
 template <int T, int U, class Agg, class Range>
 __device__ bool count_item(const Ranked &G, const Acc &A, uint32_t r, const Agg &agg, const Range &range,
                            RunShared<T> &sh, int passes) {
-    const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+    const uint32_t tid = threadIdx.x;
     const uint32_t k0 = G.upoff[r], k1 = G.upoff[r + 1];
     agg.init();
     __syncthreads();
-    const bool edge = A.mode & MODE_EDGE;
     const bool credit = A.mode & (MODE_VERTEX | MODE_EDGE);
     for (int pass = 1; pass <= passes; ++pass) {
         for (uint32_t c = k0; c < k1; c += T) {
@@ -586,114 +752,58 @@ __device__ bool count_item(const Ranked &G, const Acc &A, uint32_t r, const Agg 
                 start = G.uprun[k];
                 range(G, pass, k, start, G.uplen[k], a, cnt);
             }
-            // one scan gives both the flat offset (low 32 bits) and the
-            // compacted index (high 32 bits) of every non-empty part
-            const unsigned long long packed = ((unsigned long long)(cnt > 0) << 32) | cnt;
-            unsigned long long tot64;
-            const unsigned long long pre = block_exclusive_sum<T>(packed, sh.tmp64, &tot64);
-            const uint32_t total = (uint32_t)tot64, nne = (uint32_t)(tot64 >> 32);
-            if (cnt > 0) {
-                const uint32_t ci = (uint32_t)(pre >> 32);
-                sh.off[ci] = (uint32_t)pre;
-                sh.begin[ci] = start + a;
-                sh.kidx[ci] = k;
-                if (pass == 2) sh.sum[ci] = 0;
-            }
-            __syncthreads();
-            // runs i0 .. i0+63 held one per lane: o = flat start, bg = slot
-            uint32_t i0 = 0, o = 0, bg = 0, o_end = 0;
-            const uint32_t walk = pass == 1 || credit ? total : 0u;
-            for (uint32_t wb = wv * (U * WAVE); wb < walk; wb += T * U) {
-                uint32_t pidx[U], rel[U], xs[U];
-                bool ok[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const uint32_t base = wb + u * WAVE;
-                    ok[u] = base + lane < total;
-                    rel[u] = WAVE;
-                    pidx[u] = 0;
-                    if (base < total) {  // wave-uniform
-                        const uint32_t last = base + WAVE - 1 < total ? base + WAVE - 1 : total - 1;
-                        if (last >= o_end) {
-                            // reload: the 64 runs from the one holding `base`
-                            // always cover [base, base + 64)
-                            i0 = last_le(sh.off, i0, nne, base);
-                            const uint32_t kk = i0 + lane;
-                            o = kk < nne ? sh.off[kk] : 0xFFFFFFFFu;
-                            bg = kk < nne ? sh.begin[kk] : 0u;
-                            o_end = i0 + WAVE < nne ? sh.off[i0 + WAVE] : total;
-                        }
-                        const uint32_t f = base + lane;
-                        uint32_t lo = 0;
-#pragma unroll
-                        for (int step = WAVE / 2; step >= 1; step >>= 1) {
-                            const uint32_t cand = lo + step;
-                            if (__shfl(o, cand, WAVE) <= f) lo = cand;
-                        }
-                        const uint32_t ro = __shfl(o, lo, WAVE), rb = __shfl(bg, lo, WAVE);
-                        pidx[u] = rb + (f - ro);
-                        if (ok[u]) rel[u] = i0 + lo;
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (ok[u]) xs[u] = G.nbr[pidx[u]];
-                if (pass == 1) {
-#pragma unroll
-                    for (int u = 0; u < U; ++u)
-                        if (ok[u]) agg.insert(xs[u]);
-                } else {
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        if (wb + u * WAVE >= total) break;  // wave-uniform
-                        uint32_t d = ok[u] ? agg.count(xs[u]) - 1 : 0u;
-                        if (d && edge) A.slot_add(pidx[u], d);
-                        // segmented sum of d over lanes of the same run (runs are
-                        // lane-contiguous); d < 2^22 so 64 of them fit 32 bits
-#pragma unroll
-                        for (int sft = 1; sft < WAVE; sft <<= 1) {
-                            const uint32_t t = __shfl_down(d, sft, WAVE);
-                            const uint32_t tr = __shfl_down(rel[u], sft, WAVE);
-                            if (lane + sft < WAVE && tr == rel[u]) d += t;
-                        }
-                        const uint32_t prev = __shfl_up(rel[u], 1, WAVE);
-                        if (ok[u] && d && (lane == 0 || prev != rel[u]))
-                            atomicAdd(&sh.sum[rel[u]], (unsigned long long)d);
-                    }
-                }
-            }
-            __syncthreads();
-            if (pass == 2 && tid < nne) {
-                const unsigned long long sm = sh.sum[tid];
-                if (sm) {
-                    const uint32_t up = G.roff[r] + (sh.kidx[tid] - k0);  // slot (r -> y)
-                    if (A.mode & MODE_VERTEX) atomicAdd(&A.v[G.nbr[up]], sm);
-                    if (edge) A.slot_add(up, sm);
-                }
-            }
-            __syncthreads();
+            uint32_t total, nne;
+            compact_runs<T>(k, start, a, cnt, sh, &total, &nne);
+            if (pass == 1 || credit) walk_runs<T, U>(G, A, agg, sh, pass, total, nne);
+            if (pass == 2) flush_runs<T>(G, A, r, k0, sh, nne);
         }
         if (pass == 1) {
             if (!agg.finalize()) return false;  // (uniform) capacity exceeded: caller retries
-            unsigned long long local = 0;
-            const bool vert = A.mode & MODE_VERTEX;
-            agg.for_each([&](uint32_t key, uint32_t cc) {
-                if (cc >= 2) {
-                    const unsigned long long t = (unsigned long long)cc * (cc - 1) / 2;
-                    local += t;
-                    if (vert) atomicAdd(&A.v[key], t);
-                }
-            });
-            const unsigned long long tot = block_sum<T>(local, sh.tmp64);
-            if (tid == 0 && tot) {
-                if (A.mode & MODE_GLOBAL) atomicAdd(&A.g[G.gid ? G.gid[r] : 0u], tot);
-                if (vert) atomicAdd(&A.v[G.smid[r]], tot);
-            }
-            __syncthreads();
+            endpoint_credit<T>(G, A, r, agg, sh);
         }
     }
     __syncthreads();
     return true;
+}
+
+// A heavy source with at most T up-slots: every thread keeps one run (slot
+// start, length, cursor and the value at the cursor) in registers across the
+// whole sweep of windows, and pass 2 reuses pass 1's compacted run table.
+template <int T, int U>
+__device__ void sweep_small(const Ranked &G, const Acc &A, uint32_t r, uint32_t *words, bool half, uint32_t ws,
+                            RunShared<T> &sh) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t k0 = G.upoff[r], k1 = G.upoff[r + 1];
+    const uint32_t k = k0 + tid;
+    const bool have = k < k1;
+    const uint32_t start = have ? G.uprun[k] : 0u, pos = have ? G.uplen[k] : 0u;
+    const uint32_t *p = G.nbr + start;
+    uint32_t cur = 0, val = pos ? p[0] : 0u;
+    const bool credit = A.mode & (MODE_VERTEX | MODE_EDGE);
+    const uint32_t lo_min = G.smid[r] + 1;
+    uint32_t hi = G.cend[r];
+    while (hi > lo_min) {
+        const uint32_t lo = hi - lo_min > ws ? hi - ws : lo_min;
+        DenseAgg<T> agg{words, lo, hi - lo, half, A.err};
+        agg.init();
+        uint32_t e = cur, ev = val;
+        if (cur < pos && val >= lo) {
+            e = gallop_below(p, cur, pos, lo);
+            ev = e < pos ? p[e] : 0u;
+        }
+        __syncthreads();
+        uint32_t total, nne;
+        compact_runs<T>(k, start, cur, e - cur, sh, &total, &nne);
+        walk_runs<T, U>(G, A, agg, sh, 1, total, nne);
+        endpoint_credit<T>(G, A, r, agg, sh);
+        if (credit) {
+            walk_runs<T, U>(G, A, agg, sh, 2, total, nne);
+            flush_runs<T>(G, A, r, k0, sh, nne);
+        }
+        cur = e;
+        val = ev;
+        hi = lo;
+    }
 }
 
 template <int T, int U, int CAP>
@@ -730,7 +840,7 @@ __global__ __launch_bounds__(T) void k_count_hash_win(Ranked G, Acc A, const uin
 // R(x1, x2) <= deg_x1(x1); else 32768 ids).
 template <int T, int U>
 __global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32_t *list, uint32_t *cur, uint32_t *nxt,
-                                                   uint32_t count) {
+                                                   uint32_t *cval, uint32_t *nval, uint32_t count) {
     __shared__ uint32_t words[WIN_WORDS];
     __shared__ RunShared<T> sh;
     const bool two_pass = A.mode & (MODE_VERTEX | MODE_EDGE);
@@ -738,13 +848,17 @@ __global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32
         const uint32_t r = list[i];
         const bool half = G.upoff[r + 1] - G.upoff[r] <= 0xFFFFu;
         const uint32_t ws = half ? 2 * WIN_WORDS : WIN_WORDS;
+        if (G.upoff[r + 1] - G.upoff[r] <= (uint32_t)T) {
+            sweep_small<T, U>(G, A, r, words, half, ws, sh);
+            continue;
+        }
         const uint32_t lo_min = G.smid[r] + 1;
         uint32_t hi = G.cend[r];
         bool first = true;
         while (hi > lo_min) {
             const uint32_t lo = hi - lo_min > ws ? hi - ws : lo_min;
             DenseAgg<T> agg{words, lo, hi - lo, half, A.err};
-            count_item<T, U>(G, A, r, agg, CursorRange{cur, nxt, lo, first, two_pass}, sh, A.passes());
+            count_item<T, U>(G, A, r, agg, CursorRange{cur, nxt, cval, nval, lo, first, two_pass}, sh, A.passes());
             hi = lo;
             first = false;
         }
@@ -781,7 +895,8 @@ __global__ __launch_bounds__(T) void k_count_sort(Ranked G, Acc A, const uint32_
 // they were).
 template <int T, int U, int CAP>
 __global__ __launch_bounds__(T) void k_count_sort_heavy(Ranked G, Acc A, const uint32_t *list, const uint64_t *wsrc,
-                                                        uint32_t *cur, uint32_t *nxt, uint32_t count) {
+                                                        uint32_t *cur, uint32_t *nxt, uint32_t *cval, uint32_t *nval,
+                                                        uint32_t count) {
     static_assert(16 * T >= CAP, "count array too small");
     __shared__ SortShared<T, CAP> ss;
     __shared__ RunShared<T> sh;
@@ -796,7 +911,7 @@ __global__ __launch_bounds__(T) void k_count_sort_heavy(Ranked G, Acc A, const u
         while (hi > lo_min) {
             const uint32_t lo = hi - lo_min > width ? hi - width : lo_min;
             SortAgg<T, CAP> agg{ss.a, ss.b, ss.cnt, ss.start, ss.meta, ss.tmp, lo, hi - lo};
-            if (!count_item<T, U>(G, A, r, agg, CursorRange{cur, nxt, lo, first, true}, sh, 2)) {
+            if (!count_item<T, U>(G, A, r, agg, CursorRange{cur, nxt, cval, nval, lo, first, true}, sh, 2)) {
                 width = (hi - lo) / 2 ? (hi - lo) / 2 : 1u;
                 continue;
             }
@@ -1054,7 +1169,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         const uint32_t *sorted_src[NSORTED] = {nullptr, nullptr, nullptr};
         const uint64_t *sorted_w[NSORTED] = {nullptr, nullptr, nullptr};
         uint2 *items = nullptr;
-        uint32_t *cur = nullptr, *nxt = nullptr;
+        uint32_t *cur = nullptr, *nxt = nullptr, *cval = nullptr, *nval = nullptr;
         for (int l = 0; l < NLISTS; ++l) {
             const int sk = sorted_slot(l);
             const uint32_t nh = plan.list[l];
@@ -1081,6 +1196,8 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
             } else if (!cur) {
                 cur = ws.alloc<uint32_t>(m);
                 nxt = ws.alloc<uint32_t>(m);
+                cval = ws.alloc<uint32_t>(m);
+                nval = ws.alloc<uint32_t>(m);
                 if (ws.failed) return PB_ERR_NO_MEMORY;
             }
             PB_TRY_HIP(hipGetLastError());
@@ -1097,11 +1214,11 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
             if (c) {
                 switch (l) {
                     case L_DENSE_HEAVY:
-                        launch_items(k_count_heavy<1024, 4>, c, 1024, s, G, A, sorted_src[2], cur, nxt);
+                        launch_items(k_count_heavy<1024, 4>, c, 1024, s, G, A, sorted_src[2], cur, nxt, cval, nval);
                         break;
                     case L_SORT_HEAVY:
                         launch_items(k_count_sort_heavy<256, 4, SORT_W>, c, 256, s, G, A, sorted_src[1], sorted_w[1],
-                                     cur, nxt);
+                                     cur, nxt, cval, nval);
                         break;
                     case L_HASH_WIN:
                         launch_items(k_count_hash_win<256, 4, 2 * HASH_WIN>, plan.items, 256, s, G, A,
