@@ -34,7 +34,18 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="powerlaw_50m", choices=["powerlaw_50m", "hub_100m", "er_1k"])
+    ap.add_argument("--workload", default="powerlaw_50m",
+                    choices=["powerlaw_50m", "hub_100m", "er_1k", "batch", "serve"])
+    ap.add_argument("--graphs", type=int, default=4096, help="batch: graphs in the batch")
+    ap.add_argument("--pool-small", type=int, default=10_000, help="serve: resident small graphs")
+    ap.add_argument("--pool-big", type=int, default=50, help="serve: resident 5M-edge graphs")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve: Poisson arrivals per second")
+    ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of arrivals")
+    ap.add_argument("--slots", type=int, default=4, help="serve: concurrent batches")
+    ap.add_argument("--max-batch", type=int, default=64, help="serve: requests per batch")
+    ap.add_argument("--seq-requests", type=int, default=20_000,
+                    help="serve: first requests of the trace replayed by the sequential baseline")
+    ap.add_argument("--tune", action="store_true", help="batch: autotune the per-bucket table first")
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (tests only)")
     ap.add_argument("--rank", default=None, help="ordering (default: the workload's own)")
     ap.add_argument("--agg", default="auto", choices=["auto", "hash", "dense", "sort"])
@@ -88,6 +99,142 @@ def cpu_baseline(g, wedges, target_s):
             "est_full_s": est}
 
 
+def upload(graphs, pb):
+    return [pb.Graph.from_csr(g) for g in graphs]
+
+
+def run_batch(args):
+    """Batched workload: many uneven graphs counted in one pass vs one launch per graph."""
+    import numpy as np
+    import torch
+
+    import paper_1907_08607_amd as pb
+    from paper_1907_08607_amd import graphgen as gg
+
+    t0 = time.time()
+    graphs = gg.workload_batch(args.graphs, seed=4)
+    print(f"[bench] {len(graphs)} graphs generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    Gs = upload(graphs, pb)
+    ranks = [pb.pb_rank(G, "degree") for G in Gs]
+    outs = (None, None, [torch.empty(max(G.m, 1), dtype=torch.int64, device="cuda") for G in Gs])
+    tuning = None
+    if args.tune:
+        sample = list(range(0, len(Gs), max(1, len(Gs) // 256)))
+        tuning = pb.pb_autotune([Gs[i] for i in sample], [ranks[i] for i in sample], repeats=3)
+        print(f"[bench] autotuned table {tuning.as_dict()}", file=sys.stderr, flush=True)
+    stats = pb.pb_stats()
+    for _ in range(args.warmup):
+        pb.pb_count_batched(Gs, ranks, False, False, True, agg=args.agg, tuning=tuning, outs=outs, stats=stats)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        pb.pb_count_batched(Gs, ranks, False, False, True, agg=args.agg, tuning=tuning, outs=outs, stats=stats)
+    torch.cuda.synchronize()
+    batched = (time.perf_counter() - t) / args.steps
+    # the same work, one graph per launch
+    single_outs = [torch.empty(max(G.m, 1), dtype=torch.int64, device="cuda") for G in Gs]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for G, r, o in zip(Gs, ranks, single_outs):
+        pb.pb_count(G, r, False, False, True, agg=args.agg, tuning=tuning, outs=(None, None, o))
+    torch.cuda.synchronize()
+    single = time.perf_counter() - t
+    same = all(torch.equal(a[:G.m], b[:G.m]) for a, b, G in zip(outs[2], single_outs, Gs))
+    m_total = sum(G.m for G in Gs)
+    record = {
+        "metric": "graphs/s", "value": len(Gs) / batched, "unit": "graphs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": batched * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "batched_chung_lu", "graphs": len(Gs), "edges_total": m_total,
+                   "sizes": "|U|,|V| log-uniform [64, 20k], m log-uniform [256, 5e5] clamped to |U||V|/4, exp 2.1",
+                   "rank": "degree", "outputs": "edge", "wedges": stats.wedges,
+                   "wedges_per_s": stats.wedges / batched,
+                   "tuning": tuning.as_dict() if tuning is not None else "built-in",
+                   "one_graph_per_launch_graphs_per_s": len(Gs) / single,
+                   "speedup_vs_one_graph_per_launch": single / batched,
+                   "same_results_as_one_graph_per_launch": same},
+    }
+    print(json.dumps(record), flush=True)
+
+
+def run_serve(args):
+    """Serving workload: Poisson arrivals of count queries over a resident pool."""
+    import numpy as np
+    import torch
+
+    import paper_1907_08607_amd as pb
+    from paper_1907_08607_amd import graphgen as gg
+
+    t0 = time.time()
+    small = gg.workload_batch(args.pool_small, seed=5)
+    big = [gg.chung_lu(200_000, 50_000, 5_000_000, 2.1, 50_000.0, 200_000.0, 5_000 + i) for i in range(args.pool_big)]
+    graphs = small + big
+    print(f"[bench] pool of {len(graphs)} graphs generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    Gs = upload(graphs, pb)
+    ranks = [pb.pb_rank(G, "degree") for G in Gs]
+    # one output set per graph (every request on a graph writes the same values)
+    outs = [(torch.empty(1, dtype=torch.int64, device="cuda"), torch.empty(G.n, dtype=torch.int64, device="cuda"),
+             torch.empty(max(G.m, 1), dtype=torch.int64, device="cuda")) for G in Gs]
+    rng = np.random.default_rng(55)
+    n_req = int(args.rate * args.duration)
+    arrivals = np.cumsum(rng.exponential(1.0 / args.rate, n_req))
+    which = rng.integers(0, len(Gs), n_req)
+    kinds = rng.choice([pb.WANT["global"], pb.WANT["vertex"], pb.WANT["edge"]], n_req)
+    torch.cuda.synchronize()
+
+    def lat_stats(lat):
+        lat = np.sort(np.asarray(lat)) * 1e3
+        return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+
+    # continuous batching server
+    srv = pb.Server(hbm_budget=0, slots=args.slots, max_batch=args.max_batch, agg=args.agg)
+    gids = [srv.add_graph(G, r) for G, r in zip(Gs, ranks)]
+    t_base = time.perf_counter()
+    for i in range(n_req):
+        wait = arrivals[i] - (time.perf_counter() - t_base)
+        if wait > 0:
+            time.sleep(wait)
+        o = outs[which[i]]
+        srv.submit(gids[which[i]], int(kinds[i]), o[0], o[1], o[2])
+    srv.drain()
+    comps = srv.poll(n_req + 16)
+    srv.close()
+    assert len(comps) == n_req and all(c.status == 0 for c in comps)
+    lat = [c.done_s - c.submit_s for c in comps]
+    span = max(c.done_s for c in comps) - min(c.submit_s for c in comps)
+    p50, p99 = lat_stats(lat)
+    batch_sizes = [c.batch for c in comps]
+    # sequential one-graph-per-launch serving of the same trace
+    seq_lat = []
+    t_base = time.perf_counter()
+    names = {pb.WANT["global"]: (True, False, False), pb.WANT["vertex"]: (False, True, False),
+             pb.WANT["edge"]: (False, False, True)}
+    n_seq = min(n_req, args.seq_requests)
+    for i in range(n_seq):
+        now = time.perf_counter() - t_base
+        if arrivals[i] > now:
+            time.sleep(arrivals[i] - now)
+        wg, wv, we = names[int(kinds[i])]
+        o = outs[which[i]]
+        pb.pb_count(Gs[which[i]], ranks[which[i]], wg, wv, we, agg=args.agg,
+                    outs=(o[0] if wg else None, o[1] if wv else None, o[2] if we else None))
+        seq_lat.append(time.perf_counter() - t_base - arrivals[i])
+    seq_span = time.perf_counter() - t_base
+    s50, s99 = lat_stats(seq_lat)
+    record = {
+        "metric": "requests/s", "value": n_req / span, "unit": "requests/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": span * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "serving", "pool_small": args.pool_small, "pool_big": args.pool_big,
+                   "rate_per_s": args.rate, "duration_s": args.duration, "requests": n_req, "slots": args.slots,
+                   "max_batch": args.max_batch, "p50_ms": p50, "p99_ms": p99,
+                   "mean_batch": float(np.mean(batch_sizes)),
+                   "sequential_requests": n_seq, "sequential_requests_per_s": n_seq / seq_span, "sequential_p50_ms": s50,
+                   "sequential_p99_ms": s99},
+    }
+    print(json.dumps(record), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -101,6 +248,10 @@ def main():
 
     pb.load_library()
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        return run_batch(args)
+    if args.workload == "serve":
+        return run_serve(args)
     t0 = time.time()
     g, desc, rank_kind = make_graph(args)
     print(f"[bench] graph {desc} built in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)

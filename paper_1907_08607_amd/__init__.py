@@ -262,6 +262,7 @@ def _ptr_array(items):
 
 def pb_count_batched(graphs, ranks, want_global=True, want_vertex=False, want_edge=True, agg="auto", hub="auto",
                      stats: pb_stats | None = None, tuning=None, outs=None, stream=None, timing=False):
+    """outs, if given: (global list or None, vertex list or None, edge list or None)."""
     """Counts a batch of graphs in one pass; returns per-graph (global, vertex, edge) lists."""
     torch = _torch()
     k = len(graphs)
