@@ -27,6 +27,42 @@ sys.path.insert(0, ROOT)
 # per-edge output adds one int64 read-modify-write of the credited slot (16 B)
 BYTES_PER_WEDGE = {"global": 4, "vertex": 8, "edge": 24, "all": 24}
 HBM_PEAK_GBS = 8000.0
+INT8_MFMA_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak of the MI355X
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash():
+    """sha256 over the library's kernel sources (a measured HBM traffic figure
+    is only quoted for the sources it was measured on)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1907_08607_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload, outputs):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy calibration), or None
+    when there is none for these sources, workload and outputs."""
+    path = os.path.join(PROFILES, f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith((" ", "#")):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("source_sha256") != kernel_source_hash() or fields.get("outputs") != outputs:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -35,7 +71,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="powerlaw_50m",
-                    choices=["powerlaw_50m", "hub_100m", "er_1k", "batch", "serve"])
+                    choices=["powerlaw_50m", "hub_100m", "er_1k", "batch", "serve", "copy"])
     ap.add_argument("--graphs", type=int, default=4096, help="batch: graphs in the batch")
     ap.add_argument("--pool-small", type=int, default=10_000, help="serve: resident small graphs")
     ap.add_argument("--pool-big", type=int, default=50, help="serve: resident 5M-edge graphs")
@@ -49,6 +85,7 @@ def parse():
     ap.add_argument("--scale", type=float, default=1.0, help="shrink the workload (tests only)")
     ap.add_argument("--rank", default=None, help="ordering (default: the workload's own)")
     ap.add_argument("--agg", default="auto", choices=["auto", "hash", "dense", "sort"])
+    ap.add_argument("--hub", default="auto", choices=["auto", "off", "force"], help="hub tile mode")
     ap.add_argument("--outputs", default="all", choices=["all", "global", "vertex", "edge"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-target-s", type=float, default=15.0, help="CPU-baseline sample budget")
@@ -97,6 +134,31 @@ def cpu_baseline(g, wedges, target_s):
                       f"of its endpoint side: {t:.1f} s measured, x{stride} = {est:.1f} s estimated full run; "
                       f"wedges = the GPU ordering's wedge count",
             "est_full_s": est}
+
+
+def run_copy(args):
+    """Copy calibration: a plain device-to-device copy of known size, the
+    reference that rocprofv3's FETCH_SIZE / WRITE_SIZE counters are scaled by."""
+    import torch
+    n = 1 << 26  # 256 MiB of int32
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.steps
+    nbytes = 4 * n
+    print(json.dumps({"metric": "copy GB/s", "value": 2 * nbytes / (ms * 1e-3) / 1e9, "unit": "GB/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+                      "config": {"workload": "copy", "bytes_read_per_launch": nbytes,
+                                 "bytes_written_per_launch": nbytes}}), flush=True)
 
 
 def upload(graphs, pb):
@@ -252,6 +314,8 @@ def main():
         return run_batch(args)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload == "copy":
+        return run_copy(args)
     t0 = time.time()
     g, desc, rank_kind = make_graph(args)
     print(f"[bench] graph {desc} built in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
@@ -268,7 +332,7 @@ def main():
     def step(stats):
         G = pb.Graph(g.n_u, g.n_v, off, adj, stream)
         r = pb.pb_rank(G, rank_kind, stream=stream)
-        pb.pb_count(G, r, agg=args.agg, stats=stats, outs=step_outs, stream=stream, timing=True)
+        pb.pb_count(G, r, agg=args.agg, hub=args.hub, stats=stats, outs=step_outs, stream=stream, timing=True)
         G.close()
 
     for i in range(args.warmup):
@@ -289,23 +353,31 @@ def main():
     wedges = stats[0].wedges
     ms_step = elapsed / args.steps * 1e3
     value = wedges * args.steps / elapsed
-    dense_ms = sum(s.ms_dense for s in stats) / len(stats)
-    w_dense = stats[0].wedges_dense
+    mean = lambda k: sum(getattr(s, k) for s in stats) / len(stats)
+    heavy_ms = mean("ms_heavy")
+    w_heavy = stats[0].wedges_heavy
     bpw = BYTES_PER_WEDGE[args.outputs]
-    achieved = (w_dense * bpw / (dense_ms * 1e-3)) / 1e9 if dense_ms > 0 else 0.0
-    phases = {k: round(sum(getattr(s, k) for s in stats) / len(stats), 3)
-              for k in ("ms_prepare", "ms_dense", "ms_hash", "ms_output")}
+    achieved = (w_heavy * bpw / (heavy_ms * 1e-3)) / 1e9 if heavy_ms > 0 else 0.0
+    phases = {k: round(mean(k), 3) for k in ("ms_prepare", "ms_heavy", "ms_dense", "ms_hash", "ms_sort",
+                                              "ms_hub_gemm", "ms_hub_pass", "ms_output")}
+    st0 = stats[0]
+    gemm_ms = mean("ms_hub_gemm")
+    hub = {"mode": args.hub, "rows": st0.hub_rows, "cols": st0.hub_cols, "wedges_hub": st0.wedges_hub,
+           "mfma_int8_ops": st0.hub_mfma_ops,
+           "mfma_tops": st0.hub_mfma_ops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else None}
+    hub["mfma_frac"] = hub["mfma_tops"] / INT8_MFMA_PEAK_TOPS if hub["mfma_tops"] else None
+    traffic = measured_traffic("k_count_heavy", args.workload, args.outputs)
     record = {
         "metric": "wedges/s", "value": value, "unit": "wedges/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": dict(desc, wedges=wedges, butterflies=int(outs[0].cpu()[0]) if 0 in want else None, phases_ms=phases,
-                       wedges_dense=w_dense, wedges_hash=stats[0].wedges_hash,
-                       window_items=stats[0].window_items),
-        "roofline": {"bound": "hbm", "kernel": "k_count_dense", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_wedge": bpw, "wedges_per_launch": w_dense,
-                     "launch_ms": dense_ms},
+                       wedges_heavy=w_heavy, wedges_dense=st0.wedges_dense, wedges_hash=st0.wedges_hash,
+                       wedges_sort=st0.wedges_sort, window_items=st0.window_items, hub=hub),
+        "roofline": {"bound": "hbm", "kernel": "k_count_heavy", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "bytes_per_wedge": bpw, "wedges_per_launch": w_heavy, "launch_ms": heavy_ms},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

@@ -105,7 +105,20 @@ typedef enum {
     PB_AGG_RADIX_SORT = 3
 } pb_agg;
 
-/* Dense int8 matrix-core path for hub-to-hub endpoint pairs. */
+/* Dense int8 matrix-core tile for hub-to-hub endpoint pairs (an addition to
+ * the paper's aggregators; the counts are the same in every mode).  The hubs
+ * are the first 256 vertices, in rank order, of the side that holds the
+ * rank-0 vertex.  For two hubs h1 < h2 the pair count R(h1, h2) of Section
+ * 3.1.2 is one entry of D = A' A^T, where A is the 0/1 hub-by-centre
+ * adjacency and A' keeps the centres ranked above the row's hub; D is formed
+ * on int8 matrix cores with int32 accumulation (exact: entries are bounded by
+ * the number of centres).  The sparse aggregators then skip hub partners of
+ * hub sources.
+ *   AUTO   single graphs with at least 2^22 edges, when a cost model (hub
+ *          pair paths against compacted centre columns) predicts a gain
+ *   OFF    never
+ *   FORCE  every single graph with at least two vertices on the hub side
+ * Batched calls never use the tile. */
 typedef enum {
     PB_HUB_AUTO = 0,
     PB_HUB_OFF = 1,
@@ -133,6 +146,15 @@ typedef struct {
     double ms_hash;           /* hash counting kernels */
     double ms_sort;           /* radix-sort counting kernel */
     double ms_output;         /* output combine */
+    /* The heavy-source dense-window kernel alone. */
+    uint64_t wedges_heavy;    /* wedges it aggregated */
+    double ms_heavy;          /* its time (PB_FLAG_TIMING) */
+    /* Hub tile (zero when it was not used). */
+    uint64_t hub_rows;        /* hubs in the tile */
+    uint64_t hub_cols;        /* compacted centre columns */
+    uint64_t hub_mfma_ops;    /* int8 operations issued on matrix cores */
+    double ms_hub_gemm;       /* the matrix-core kernel (included in ms_prepare) */
+    double ms_hub_pass;       /* the hub pairs' centre and edge credit pass */
 } pb_stats;
 
 /* opts.flags bits */

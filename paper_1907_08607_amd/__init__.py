@@ -48,7 +48,10 @@ class pb_stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_uint64) for name in (
         "wedges", "sources", "sources_hash", "sources_dense", "sources_sort", "window_items",
         "wedges_hash", "wedges_dense", "wedges_sort", "wedges_hub", "workspace_bytes")] + [
-        (name, ctypes.c_double) for name in ("ms_prepare", "ms_dense", "ms_hash", "ms_sort", "ms_output")]
+        (name, ctypes.c_double) for name in ("ms_prepare", "ms_dense", "ms_hash", "ms_sort", "ms_output")] + [
+        ("wedges_heavy", ctypes.c_uint64), ("ms_heavy", ctypes.c_double)] + [
+        (name, ctypes.c_uint64) for name in ("hub_rows", "hub_cols", "hub_mfma_ops")] + [
+        (name, ctypes.c_double) for name in ("ms_hub_gemm", "ms_hub_pass")]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

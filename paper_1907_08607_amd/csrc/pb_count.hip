@@ -45,12 +45,13 @@ inline uint32_t grid_for(uint64_t n, uint32_t block = 256, uint32_t cap = 65536)
 // ---------------------------------------------------------------- relabel
 
 __global__ void k_rank_check(const uint32_t *rank, uint64_t n, uint32_t *order, uint32_t *seen,
-                             uint32_t *flags) {
+                             uint32_t *flags, uint32_t *top) {
     GRID_STRIDE(x, n) {
         const uint32_t r = rank[x];
         if (r >= n) { atomicOr(flags, FLAG_BAD_RANK); continue; }
         if (atomicAdd(&seen[r], 1u) != 0) atomicOr(flags, FLAG_BAD_RANK);
         order[r] = (uint32_t)x;
+        if (r == 0) *top = (uint32_t)x;
     }
 }
 
@@ -133,11 +134,13 @@ enum : int {
     L_SORT_HEAVY,      // 256-thread LDS radix sort over candidate windows
     L_DENSE_HEAVY,     // 1024-thread dense LDS windows swept with cursors
     L_DENSE_SMALL,     // 256-thread dense counters, candidate range <= 4096
+    L_DENSE_GLOBAL,    // giant sources: dense histogram in global scratch, split over workgroups
     NLISTS
 };
-constexpr int NSORTED = 3;  // lists dispatched most-wedges-first
+constexpr int NSORTED = 4;  // lists dispatched most-wedges-first
 __host__ __device__ inline int sorted_slot(int list) {
-    return list == L_HASH_WIN ? 0 : list == L_SORT_HEAVY ? 1 : list == L_DENSE_HEAVY ? 2 : -1;
+    return list == L_HASH_WIN ? 0 : list == L_SORT_HEAVY ? 1 : list == L_DENSE_HEAVY ? 2
+                                  : list == L_DENSE_GLOBAL ? 3 : -1;
 }
 
 constexpr uint32_t LIGHT_D = 512;       // 1-wave hash: 1024 slots
@@ -147,6 +150,14 @@ constexpr uint32_t WIN_WORDS = 32768;   // 128 KB of LDS counters in the heavy d
 constexpr uint32_t HASH_WIN = 4096;     // candidate window of a hash item over a heavy source
 constexpr uint32_t SORT_LIGHT_W = 512;  // wedges sorted by the 1-wave sort kernel
 constexpr uint32_t SORT_W = 2048;       // wedges sorted by the 256-thread sort kernels
+// A dense-aggregated source with this many up-slots would be one long serial
+// chain in a single workgroup; it gets a histogram in global scratch instead,
+// with its up-slots split into items of GH_CHUNK over many workgroups.
+constexpr uint32_t GH_MIN_UPS = 65536;
+constexpr uint32_t GH_CHUNK = 8192;
+constexpr uint32_t GH_SEG = 65536;      // histogram entries per endpoint-step item
+constexpr uint32_t NXCD = 8;            // accelerator complex dies; workgroup b runs on die b % NXCD
+constexpr uint32_t GH_WG_PER_XCD = 256;
 
 // Aggregator per bucket of the distinct-endpoint bound (light, medium, heavy).
 struct Policy {
@@ -158,17 +169,32 @@ struct PlanCounts {
     uint32_t list[NLISTS];
     uint32_t items;  // hash (source, window) items
     uint32_t flags;
+    uint32_t top;    // unified id of the rank-0 vertex
+    uint32_t hub_items;  // (hub, up-slot chunk) items of the hub credit pass
     unsigned long long sources;
     unsigned long long wedges[NLISTS];
+    HubCounters hub;
 };
 
+// First candidate endpoint id of a source with side-major id s: s + 1, or the
+// end of the hub range for a hub (its hub partners are counted by the tile).
+__host__ __device__ inline uint32_t cand_lo(uint32_t s, uint32_t hub_base, uint32_t hub_end) {
+    return (s >= hub_base && s < hub_end) ? hub_end : s + 1;
+}
+
+// Hub sources lose the wedges of their hub partners (counted by the tile).
 __global__ void k_plan(const uint32_t *upoff, const uint64_t *wscan, const uint32_t *smid, const uint32_t *cend,
-                       uint64_t n, Policy pol, uint32_t *lists, uint32_t *nwin, uint64_t *wl, PlanCounts *pc) {
+                       uint64_t n, Policy pol, uint32_t hub_base, uint32_t hub_end, const unsigned long long *roww,
+                       uint32_t *lists, uint32_t *nwin, uint64_t *wl, PlanCounts *pc) {
+    if (!pc->hub.on) hub_end = hub_base;
     GRID_STRIDE(r, n) {
-        const uint64_t w = wscan[upoff[r + 1]] - wscan[upoff[r]];
-        if (w == 0) continue;
+        const uint32_t sm = smid[r];
+        uint64_t w = wscan[upoff[r + 1]] - wscan[upoff[r]];
+        if (sm >= hub_base && sm < hub_end) w -= roww[sm - hub_base];
+        const uint32_t lo = cand_lo(sm, hub_base, hub_end);
+        if (w == 0 || lo >= cend[r]) continue;
         atomicAdd(&pc->sources, 1ull);
-        const uint32_t range = cend[r] - smid[r] - 1;
+        const uint32_t range = cend[r] - lo;
         const uint64_t dist = w < range ? w : range;
         const int bucket = dist <= pol.light_max ? 0 : dist <= pol.medium_max ? 1 : 2;
         int which;
@@ -180,7 +206,9 @@ __global__ void k_plan(const uint32_t *upoff, const uint64_t *wscan, const uint3
                 which = w <= SORT_LIGHT_W ? L_SORT_LIGHT : w <= SORT_W ? L_SORT_MEDIUM : L_SORT_HEAVY;
                 break;
             default:
-                which = range <= SMALL_WIN ? L_DENSE_SMALL : L_DENSE_HEAVY;
+                which = range <= SMALL_WIN                          ? L_DENSE_SMALL
+                        : upoff[r + 1] - upoff[r] >= GH_MIN_UPS ? L_DENSE_GLOBAL
+                                                                : L_DENSE_HEAVY;
                 break;
         }
         const uint32_t slot = atomicAdd(&pc->list[which], 1u);
@@ -258,6 +286,9 @@ struct Ranked {
     const uint32_t *cend;  // per rank: end of its candidate id range (its side of its graph)
     const uint32_t *gid;   // per rank: its graph in a batch (null: one graph)
     uint32_t n_u, n;
+    uint32_t hub_base, hub_end;  // side-major ids of the hub tile's vertices (empty: no tile)
+    // first candidate endpoint id of source r
+    __device__ uint32_t lo(uint32_t r) const { return cand_lo(smid[r], hub_base, hub_end); }
 };
 
 struct Acc {
@@ -495,13 +526,21 @@ struct SortAgg {
 
 // Which part [a, a + cnt) of run k (up-slot k, run N(y)[0, pos) at nbr[start])
 // an item covers, in each pass.
+// The whole run, cut below `lo` for a hub source (whose hub partners sit at
+// the end of each run).
 struct FullRange {
-    __device__ void operator()(const Ranked &, int, uint32_t, uint32_t, uint32_t pos, uint32_t &a,
+    uint32_t lo;
+    bool cut;
+    __device__ void operator()(const Ranked &G, int, uint32_t, uint32_t start, uint32_t pos, uint32_t &a,
                                uint32_t &cnt) const {
         a = 0;
-        cnt = pos;
+        cnt = cut ? first_below(G.nbr + start, 0, pos, lo) : pos;
     }
 };
+__device__ inline FullRange full_range(const Ranked &G, uint32_t r) {
+    const uint32_t lo = G.lo(r);
+    return FullRange{lo, lo != G.smid[r] + 1};
+}
 
 // Candidate window [lo, hi): both ends by binary search.
 struct SearchRange {
@@ -780,7 +819,7 @@ __device__ void sweep_small(const Ranked &G, const Acc &A, uint32_t r, uint32_t 
     const uint32_t *p = G.nbr + start;
     uint32_t cur = 0, val = pos ? p[0] : 0u;
     const bool credit = A.mode & (MODE_VERTEX | MODE_EDGE);
-    const uint32_t lo_min = G.smid[r] + 1;
+    const uint32_t lo_min = G.lo(r);
     uint32_t hi = G.cend[r];
     while (hi > lo_min) {
         const uint32_t lo = hi - lo_min > ws ? hi - ws : lo_min;
@@ -813,7 +852,7 @@ __global__ __launch_bounds__(T) void k_count_hash(Ranked G, Acc A, const uint32_
     __shared__ RunShared<T> sh;
     HashAgg<T, CAP> agg{keys, cnts, A.err};
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x)
-        count_item<T, U>(G, A, list[i], agg, FullRange{}, sh, A.passes());
+        count_item<T, U>(G, A, list[i], agg, full_range(G, list[i]), sh, A.passes());
 }
 
 // Hash over a candidate window of at most CAP/2 ids (forced hash on heavy
@@ -828,7 +867,7 @@ __global__ __launch_bounds__(T) void k_count_hash_win(Ranked G, Acc A, const uin
         const uint2 it = items[i];
         const uint32_t r = it.x, w = it.y;
         const uint32_t side_end = G.cend[r];
-        const uint32_t lo = G.smid[r] + 1 + w * HASH_WIN;
+        const uint32_t lo = G.lo(r) + w * HASH_WIN;
         const uint32_t hi = side_end - lo > HASH_WIN ? lo + HASH_WIN : side_end;
         count_item<T, U>(G, A, r, agg, SearchRange{lo, hi}, sh, A.passes());
     }
@@ -852,7 +891,7 @@ __global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32
             sweep_small<T, U>(G, A, r, words, half, ws, sh);
             continue;
         }
-        const uint32_t lo_min = G.smid[r] + 1;
+        const uint32_t lo_min = G.lo(r);
         uint32_t hi = G.cend[r];
         bool first = true;
         while (hi > lo_min) {
@@ -882,9 +921,9 @@ __global__ __launch_bounds__(T) void k_count_sort(Ranked G, Acc A, const uint32_
     __shared__ RunShared<T> sh;
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
         const uint32_t r = list[i];
-        const uint32_t lo = G.smid[r] + 1, side_end = G.cend[r];
+        const uint32_t lo = G.lo(r), side_end = G.cend[r];
         SortAgg<T, CAP> agg{ss.a, ss.b, ss.cnt, ss.start, ss.meta, ss.tmp, lo, side_end - lo};
-        if (!count_item<T, U>(G, A, r, agg, FullRange{}, sh, A.passes())) atomicOr(A.err, FLAG_INTERNAL);
+        if (!count_item<T, U>(G, A, r, agg, full_range(G, r), sh, A.passes())) atomicOr(A.err, FLAG_INTERNAL);
     }
 }
 
@@ -902,7 +941,7 @@ __global__ __launch_bounds__(T) void k_count_sort_heavy(Ranked G, Acc A, const u
     __shared__ RunShared<T> sh;
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
         const uint32_t r = list[i];
-        const uint32_t lo_min = G.smid[r] + 1;
+        const uint32_t lo_min = G.lo(r);
         uint32_t hi = G.cend[r];
         const uint64_t w = wsrc[i] ? wsrc[i] : 1;
         uint64_t guess = (uint64_t)(hi - lo_min) * (CAP / 2) / w;
@@ -930,9 +969,175 @@ __global__ __launch_bounds__(T) void k_count_dense_src(Ranked G, Acc A, const ui
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
         const uint32_t r = list[i];
         const uint32_t side_end = G.cend[r];
-        const uint32_t lo = G.smid[r] + 1;
+        const uint32_t lo = G.lo(r);
         DenseAgg<T> agg{words, lo, side_end - lo, false, A.err};
-        count_item<T, U>(G, A, r, agg, FullRange{}, sh, A.passes());
+        count_item<T, U>(G, A, r, agg, full_range(G, r), sh, A.passes());
+    }
+}
+
+// ---------------------------------------------------------------- giant sources
+
+// Dense per-source histogram in global scratch (GET-FREQ by histogramming,
+// Section 3.1.2, one counter per candidate endpoint): pass 1 adds one per
+// wedge with an atomic, the endpoint step reads every counter once, pass 2
+// reads R back.  Counters stay in the L2 of one die: all items of a source run
+// on workgroups of the same die.
+struct GlobalAgg {
+    uint32_t *h;
+    uint32_t lo;
+    __device__ void insert(uint32_t x) const { atomicAdd(&h[x - lo], 1u); }
+    __device__ uint32_t count(uint32_t x) const { return h[x - lo]; }
+};
+
+struct GhSrc {
+    uint32_t r, lo, ups, range;  // source rank, first candidate id, up-slots, candidate range
+    uint64_t hoff;               // its counters: hist[hoff .. hoff + range)
+};
+
+__global__ void k_gh_info(Ranked G, const uint32_t *src, uint32_t c, uint32_t *info) {
+    GRID_STRIDE(i, (uint64_t)c) {
+        const uint32_t r = src[i];
+        const uint32_t lo = G.lo(r);
+        info[4 * i] = r;
+        info[4 * i + 1] = lo;
+        info[4 * i + 2] = G.upoff[r + 1] - G.upoff[r];
+        info[4 * i + 3] = G.cend[r] - lo;
+    }
+}
+
+// Walks items (source s, up-slot chunk j) of this workgroup's die: pass 1
+// inserts every wedge into the source's counters, pass 2 credits R - 1.
+template <int T, int U, int PASS>
+__global__ __launch_bounds__(T) void k_gh_walk(Ranked G, Acc A, const GhSrc *src, const uint2 *items,
+                                               const uint32_t *xoff, uint32_t *hist) {
+    __shared__ RunShared<T> sh;
+    const uint32_t x = blockIdx.x % NXCD, per = gridDim.x / NXCD;
+    for (uint32_t j = xoff[x] + blockIdx.x / NXCD; j < xoff[x + 1]; j += per) {
+        const uint2 it = items[j];
+        const GhSrc sr = src[it.x];
+        const uint32_t k0 = G.upoff[sr.r], k1 = G.upoff[sr.r + 1];
+        const uint32_t kb = k0 + it.y * GH_CHUNK;
+        const uint32_t ke = kb + GH_CHUNK < k1 ? kb + GH_CHUNK : k1;
+        const GlobalAgg agg{hist + sr.hoff, sr.lo};
+        const bool cut = sr.lo != G.smid[sr.r] + 1;
+        for (uint32_t c = kb; c < ke; c += T) {
+            const uint32_t k = c + threadIdx.x;
+            uint32_t cnt = 0, start = 0;
+            if (k < ke) {
+                start = G.uprun[k];
+                const uint32_t pos = G.uplen[k];
+                cnt = cut ? first_below(G.nbr + start, 0, pos, sr.lo) : pos;
+            }
+            uint32_t total, nne;
+            compact_runs<T>(k, start, 0u, cnt, sh, &total, &nne);
+            walk_runs<T, U>(G, A, agg, sh, PASS, total, nne);
+            if (PASS == 2) flush_runs<T>(G, A, sr.r, k0, sh, nne);
+        }
+    }
+}
+
+// Endpoint step over the counters: C(R,2) per candidate into the total and,
+// for per-vertex counts, into both endpoints.  Items (source, segment of
+// GH_SEG counters), grouped by die like the walk.
+template <int T>
+__global__ __launch_bounds__(T) void k_gh_endpoint(Ranked G, Acc A, const GhSrc *src, const uint2 *items,
+                                                   const uint32_t *xoff, const uint32_t *hist) {
+    __shared__ unsigned long long tmp[T / WAVE + 1];
+    const bool vert = A.mode & MODE_VERTEX;
+    const uint32_t x = blockIdx.x % NXCD, per = gridDim.x / NXCD;
+    for (uint32_t j = xoff[x] + blockIdx.x / NXCD; j < xoff[x + 1]; j += per) {
+        const uint2 it = items[j];
+        const GhSrc sr = src[it.x];
+        const uint32_t b = it.y * GH_SEG, e = b + GH_SEG < sr.range ? b + GH_SEG : sr.range;
+        const uint32_t *h = hist + sr.hoff;
+        unsigned long long local = 0;
+        for (uint32_t i = b + threadIdx.x; i < e; i += T) {
+            const uint32_t cc = h[i];
+            if (cc >= 2) {
+                const unsigned long long t = (unsigned long long)cc * (cc - 1) / 2;
+                local += t;
+                if (vert) atomicAdd(&A.v[sr.lo + i], t);
+            }
+        }
+        const unsigned long long tot = block_sum<T>(local, tmp);
+        if (threadIdx.x == 0 && tot) {
+            if (A.mode & MODE_GLOBAL) atomicAdd(&A.g[G.gid ? G.gid[sr.r] : 0u], tot);
+            if (vert) atomicAdd(&A.v[G.smid[sr.r]], tot);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- hub credit pass
+
+constexpr uint32_t HUB_CHUNK = 4096;          // up-slots per item of the hub credit pass
+constexpr uint64_t HUB_AUTO_MIN_M = 1u << 22;  // AUTO considers the tile from this many edges
+constexpr uint32_t HUB_PASS_GRID = 4096;
+
+// R of hub pairs, read from the tile (the credit pass needs count() only).
+struct HubAgg {
+    const uint32_t *row;  // D row of the lower endpoint
+    uint32_t base;
+    __device__ void insert(uint32_t) const {}
+    __device__ uint32_t count(uint32_t x) const { return row[x - base]; }
+};
+
+// Items of the hub credit pass: hub i owns ceil(up-slots / HUB_CHUNK)
+// consecutive items starting at hoff[i]; hoff[HUB_T] is the total.
+__global__ __launch_bounds__(HUB_T) void k_hub_items(const uint32_t *upoff, const uint32_t *hub_rank, uint32_t H,
+                                                     uint32_t *hoff, PlanCounts *pc) {
+    __shared__ uint32_t tmp[HUB_T / WAVE + 1];
+    const uint32_t i = threadIdx.x;
+    uint32_t c = 0;
+    if (i < H && pc->hub.on) {
+        const uint32_t r = hub_rank[i];
+        c = (upoff[r + 1] - upoff[r] + HUB_CHUNK - 1) / HUB_CHUNK;
+    }
+    uint32_t total;
+    const uint32_t o = block_exclusive_sum<HUB_T>(c, tmp, &total);
+    hoff[i] = o;
+    if (i == 0) {
+        hoff[HUB_T] = total;
+        pc->hub_items = total;
+    }
+}
+
+// Pass 2 for the hub pairs (Algorithms 3, 4 with R from the tile): for each
+// up-slot (h1 -> y) of a hub, the part of N(y) inside (h1, hub end) holds its
+// hub partners; each gets R - 1 on the slot (y -> h2) and the run's sum goes
+// to the centre y and the slot (h1 -> y).  A hub's up-slots are split into
+// items of HUB_CHUNK, so one giant hub spreads over many workgroups.
+template <int T, int U>
+__global__ __launch_bounds__(T) void k_count_hub_pass(Ranked G, Acc A, const uint32_t *hub_rank, const uint32_t *hoff,
+                                                      const uint32_t *D) {
+    __shared__ RunShared<T> sh;
+    const uint32_t count = hoff[HUB_T];
+    for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
+        uint32_t lo = 0, hi = HUB_T;  // hoff[lo] <= it < hoff[hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (hoff[mid] <= it) lo = mid; else hi = mid;
+        }
+        const uint32_t r = hub_rank[lo];
+        const uint32_t k0 = G.upoff[r], k1 = G.upoff[r + 1];
+        const uint32_t kb = k0 + (it - hoff[lo]) * HUB_CHUNK;
+        const uint32_t ke = kb + HUB_CHUNK < k1 ? kb + HUB_CHUNK : k1;
+        const HubAgg agg{D + (uint64_t)lo * HUB_T, G.hub_base};
+        const uint32_t s_lo = G.smid[r] + 1;
+        for (uint32_t c = kb; c < ke; c += T) {
+            const uint32_t k = c + threadIdx.x;
+            uint32_t a = 0, cnt = 0, start = 0;
+            if (k < ke) {
+                start = G.uprun[k];
+                const uint32_t pos = G.uplen[k];
+                const uint32_t *p = G.nbr + start;
+                a = first_below(p, 0, pos, G.hub_end);
+                cnt = first_below(p, a, pos, s_lo) - a;
+            }
+            uint32_t total, nne;
+            compact_runs<T>(k, start, a, cnt, sh, &total, &nne);
+            walk_runs<T, U>(G, A, agg, sh, 2, total, nne);
+            flush_runs<T>(G, A, r, k0, sh, nne);
+        }
     }
 }
 
@@ -1042,10 +1247,12 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
     if (opts.stats) *opts.stats = pb_stats{};
 
     const bool timing = ((opts.flags & PB_FLAG_TIMING) && opts.stats) || list_ms;
-    // events: [0] start, [1] plan done, [2 + i] after list i, [2 + NLISTS] end
+    // events: [0] start, [1] plan done, [2 + i] after list i, [2 + NLISTS] end,
+    // then the hub tile's matrix-core kernel and the hub credit pass
     constexpr int NEV = NLISTS + 3;
+    constexpr int E_HG0 = NEV, E_HG1 = NEV + 1, E_HP0 = NEV + 2, E_HP1 = NEV + 3;
     struct Events {
-        hipEvent_t e[NEV] = {};
+        hipEvent_t e[NEV + 4] = {};
         bool ok = false;
         ~Events() {
             for (auto &x : e)
@@ -1090,7 +1297,8 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
     if (n > 0) {
         PB_TRY(fill<uint32_t>(seen, 0u, n, s));
         PB_TRY(fill<uint32_t>(order, 0u, n, s));
-        hipLaunchKernelGGL(k_rank_check, dim3(grid_for(n)), dim3(256), 0, s, in.rank, n, order, seen, &pc->flags);
+        hipLaunchKernelGGL(k_rank_check, dim3(grid_for(n)), dim3(256), 0, s, in.rank, n, order, seen, &pc->flags,
+                           &pc->top);
         PB_TRY_HIP(hipGetLastError());
         PB_TRY_HIP(hipMemcpyAsync(hpc, pc, sizeof(PlanCounts), hipMemcpyDeviceToHost, s));
         PB_TRY_HIP(hipStreamSynchronize(s));
@@ -1098,8 +1306,30 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
     }
     ws.release(seen);
 
+    // Hub tile candidates (one graph only): the first HUB_T vertices in rank
+    // order of the rank-0 vertex's side.
+    uint32_t hub_base = 0, hub_end = 0;
+    if (m > 0 && ng == 1 && opts.hub != PB_HUB_OFF && (opts.hub == PB_HUB_FORCE || m >= HUB_AUTO_MIN_M)) {
+        const bool hub_v = hpc->top >= in.n_u;
+        const uint64_t side = hub_v ? n - in.n_u : in.n_u;
+        const uint32_t H = (uint32_t)std::min<uint64_t>(HUB_T, side);
+        if (H >= 2) {
+            hub_base = hub_v ? in.n_u : 0u;
+            hub_end = hub_base + H;
+        }
+    }
+    uint32_t *hub_rank = nullptr, *hub_d = nullptr, *hub_off = nullptr;
+    unsigned long long *hub_roww = nullptr;
+    uint32_t hub_grid = 0;
+
     uint64_t wtotal = 0;
     PlanCounts plan{};
+    bool hub_pass_ran = false;
+    // host tables of the giant-source items (alive until the call's last synchronisation)
+    std::vector<uint32_t> gh_info;
+    std::vector<GhSrc> gh_src;
+    std::vector<uint2> gh_items, gh_eitems;
+    uint32_t gh_xoff[NXCD + 1] = {}, gh_exoff[NXCD + 1] = {};
     uint32_t *smid = nullptr, *eslot = nullptr;
     if (m > 0) {
         // 2. relabel (Algorithm 1) ---------------------------------------------
@@ -1148,6 +1378,23 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         ws.release(hideg);
         ws.release(isv);
 
+        // 3a. hub tile: R of hub pairs on matrix cores, C(R,2) credits ------------
+        if (hub_end > hub_base) {
+            hub_rank = ws.alloc<uint32_t>(HUB_T);
+            hub_d = ws.alloc<uint32_t>((uint64_t)HUB_T * HUB_T);
+            hub_roww = ws.alloc<unsigned long long>(HUB_T);
+            hub_off = ws.alloc<uint32_t>(HUB_T + 1);
+            if (ws.failed) return PB_ERR_NO_MEMORY;
+            const HubIn hin{n, in.n_u, smid, roff, upoff, nbr, hub_base, hub_end, opts.hub == PB_HUB_FORCE, gacc,
+                            vacc};
+            PB_TRY(hub_tile(hin, &pc->hub, HubOut{hub_rank, hub_d, hub_roww}, ws, s, ev.ok ? ev.e[E_HG0] : nullptr,
+                            ev.ok ? ev.e[E_HG1] : nullptr, &hub_grid));
+            if (mode & (MODE_VERTEX | MODE_EDGE))
+                hipLaunchKernelGGL(k_hub_items, dim3(1), dim3(HUB_T), 0, s, (const uint32_t *)upoff,
+                                   (const uint32_t *)hub_rank, hub_end - hub_base, hub_off, pc);
+            PB_TRY_HIP(hipGetLastError());
+        }
+
         // 3. plan: wedges per source, bucket by distinct-endpoint bound -------
         uint64_t *wscan = ws.alloc<uint64_t>(m + 1);
         uint32_t *lists = ws.alloc<uint32_t>((uint64_t)NLISTS * n);
@@ -1155,8 +1402,8 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         uint64_t *wl = ws.alloc<uint64_t>((uint64_t)NSORTED * n);
         if (ws.failed) return PB_ERR_NO_MEMORY;
         PB_TRY((scan_exclusive<uint32_t, uint64_t>(uplen, wscan, m, wscan + m, ws)));
-        hipLaunchKernelGGL(k_plan, dim3(grid_for(n)), dim3(256), 0, s, upoff, wscan, smid, cend, n, pol, lists, nwin,
-                           wl, pc);
+        hipLaunchKernelGGL(k_plan, dim3(grid_for(n)), dim3(256), 0, s, upoff, wscan, smid, cend, n, pol, hub_base,
+                           hub_end, (const unsigned long long *)hub_roww, lists, nwin, wl, pc);
         PB_TRY_HIP(hipGetLastError());
         PB_TRY_HIP(hipMemcpyAsync(hpc, pc, sizeof(PlanCounts), hipMemcpyDeviceToHost, s));
         PB_TRY_HIP(hipMemcpyAsync(&wtotal, wscan + m, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
@@ -1166,8 +1413,8 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         auto list_of = [&](int l) { return (const uint32_t *)(lists + (uint64_t)l * n); };
 
         // most-wedges-first order for the window lists
-        const uint32_t *sorted_src[NSORTED] = {nullptr, nullptr, nullptr};
-        const uint64_t *sorted_w[NSORTED] = {nullptr, nullptr, nullptr};
+        const uint32_t *sorted_src[NSORTED] = {};
+        const uint64_t *sorted_w[NSORTED] = {};
         uint2 *items = nullptr;
         uint32_t *cur = nullptr, *nxt = nullptr, *cval = nullptr, *nval = nullptr;
         for (int l = 0; l < NLISTS; ++l) {
@@ -1193,7 +1440,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
                 if (ws.failed) return PB_ERR_NO_MEMORY;
                 PB_TRY((scan_exclusive<uint32_t, uint32_t>(hnw, hoff, nh, hoff + nh, ws)));
                 hipLaunchKernelGGL(k_heavy_expand, dim3(grid_for(nh)), dim3(256), 0, s, hsrc, hnw, hoff, nh, items);
-            } else if (!cur) {
+            } else if (!cur && (l == L_DENSE_HEAVY || l == L_SORT_HEAVY)) {
                 cur = ws.alloc<uint32_t>(m);
                 nxt = ws.alloc<uint32_t>(m);
                 cval = ws.alloc<uint32_t>(m);
@@ -1206,8 +1453,59 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         }
 
         // 4. count ---------------------------------------------------------------
-        Ranked G{roff, nbr, upoff, uprun, uplen, smid, cend, gid, in.n_u, (uint32_t)n};
+        const bool hub_on = plan.hub.on && hub_end > hub_base;
+        Ranked G{roff, nbr, upoff, uprun, uplen, smid, cend, gid, in.n_u, (uint32_t)n,
+                 hub_on ? hub_base : 0u, hub_on ? hub_end : 0u};
         Acc A{gacc, vacc, sacc, sacc32, &pc->flags, mode};
+
+        // giant sources: per-die item lists, built on the host (one extra
+        // synchronisation, only when there are such sources)
+        GhSrc *d_gh_src = nullptr;
+        uint2 *d_gh_items = nullptr, *d_gh_eitems = nullptr;
+        uint32_t *d_gh_xoff = nullptr, *d_gh_exoff = nullptr, *gh_hist = nullptr;
+        uint64_t gh_total = 0;
+        if (const uint32_t c = plan.list[L_DENSE_GLOBAL]) {
+            uint32_t *d_info = ws.alloc<uint32_t>(4ull * c);
+            if (ws.failed) return PB_ERR_NO_MEMORY;
+            hipLaunchKernelGGL(k_gh_info, dim3(grid_for(c)), dim3(256), 0, s, G, sorted_src[sorted_slot(L_DENSE_GLOBAL)],
+                               c, d_info);
+            PB_TRY_HIP(hipGetLastError());
+            gh_info.resize(4ull * c);
+            PB_TRY_HIP(hipMemcpyAsync(gh_info.data(), d_info, 16ull * c, hipMemcpyDeviceToHost, s));
+            PB_TRY_HIP(hipStreamSynchronize(s));
+            // sources are in most-wedges-first order: deal them round-robin to the dies
+            std::vector<uint2> per_w[NXCD], per_e[NXCD];
+            gh_src.resize(c);
+            for (uint32_t i = 0; i < c; ++i) {
+                const uint32_t *f = &gh_info[4ull * i];
+                gh_src[i] = GhSrc{f[0], f[1], f[2], f[3], gh_total};
+                gh_total += f[3];
+                for (uint32_t j = 0; j < ceil_div(f[2], GH_CHUNK); ++j) per_w[i % NXCD].push_back(make_uint2(i, j));
+                for (uint32_t j = 0; j < ceil_div(f[3], GH_SEG); ++j) per_e[i % NXCD].push_back(make_uint2(i, j));
+            }
+            for (uint32_t x = 0; x < NXCD; ++x) {
+                gh_xoff[x] = (uint32_t)gh_items.size();
+                gh_exoff[x] = (uint32_t)gh_eitems.size();
+                gh_items.insert(gh_items.end(), per_w[x].begin(), per_w[x].end());
+                gh_eitems.insert(gh_eitems.end(), per_e[x].begin(), per_e[x].end());
+            }
+            gh_xoff[NXCD] = (uint32_t)gh_items.size();
+            gh_exoff[NXCD] = (uint32_t)gh_eitems.size();
+            d_gh_src = ws.alloc<GhSrc>(c);
+            d_gh_items = ws.alloc<uint2>(gh_items.size());
+            d_gh_eitems = ws.alloc<uint2>(gh_eitems.size());
+            d_gh_xoff = ws.alloc<uint32_t>(2 * (NXCD + 1));
+            gh_hist = ws.alloc<uint32_t>(gh_total);
+            if (ws.failed) return PB_ERR_NO_MEMORY;
+            d_gh_exoff = d_gh_xoff + NXCD + 1;
+            PB_TRY_HIP(hipMemcpyAsync(d_gh_src, gh_src.data(), sizeof(GhSrc) * c, hipMemcpyHostToDevice, s));
+            PB_TRY_HIP(hipMemcpyAsync(d_gh_items, gh_items.data(), sizeof(uint2) * gh_items.size(),
+                                      hipMemcpyHostToDevice, s));
+            PB_TRY_HIP(hipMemcpyAsync(d_gh_eitems, gh_eitems.data(), sizeof(uint2) * gh_eitems.size(),
+                                      hipMemcpyHostToDevice, s));
+            PB_TRY_HIP(hipMemcpyAsync(d_gh_xoff, gh_xoff, sizeof(gh_xoff), hipMemcpyHostToDevice, s));
+            PB_TRY_HIP(hipMemcpyAsync(d_gh_exoff, gh_exoff, sizeof(gh_exoff), hipMemcpyHostToDevice, s));
+        }
         mark(1);
         for (int l = 0; l < NLISTS; ++l) {
             const uint32_t c = plan.list[l];
@@ -1239,10 +1537,27 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
                     case L_DENSE_SMALL:
                         launch_items(k_count_dense_src<256, 4, SMALL_WIN>, c, 256, s, G, A, list_of(l));
                         break;
+                    case L_DENSE_GLOBAL: {
+                        const dim3 grid(NXCD * GH_WG_PER_XCD);
+                        PB_TRY(fill<uint32_t>(gh_hist, 0u, gh_total, s));
+                        k_gh_walk<256, 4, 1><<<grid, 256, 0, s>>>(G, A, d_gh_src, d_gh_items, d_gh_xoff, gh_hist);
+                        k_gh_endpoint<256><<<grid, 256, 0, s>>>(G, A, d_gh_src, d_gh_eitems, d_gh_exoff, gh_hist);
+                        if (mode & (MODE_VERTEX | MODE_EDGE))
+                            k_gh_walk<256, 4, 2><<<grid, 256, 0, s>>>(G, A, d_gh_src, d_gh_items, d_gh_xoff, gh_hist);
+                        break;
+                    }
                 }
                 PB_TRY_HIP(hipGetLastError());
             }
             mark(2 + l);
+        }
+        if (hub_on && (mode & (MODE_VERTEX | MODE_EDGE)) && plan.hub_items) {
+            hub_pass_ran = true;
+            if (ev.ok) ev.ok = hipEventRecord(ev.e[E_HP0], s) == hipSuccess;
+            k_count_hub_pass<256, 4><<<dim3(std::min(plan.hub_items, HUB_PASS_GRID)), dim3(256), 0, s>>>(
+                G, A, hub_rank, hub_off, hub_d);
+            PB_TRY_HIP(hipGetLastError());
+            if (ev.ok) ev.ok = hipEventRecord(ev.e[E_HP1], s) == hipSuccess;
         }
     } else {
         for (int l = 0; l < NLISTS; ++l) mark(1 + l);
@@ -1262,9 +1577,16 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
     PB_TRY_HIP(hipStreamSynchronize(s));
     if (hpc->flags & FLAG_INTERNAL) return PB_ERR_HIP;
 
-    float t[NEV - 1] = {};
-    if (timing && ev.ok)
+    // t[0] prepare, t[1 + l] list l, t[1 + NLISTS] output; hub kernels apart
+    float t[NEV - 1] = {}, t_gemm = 0, t_hub_pass = 0;
+    if (timing && ev.ok) {
         for (int i = 0; i + 1 < NEV; ++i) (void)hipEventElapsedTime(&t[i], ev.e[i], ev.e[i + 1]);
+        if (hub_pass_ran) {
+            (void)hipEventElapsedTime(&t_hub_pass, ev.e[E_HP0], ev.e[E_HP1]);
+            (void)hipEventElapsedTime(&t[1 + NLISTS], ev.e[E_HP1], ev.e[2 + NLISTS]);
+        }
+        if (hub_grid && plan.hub.on) (void)hipEventElapsedTime(&t_gemm, ev.e[E_HG0], ev.e[E_HG1]);
+    }
     if (list_ms)
         for (int l = 0; l < NLISTS; ++l) list_ms[l] = t[1 + l];
     if (opts.stats) {
@@ -1272,17 +1594,27 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         st.wedges = wtotal;
         st.sources = plan.sources;
         st.sources_hash = plan.list[L_HASH_LIGHT] + plan.list[L_HASH_MEDIUM] + plan.list[L_HASH_WIN];
-        st.sources_dense = plan.list[L_DENSE_HEAVY] + plan.list[L_DENSE_SMALL];
+        st.sources_dense = plan.list[L_DENSE_HEAVY] + plan.list[L_DENSE_SMALL] + plan.list[L_DENSE_GLOBAL];
         st.sources_sort = plan.list[L_SORT_LIGHT] + plan.list[L_SORT_MEDIUM] + plan.list[L_SORT_HEAVY];
         st.window_items = plan.items + plan.list[L_DENSE_HEAVY] + plan.list[L_SORT_HEAVY];
         st.wedges_hash = plan.wedges[L_HASH_LIGHT] + plan.wedges[L_HASH_MEDIUM] + plan.wedges[L_HASH_WIN];
-        st.wedges_dense = plan.wedges[L_DENSE_HEAVY] + plan.wedges[L_DENSE_SMALL];
+        st.wedges_dense = plan.wedges[L_DENSE_HEAVY] + plan.wedges[L_DENSE_SMALL] + plan.wedges[L_DENSE_GLOBAL];
         st.wedges_sort = plan.wedges[L_SORT_LIGHT] + plan.wedges[L_SORT_MEDIUM] + plan.wedges[L_SORT_HEAVY];
         st.workspace_bytes = ws.peak;
+        st.wedges_heavy = plan.wedges[L_DENSE_HEAVY];
+        if (hub_grid && plan.hub.on) {
+            st.wedges_hub = plan.hub.wedges;
+            st.hub_rows = hub_end - hub_base;
+            st.hub_cols = plan.hub.cols;
+            st.hub_mfma_ops = hub_gemm_ops(plan.hub.cols);
+        }
         if (timing && ev.ok) {
+            st.ms_heavy = t[1 + L_DENSE_HEAVY];
+            st.ms_hub_gemm = t_gemm;
+            st.ms_hub_pass = t_hub_pass;
             st.ms_prepare = t[0];
             st.ms_hash = t[1 + L_HASH_LIGHT] + t[1 + L_HASH_MEDIUM] + t[1 + L_HASH_WIN];
-            st.ms_dense = t[1 + L_DENSE_HEAVY] + t[1 + L_DENSE_SMALL];
+            st.ms_dense = t[1 + L_DENSE_HEAVY] + t[1 + L_DENSE_SMALL] + t[1 + L_DENSE_GLOBAL];
             st.ms_sort = t[1 + L_SORT_LIGHT] + t[1 + L_SORT_MEDIUM] + t[1 + L_SORT_HEAVY];
             st.ms_output = t[1 + NLISTS];
         }

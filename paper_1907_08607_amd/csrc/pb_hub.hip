@@ -1,0 +1,280 @@
+// Hub-to-hub tile: the pair counts R of the highest-priority vertices of one
+// side as a dense 0/1 product D = A' A^T on int8 matrix cores (gfx950
+// v_mfma_i32_32x32x32_i8, int32 accumulation), instead of one hash or counter
+// update per wedge.  The products are 0/1, so every sum is an exact integer no
+// larger than the number of centres.
+//
+// Pipeline (all on the device, no host synchronisation):
+//   k_hub_rank    rank of each hub
+//   k_hub_mark    keep the centres with >= 2 hub neighbours, at least one of
+//                 them ranked below the centre; sum C(k,2) over kept centres
+//   k_hub_decide  cost model (or forced on)
+//   k_hub_fill    compacted column table: slot range of the hub neighbours
+//                 (the tail of N(y), since hubs have the smallest side-major
+//                 ids) and where A' starts inside it
+//   k_hub_gemm    split-K over column chunks: each workgroup scatters 128
+//                 columns into two LDS byte tiles and accumulates the upper
+//                 64x64 blocks of D in registers, then writes its partial D
+//   k_hub_reduce  sums the partials; per pair: C(R,2) into the total and both
+//                 endpoints (Section 3.1.3); per hub: its wedges as the lower
+//                 endpoint (the plan subtracts them)
+#include "pb_internal.h"
+
+#include <algorithm>
+
+using namespace pb;
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr uint32_t KC = 128;               // centre columns per LDS tile
+constexpr uint32_t ROWB = KC + 16;         // bytes per tile row; the pad spreads 16-byte reads over all banks
+constexpr uint32_t GEMM_THREADS = 1024;    // 16 waves: one 64x64 block of D each (upper ones compute)
+constexpr uint32_t GEMM_MAX_GRID = 256;    // one workgroup per compute unit
+
+// AUTO cost model, nanoseconds: the sparse path spends about NS_PER_PATH per
+// hub-pair wedge in its first pass; the tile about NS_PER_COL per column.
+constexpr double NS_PER_PATH = 0.1;
+constexpr double NS_PER_COL = 0.1;
+constexpr double NS_FIXED = 50000.0;
+
+#define HUB_GRID_STRIDE(i, n)                                                       \
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); \
+         i += (uint64_t)gridDim.x * blockDim.x)
+
+inline uint32_t grid_for(uint64_t n, uint32_t block = 256, uint32_t cap = 65536) {
+    uint64_t g = (n + block - 1) / block;
+    if (g == 0) g = 1;
+    return (uint32_t)(g > cap ? cap : g);
+}
+
+// Smallest i in [lo, len] with p[i] < v (p strictly decreasing).
+__device__ inline uint32_t tail_start(const uint32_t *p, uint32_t lo, uint32_t len, uint32_t v) {
+    uint32_t hi = len;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (p[mid] < v) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+__device__ inline bool other_side(const HubIn &in, uint32_t s) { return (s >= in.n_u) != (in.base >= in.n_u); }
+
+__global__ void k_hub_rank(const uint32_t *smid, uint64_t n, uint32_t base, uint32_t end, uint32_t *hub_rank) {
+    HUB_GRID_STRIDE(r, n) {
+        const uint32_t s = smid[r];
+        if (s >= base && s < end) hub_rank[s - base] = (uint32_t)r;
+    }
+}
+
+__global__ void k_hub_mark(HubIn in, uint32_t *keep, HubCounters *hc) {
+    for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x; b0 < in.n; b0 += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t r = b0 + threadIdx.x;
+        uint32_t flag = 0;
+        unsigned long long paths = 0;
+        if (r < in.n) {
+            if (other_side(in, in.smid[r])) {
+                const uint32_t o = in.roff[r], deg = in.roff[r + 1] - o;
+                const uint32_t hi = in.upoff[r + 1] - in.upoff[r];  // neighbours ranked above y
+                const uint32_t k = deg - tail_start(in.nbr + o, 0, deg, in.end);
+                if (k >= 2 && hi < deg) {
+                    flag = 1;
+                    paths = (unsigned long long)k * (k - 1) / 2;
+                }
+            }
+            keep[r] = flag;
+        }
+        paths = wave_sum(paths);
+        if ((threadIdx.x & (WAVE - 1)) == 0 && paths) atomicAdd(&hc->paths, paths);
+    }
+}
+
+__global__ void k_hub_decide(const uint32_t *cols, HubCounters *hc, bool force) {
+    const uint32_t c = *cols;
+    hc->cols = c;
+    const double dense = NS_FIXED + NS_PER_COL * (double)c;
+    const double sparse = NS_PER_PATH * (double)hc->paths;
+    hc->on = (force || sparse > dense) ? 1u : 0u;
+}
+
+__global__ void k_hub_fill(HubIn in, const uint32_t *keep, const uint32_t *coff, const HubCounters *hc,
+                           uint32_t *cstart, uint32_t *clen, uint32_t *ca) {
+    if (!hc->on) return;
+    HUB_GRID_STRIDE(r, in.n) {
+        if (!keep[r]) continue;
+        const uint32_t c = coff[r];
+        const uint32_t o = in.roff[r], deg = in.roff[r + 1] - o;
+        const uint32_t hi = in.upoff[r + 1] - in.upoff[r];
+        const uint32_t t0 = tail_start(in.nbr + o, 0, deg, in.end);
+        cstart[c] = o + t0;
+        clen[c] = deg - t0;
+        // tail entries from position hi on are ranked below y: those are A'
+        ca[c] = hi > t0 ? hi - t0 : 0u;
+    }
+}
+
+// Split-K product.  Wave w owns block (w / 4, w % 4) of D in 64x64 blocks and
+// computes it when it is on or above the diagonal: 2x2 tiles of 32x32, each a
+// chain of 32x32x32 int8 MFMAs over the chunk.  Both operands are read from
+// LDS with the same lane/byte pattern, so the K order inside an instruction
+// does not matter.  Output layout of a 32x32 tile: lane l, register q holds
+// row 8(q/4) + 4(l/32) + q%4, column l%32.
+__global__ __launch_bounds__(GEMM_THREADS) void k_hub_gemm(const uint32_t *cstart, const uint32_t *clen,
+                                                           const uint32_t *ca, const uint32_t *nbr, uint32_t base,
+                                                           const HubCounters *hc, uint32_t *part) {
+    __shared__ __attribute__((aligned(16))) uint8_t tA[HUB_T * ROWB];  // A' (lower endpoint h1)
+    __shared__ __attribute__((aligned(16))) uint8_t tB[HUB_T * ROWB];  // A (upper endpoint h2)
+    __shared__ uint32_t ms[KC], ml[KC], ma[KC];
+    if (!hc->on) return;
+    const uint32_t C = hc->cols;
+    const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
+    const uint32_t bi = w >> 2, bj = w & 3;
+    const bool active = bj >= bi;
+    v16i acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[a][b][q] = 0;
+
+    for (uint32_t c0 = blockIdx.x * KC; c0 < C; c0 += gridDim.x * KC) {
+        uint4 *za = reinterpret_cast<uint4 *>(tA), *zb = reinterpret_cast<uint4 *>(tB);
+        for (uint32_t i = tid; i < HUB_T * ROWB / 16; i += GEMM_THREADS) {
+            za[i] = make_uint4(0, 0, 0, 0);
+            zb[i] = make_uint4(0, 0, 0, 0);
+        }
+        if (tid < KC) {
+            const uint32_t c = c0 + tid;
+            if (c < C) {
+                ms[tid] = cstart[c];
+                ml[tid] = clen[c];
+                ma[tid] = ca[c];
+            } else {
+                ml[tid] = 0;
+            }
+        }
+        __syncthreads();
+        {
+            const uint32_t col = tid >> 3, sub = tid & 7;  // 8 threads per column
+            const uint32_t len = ml[col], st = ms[col], a0 = ma[col];
+            for (uint32_t j = sub; j < len; j += 8) {
+                const uint32_t h = nbr[st + j] - base;
+                if (h < HUB_T) {
+                    tB[h * ROWB + col] = 1;
+                    if (j >= a0) tA[h * ROWB + col] = 1;
+                }
+            }
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (uint32_t ks = 0; ks < KC; ks += 32) {
+                const uint32_t kb = ks + 16 * (lane >> 5);
+                v4i a[2], b[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    a[t] = *reinterpret_cast<const v4i *>(&tA[(bi * 64 + t * 32 + (lane & 31)) * ROWB + kb]);
+                    b[t] = *reinterpret_cast<const v4i *>(&tB[(bj * 64 + t * 32 + (lane & 31)) * ROWB + kb]);
+                }
+#pragma unroll
+                for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+                    for (int tj = 0; tj < 2; ++tj)
+                        acc[ti][tj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    if (active) {
+        uint32_t *P = part + (uint64_t)blockIdx.x * HUB_T * HUB_T;
+#pragma unroll
+        for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const uint32_t i = bi * 64 + ti * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+                    const uint32_t j = bj * 64 + tj * 32 + (lane & 31);
+                    P[i * HUB_T + j] = (uint32_t)acc[ti][tj][q];
+                }
+    }
+}
+
+// One block per row i, one thread per column j.
+__global__ __launch_bounds__(HUB_T) void k_hub_reduce(const uint32_t *part, uint32_t nparts, uint32_t H,
+                                                      unsigned long long *g, unsigned long long *v, uint32_t base,
+                                                      HubCounters *hc, uint32_t *D, unsigned long long *roww) {
+    __shared__ unsigned long long tmp[HUB_T / WAVE + 1];
+    if (!hc->on) return;
+    const uint32_t i = blockIdx.x, j = threadIdx.x;
+    uint32_t s = 0;
+    if (i < H && j < H && j > i)
+        for (uint32_t b = 0; b < nparts; ++b) s += part[((uint64_t)b * HUB_T + i) * HUB_T + j];
+    D[i * HUB_T + j] = s;
+    const unsigned long long t = s >= 2 ? (unsigned long long)s * (s - 1) / 2 : 0ull;
+    if (v && t) {
+        atomicAdd(&v[base + i], t);
+        atomicAdd(&v[base + j], t);
+    }
+    const unsigned long long rs = block_sum<HUB_T>((unsigned long long)s, tmp);
+    const unsigned long long ts = block_sum<HUB_T>(t, tmp);
+    if (j == 0) {
+        roww[i] = rs;
+        if (rs) atomicAdd(&hc->wedges, rs);
+        if (ts) atomicAdd(g, ts);
+    }
+}
+
+}  // namespace
+
+namespace pb {
+
+uint64_t hub_gemm_ops(uint32_t cols) {
+    // per chunk of KC columns: 10 upper 64x64 blocks of 2x2 tiles, KC/32
+    // MFMAs of 32x32x32 (2 * 32^3 operations) each
+    const uint64_t chunks = (cols + KC - 1) / KC;
+    return chunks * 10ull * 4ull * (KC / 32) * 2ull * 32 * 32 * 32;
+}
+
+pb_status hub_tile(const HubIn &in, HubCounters *hc, const HubOut &out, Workspace &ws, hipStream_t s,
+                   hipEvent_t ev0, hipEvent_t ev1, uint32_t *gemm_grid) {
+    const uint64_t n = in.n;
+    const uint32_t H = in.end - in.base;
+    if (H < 2 || H > HUB_T) return PB_ERR_INVALID_ARG;
+    // centres live on the other side: at most that many columns
+    const uint64_t other = in.base >= in.n_u ? in.n_u : n - in.n_u;
+    uint32_t *keep = ws.alloc<uint32_t>(n + 1), *coff = ws.alloc<uint32_t>(n + 1);
+    uint32_t *cstart = ws.alloc<uint32_t>(other + 1), *clen = ws.alloc<uint32_t>(other + 1);
+    uint32_t *ca = ws.alloc<uint32_t>(other + 1);
+    const uint32_t grid = std::max<uint32_t>(1u, std::min<uint32_t>(GEMM_MAX_GRID, ceil_div(other, KC)));
+    uint32_t *part = ws.alloc<uint32_t>((uint64_t)grid * HUB_T * HUB_T);
+    if (ws.failed) return PB_ERR_NO_MEMORY;
+    *gemm_grid = grid;
+    hipLaunchKernelGGL(k_hub_rank, dim3(grid_for(n)), dim3(256), 0, s, in.smid, n, in.base, in.end, out.hub_rank);
+    hipLaunchKernelGGL(k_hub_mark, dim3(grid_for(n)), dim3(256), 0, s, in, keep, hc);
+    PB_TRY_HIP(hipGetLastError());
+    PB_TRY((scan_exclusive<uint32_t, uint32_t>(keep, coff, n, coff + n, ws)));
+    hipLaunchKernelGGL(k_hub_decide, dim3(1), dim3(1), 0, s, (const uint32_t *)(coff + n), hc, in.force);
+    hipLaunchKernelGGL(k_hub_fill, dim3(grid_for(n)), dim3(256), 0, s, in, keep, coff, hc, cstart, clen, ca);
+    PB_TRY_HIP(hipGetLastError());
+    if (ev0) PB_TRY_HIP(hipEventRecord(ev0, s));
+    hipLaunchKernelGGL(k_hub_gemm, dim3(grid), dim3(GEMM_THREADS), 0, s, cstart, clen, ca, in.nbr, in.base, hc,
+                       part);
+    PB_TRY_HIP(hipGetLastError());
+    if (ev1) PB_TRY_HIP(hipEventRecord(ev1, s));
+    hipLaunchKernelGGL(k_hub_reduce, dim3(HUB_T), dim3(HUB_T), 0, s, part, grid, H, in.g, in.v, in.base, hc, out.D,
+                       out.roww);
+    PB_TRY_HIP(hipGetLastError());
+    ws.release(part);
+    ws.release(ca);
+    ws.release(clen);
+    ws.release(cstart);
+    ws.release(coff);
+    ws.release(keep);
+    return PB_OK;
+}
+
+}  // namespace pb

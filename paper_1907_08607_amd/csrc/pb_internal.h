@@ -161,6 +161,50 @@ __device__ inline T block_sum(T v, T *s_tmp) {
     return r;
 }
 
+
+// ---------------------------------------------------------------- hub tile
+
+// Dense hub-to-hub pairs on int8 matrix cores.  The hubs are the first HUB_T
+// (or fewer) vertices in rank order of one side; their side-major ids form
+// [base, end).  For hub pairs h1 < h2 (rank order) and centres y on the other
+// side, A[h][y] = 1 when y is a neighbour of h and A'[h][y] additionally needs
+// rank y > rank h.  D = A' A^T then holds R(h1, h2) = |{y in N(h1) & N(h2) :
+// rank y > rank h1}| above the diagonal (Section 3.1.2's wedge counts of the
+// pair), as an exact int32 sum of 0/1 products.
+constexpr uint32_t HUB_T = 256;
+
+struct HubCounters {
+    uint32_t on;                // tile in use (set on device; AUTO may decline)
+    uint32_t cols;              // compacted centre columns
+    unsigned long long paths;   // sum over kept columns of C(k, 2), k = hub neighbours
+    unsigned long long wedges;  // wedges of hub pairs: sum of R over h1 < h2
+};
+
+struct HubIn {
+    uint64_t n;
+    uint32_t n_u;
+    const uint32_t *smid, *roff, *upoff, *nbr;  // ranked CSR (rank-indexed)
+    uint32_t base, end;                         // hub side-major ids
+    bool force;                                 // skip the cost model
+    unsigned long long *g;                      // global accumulator (one graph)
+    unsigned long long *v;                      // per-vertex accumulator by smid, or null
+};
+
+struct HubOut {
+    uint32_t *hub_rank;         // HUB_T: rank of hub i
+    uint32_t *D;                // HUB_T * HUB_T: R(hub i, hub j) for i < j, else 0
+    unsigned long long *roww;   // HUB_T: wedges of hub i as the lower endpoint
+};
+
+// Builds the tile and credits C(R,2) per hub pair to the global count and both
+// endpoints.  Everything stays on the device (hc->on may turn the tile off);
+// `ev0`/`ev1`, if not null, are recorded around the matrix-core kernel.
+pb_status hub_tile(const HubIn &in, HubCounters *hc, const HubOut &out, Workspace &ws, hipStream_t s,
+                   hipEvent_t ev0, hipEvent_t ev1, uint32_t *gemm_grid);
+
+// int8 operations the matrix-core kernel issues for `cols` compacted columns.
+uint64_t hub_gemm_ops(uint32_t cols);
+
 }  // namespace pb
 
 // ---------------------------------------------------------------- the graph handle

@@ -238,6 +238,21 @@ def random_small(n_u: int, n_v: int, p: float, seed: int) -> BipartiteCSR:
     return from_edges(n_u, n_v, u, v)
 
 
+def giant_hubs(n_u: int, n_v: int, hubs: int, hub_deg: int, per_u: int, seed: int) -> BipartiteCSR:
+    """A few giant V vertices on a sparse background: V ids 0..hubs-1 each take
+    hub_deg distinct random U neighbours, and every U vertex takes per_u random
+    V neighbours (duplicates dropped).  The hubs are sources with far more
+    up-slots than any other, the shape of the heaviest sources of a hub-skewed
+    graph, at a size the oracle finishes quickly."""
+    rng = np.random.Generator(np.random.PCG64([seed, 11]))
+    hu = np.concatenate([rng.choice(n_u, size=hub_deg, replace=False) for _ in range(hubs)])
+    hv = np.repeat(np.arange(hubs), hub_deg)
+    bu = np.repeat(np.arange(n_u), per_u)
+    bv = rng.integers(0, n_v, size=bu.size)
+    keys = np.unique(np.concatenate([hu * np.int64(n_v) + hv, bu * np.int64(n_v) + bv]))
+    return _csr_from_keys(n_u, n_v, keys)
+
+
 # --------------------------------------------------------------------------
 # The named workloads.
 
