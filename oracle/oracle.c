@@ -12,7 +12,7 @@
  *   b(x) = number of butterflies containing vertex x;
  *   b(e) = number of butterflies containing edge e;
  *   B    = number of butterflies.
- * Lemma "lem-count" (Section 4.2, equations eq-vert and eq-edge):
+ * Lemma "lem-count" (Section 4.4, equations eq-vert and eq-edge):
  *   b(u)   = sum over u' != u of C(|N(u) & N(u')|, 2)
  *   b(u,v) = sum over u' in N(v), u' != u, of (|N(u) & N(u')| - 1)
  *

@@ -2,15 +2,15 @@
 // butterfly credit, output combine.
 //
 // Paper map (arXiv 1907.08607):
-//   relabel + modified degrees   Algorithm 1 (PREPROCESS), Section 4.1
-//   wedge retrieval              Algorithm 2 (GET-WEDGES), Section 4.2.1
+//   relabel + modified degrees   Algorithm 1 (PREPROCESS), Section 4.3
+//   wedge retrieval              Algorithm 2 (GET-WEDGES), Section 4.4.1
 //   wedge aggregation            GET-FREQ, Sections 3.1.2 and 4.2.1
 //   butterfly credit             Section 3.1.3, Algorithms 3 (COUNT-V) and 4 (COUNT-E)
 //
 // Layout after relabelling.  Vertices are renamed to their rank r.  N(r) is
 // stored at nbr[roff[r] .. roff[r+1]) sorted by decreasing rank, so the
 // neighbours ranked above r form the prefix of length hideg[r] (the modified
-// degree deg_r(r) of Section 4.1).  A neighbour is stored by its side-major id
+// degree deg_r(r) of Section 4.3).  A neighbour is stored by its side-major id
 // (smid): U vertices in rank order take 0..n_u-1, V vertices n_u..n-1; within
 // one side smid increases with rank, so every list is also sorted by
 // decreasing smid and an smid range of candidate endpoints is a contiguous
@@ -183,44 +183,82 @@ __host__ __device__ inline uint32_t cand_lo(uint32_t s, uint32_t hub_base, uint3
 }
 
 // Hub sources lose the wedges of their hub partners (counted by the tile).
-__global__ void k_plan(const uint32_t *upoff, const uint64_t *wscan, const uint32_t *smid, const uint32_t *cend,
-                       uint64_t n, Policy pol, uint32_t hub_base, uint32_t hub_end, const unsigned long long *roww,
-                       uint32_t *lists, uint32_t *nwin, uint64_t *wl, PlanCounts *pc) {
+// List slots and totals are reserved per block (LDS atomics, then one global
+// atomic per list per block), so no global counter sees one atomic per source.
+constexpr uint32_t PLAN_GRID = 2048;
+__global__ __launch_bounds__(256) void k_plan(const uint32_t *upoff, const uint64_t *wscan, const uint32_t *smid,
+                                              const uint32_t *cend, uint64_t n, Policy pol, uint32_t hub_base,
+                                              uint32_t hub_end, const unsigned long long *roww, uint32_t *lists,
+                                              uint32_t *nwin, uint64_t *wl, PlanCounts *pc) {
+    __shared__ uint32_t cnt[NLISTS], base[NLISTS], s_items;
+    __shared__ unsigned long long wsum[NLISTS], s_sources;
     if (!pc->hub.on) hub_end = hub_base;
-    GRID_STRIDE(r, n) {
-        const uint32_t sm = smid[r];
-        uint64_t w = wscan[upoff[r + 1]] - wscan[upoff[r]];
-        if (sm >= hub_base && sm < hub_end) w -= roww[sm - hub_base];
-        const uint32_t lo = cand_lo(sm, hub_base, hub_end);
-        if (w == 0 || lo >= cend[r]) continue;
-        atomicAdd(&pc->sources, 1ull);
-        const uint32_t range = cend[r] - lo;
-        const uint64_t dist = w < range ? w : range;
-        const int bucket = dist <= pol.light_max ? 0 : dist <= pol.medium_max ? 1 : 2;
-        int which;
-        switch (pol.agg[bucket]) {
-            case PB_AGG_LDS_HASH:  // the policy keeps light_max <= 512 and medium_max <= 4096
-                which = bucket == 0 ? L_HASH_LIGHT : bucket == 1 ? L_HASH_MEDIUM : L_HASH_WIN;
-                break;
-            case PB_AGG_RADIX_SORT:
-                which = w <= SORT_LIGHT_W ? L_SORT_LIGHT : w <= SORT_W ? L_SORT_MEDIUM : L_SORT_HEAVY;
-                break;
-            default:
-                which = range <= SMALL_WIN                          ? L_DENSE_SMALL
-                        : upoff[r + 1] - upoff[r] >= GH_MIN_UPS ? L_DENSE_GLOBAL
-                                                                : L_DENSE_HEAVY;
-                break;
+    const uint32_t tid = threadIdx.x;
+    for (uint64_t b0 = (uint64_t)blockIdx.x * 256; b0 < n; b0 += (uint64_t)gridDim.x * 256) {
+        if (tid < NLISTS) {
+            cnt[tid] = 0;
+            wsum[tid] = 0;
         }
-        const uint32_t slot = atomicAdd(&pc->list[which], 1u);
-        atomicAdd(&pc->wedges[which], (unsigned long long)w);
-        lists[(uint64_t)which * n + slot] = (uint32_t)r;
-        const int sk = sorted_slot(which);
-        if (sk >= 0) {
-            const uint32_t nw = which == L_HASH_WIN ? (range + HASH_WIN - 1) / HASH_WIN : 1u;
-            nwin[(uint64_t)sk * n + slot] = nw;
-            wl[(uint64_t)sk * n + slot] = w;
-            if (which == L_HASH_WIN) atomicAdd(&pc->items, nw);
+        if (tid == 0) {
+            s_items = 0;
+            s_sources = 0;
         }
+        __syncthreads();
+        const uint64_t r = b0 + tid;
+        int which = -1;
+        uint32_t local = 0, nw = 1, range = 0;
+        uint64_t w = 0;
+        if (r < n) {
+            const uint32_t sm = smid[r];
+            w = wscan[upoff[r + 1]] - wscan[upoff[r]];
+            if (sm >= hub_base && sm < hub_end) w -= roww[sm - hub_base];
+            const uint32_t lo = cand_lo(sm, hub_base, hub_end);
+            if (w != 0 && lo < cend[r]) {
+                range = cend[r] - lo;
+                const uint64_t dist = w < range ? w : range;
+                const int bucket = dist <= pol.light_max ? 0 : dist <= pol.medium_max ? 1 : 2;
+                switch (pol.agg[bucket]) {
+                    case PB_AGG_LDS_HASH:  // the policy keeps light_max <= 512 and medium_max <= 4096
+                        which = bucket == 0 ? L_HASH_LIGHT : bucket == 1 ? L_HASH_MEDIUM : L_HASH_WIN;
+                        break;
+                    case PB_AGG_RADIX_SORT:
+                        which = w <= SORT_LIGHT_W ? L_SORT_LIGHT : w <= SORT_W ? L_SORT_MEDIUM : L_SORT_HEAVY;
+                        break;
+                    default:
+                        which = range <= SMALL_WIN                          ? L_DENSE_SMALL
+                                : upoff[r + 1] - upoff[r] >= GH_MIN_UPS ? L_DENSE_GLOBAL
+                                                                        : L_DENSE_HEAVY;
+                        break;
+                }
+                local = atomicAdd(&cnt[which], 1u);
+                atomicAdd(&wsum[which], (unsigned long long)w);
+                atomicAdd(&s_sources, 1ull);
+                if (which == L_HASH_WIN) {
+                    nw = (range + HASH_WIN - 1) / HASH_WIN;
+                    atomicAdd(&s_items, nw);
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < NLISTS && cnt[tid]) {
+            base[tid] = atomicAdd(&pc->list[tid], cnt[tid]);
+            atomicAdd(&pc->wedges[tid], wsum[tid]);
+        }
+        if (tid == 0) {
+            if (s_sources) atomicAdd(&pc->sources, s_sources);
+            if (s_items) atomicAdd(&pc->items, s_items);
+        }
+        __syncthreads();
+        if (which >= 0) {
+            const uint32_t slot = base[which] + local;
+            lists[(uint64_t)which * n + slot] = (uint32_t)r;
+            const int sk = sorted_slot(which);
+            if (sk >= 0) {
+                nwin[(uint64_t)sk * n + slot] = nw;
+                wl[(uint64_t)sk * n + slot] = w;
+            }
+        }
+        __syncthreads();  // cnt and base are reset by the next round
     }
 }
 
@@ -315,16 +353,92 @@ __device__ inline uint32_t first_below(const uint32_t *p, uint32_t lo, uint32_t 
     return lo;
 }
 
-// The same by galloping forward from s (cheap when the answer is near s).
-__device__ inline uint32_t gallop_below(const uint32_t *p, uint32_t s, uint32_t len, uint32_t v) {
-    if (s >= len || p[s] < v) return s;
-    uint32_t lo = s, step = 1;  // p[lo] >= v
-    while (lo + step < len && p[lo + step] >= v) {
-        lo += step;
-        step <<= 1;
+// Entries of zero padding after the ranked lists: vector reads of up to 20
+// entries from any list position stay inside the allocation.
+constexpr uint32_t NBR_PAD = 64;
+
+// Smallest e in (s, len] with p[e] < v, where p = nbr + start is strictly
+// decreasing, s < len and p[s] >= v; *pe = p[e] (0 when e == len).  The 16
+// entries after s come in one round trip of aligned 16-byte loads, which
+// settles every part of at most 16 entries; a longer part gallops and then
+// narrows with 8 independent probes per round trip, instead of one
+// dependent load per step.
+__device__ inline uint32_t probe_below(const uint32_t *nbr, uint32_t start, uint32_t s, uint32_t len, uint32_t v,
+                                       uint32_t *pe) {
+    const uint32_t a = start + s + 1;  // absolute index of p[s + 1]
+    const uint32_t b = a & ~3u;
+    uint32_t w[20];
+    const uint4 *q = reinterpret_cast<const uint4 *>(nbr + b);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const uint4 c = q[i];
+        w[4 * i] = c.x;
+        w[4 * i + 1] = c.y;
+        w[4 * i + 2] = c.z;
+        w[4 * i + 3] = c.w;
     }
-    const uint32_t hi = lo + step < len ? lo + step : len;
-    return first_below(p, lo + 1, hi, v);
+    const uint32_t lim = len - s - 1 < 16 ? len - s - 1 : 16u;  // entries after s that exist, up to 16
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int i = 0; i < 20; ++i) {
+        const uint32_t rel = b + i - a;  // wraps to a huge value before p[s + 1]
+        if (rel < lim && w[i] >= v) ++cnt;
+    }
+    if (cnt < lim) {
+        uint32_t val = 0;
+#pragma unroll
+        for (int i = 0; i < 20; ++i)
+            if (b + i - a == cnt) val = w[i];
+        *pe = val;
+        return s + 1 + cnt;
+    }
+    if (lim < 16) {  // every entry after s is >= v
+        *pe = 0;
+        return len;
+    }
+    // answer in (x, y]; p[x] >= v; y == len or p[y] = yv < v
+    uint32_t x = s + 16, y = len, yv = 0;
+    for (uint64_t scale = 16;; scale <<= 8) {
+        uint32_t qi[8], qv[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint64_t d = x + (scale << j);
+            qi[j] = d < y ? (uint32_t)d : y;
+            qv[j] = qi[j] < y ? nbr[start + qi[j]] : 0u;
+        }
+        bool found = false;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (found) continue;
+            if (qi[j] >= y || qv[j] < v) {
+                found = true;
+                if (qi[j] < y) { y = qi[j]; yv = qv[j]; }
+            } else {
+                x = qi[j];
+            }
+        }
+        if (found) break;
+    }
+    while (y - x > 1) {
+        const uint32_t wdt = y - x - 1;  // candidates x+1 .. y-1
+        uint32_t nx = x, ny = y, nyv = yv;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t qi = x + 1 + (uint32_t)(((uint64_t)wdt * j) / 8);
+            const uint32_t qv = nbr[start + qi];
+            if (qv >= v) {
+                if (qi > nx) nx = qi;
+            } else if (qi < ny) {
+                ny = qi;
+                nyv = qv;
+            }
+        }
+        x = nx;
+        y = ny;
+        yv = nyv;
+    }
+    *pe = y < len ? yv : 0u;
+    return y;
 }
 
 // Dense counters for the candidate window [lo, lo + size); 16-bit counters
@@ -579,10 +693,7 @@ struct CursorRange {
         if (pass == 1) {
             e = s;
             uint32_t ev = v;
-            if (s < pos && v >= lo) {
-                e = gallop_below(p, s, pos, lo);
-                ev = e < pos ? p[e] : 0u;
-            }
+            if (s < pos && v >= lo) e = probe_below(G.nbr, start, s, pos, lo, &ev);
             if (two_pass) {
                 nxt[k] = e;
                 nval[k] = ev;
@@ -826,10 +937,7 @@ __device__ void sweep_small(const Ranked &G, const Acc &A, uint32_t r, uint32_t 
         DenseAgg<T> agg{words, lo, hi - lo, half, A.err};
         agg.init();
         uint32_t e = cur, ev = val;
-        if (cur < pos && val >= lo) {
-            e = gallop_below(p, cur, pos, lo);
-            ev = e < pos ? p[e] : 0u;
-        }
+        if (cur < pos && val >= lo) e = probe_below(G.nbr, start, cur, pos, lo, &ev);
         __syncthreads();
         uint32_t total, nne;
         compact_runs<T>(k, start, cur, e - cur, sh, &total, &nne);
@@ -1358,11 +1466,12 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         uint32_t *vs;
         PB_TRY(radix_sort_pairs(k0, v0, k1, v1, ns, 2 * b, ws, &ks, &vs));
 
-        uint32_t *nbr = ws.alloc<uint32_t>(ns);
+        uint32_t *nbr = ws.alloc<uint32_t>(ns + NBR_PAD);
         eslot = ws.alloc<uint32_t>(ns);
         uint32_t *hideg = ws.alloc<uint32_t>(n + 1), *upoff = ws.alloc<uint32_t>(n + 1);
         if (ws.failed) return PB_ERR_NO_MEMORY;
         PB_TRY(fill<uint32_t>(hideg, 0u, n + 1, s));
+        PB_TRY(fill<uint32_t>(nbr + ns, 0u, NBR_PAD, s));
         hipLaunchKernelGGL(k_slots, dim3(grid_for(ns)), dim3(256), 0, s, ks, vs, ns, b, smid, roff, nbr, eslot,
                            hideg);
         PB_TRY((scan_exclusive<uint32_t, uint32_t>(hideg, upoff, n, upoff + n, ws)));
@@ -1402,8 +1511,8 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         uint64_t *wl = ws.alloc<uint64_t>((uint64_t)NSORTED * n);
         if (ws.failed) return PB_ERR_NO_MEMORY;
         PB_TRY((scan_exclusive<uint32_t, uint64_t>(uplen, wscan, m, wscan + m, ws)));
-        hipLaunchKernelGGL(k_plan, dim3(grid_for(n)), dim3(256), 0, s, upoff, wscan, smid, cend, n, pol, hub_base,
-                           hub_end, (const unsigned long long *)hub_roww, lists, nwin, wl, pc);
+        hipLaunchKernelGGL(k_plan, dim3(grid_for(n, 256, PLAN_GRID)), dim3(256), 0, s, upoff, wscan, smid, cend, n,
+                           pol, hub_base, hub_end, (const unsigned long long *)hub_roww, lists, nwin, wl, pc);
         PB_TRY_HIP(hipGetLastError());
         PB_TRY_HIP(hipMemcpyAsync(hpc, pc, sizeof(PlanCounts), hipMemcpyDeviceToHost, s));
         PB_TRY_HIP(hipMemcpyAsync(&wtotal, wscan + m, sizeof(uint64_t), hipMemcpyDeviceToHost, s));

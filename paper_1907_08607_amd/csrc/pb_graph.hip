@@ -42,7 +42,7 @@ __device__ inline uint32_t row_of(const int64_t *u_off, uint32_t lo, uint32_t hi
 // searches that (short) range.
 __global__ __launch_bounds__(EDGE_BLOCK) void k_edge_rows(const int64_t *u_off, const uint32_t *u_adj,
                                                           uint32_t n_u, uint32_t n_v, uint64_t m,
-                                                          uint32_t *eu, uint32_t *vdeg, uint32_t *flags) {
+                                                          uint32_t *eu, uint32_t *flags) {
     __shared__ uint32_t s_lo, s_hi;
     const uint64_t e0 = (uint64_t)blockIdx.x * EDGES_PER_BLOCK;
     const uint64_t e1 = e0 + EDGES_PER_BLOCK < m ? e0 + EDGES_PER_BLOCK : m;
@@ -59,7 +59,6 @@ __global__ __launch_bounds__(EDGE_BLOCK) void k_edge_rows(const int64_t *u_off, 
         eu[e] = r;
         const uint32_t v = u_adj[e];
         if (v >= n_v) bad |= BAD_ID;
-        else atomicAdd(&vdeg[v], 1u);
         if ((int64_t)e > u_off[r] && e > 0 && u_adj[e - 1] >= v) bad |= NOT_INCREASING;
     }
     if (bad) atomicOr(flags, bad);
@@ -73,14 +72,30 @@ __global__ void k_iota_keys(const uint32_t *u_adj, uint64_t m, uint64_t *keys, u
     }
 }
 
+// V-side row offsets from the edges sorted by V id: position p starts the
+// rows of every id in (key[p-1], key[p]].  Skipped when an id was out of
+// range (the keys are then not a valid order and the call fails anyway).
+__global__ void k_voff_from_sorted(const uint64_t *key, uint64_t m, uint32_t n_v, const uint32_t *flags,
+                                   uint32_t *v_off) {
+    if (flags[0] & BAD_ID) return;
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p <= m;
+         p += (uint64_t)gridDim.x * blockDim.x) {
+        const int64_t prev = p == 0 ? -1 : (int64_t)key[p - 1];
+        const int64_t cur = p == m ? (int64_t)n_v : (int64_t)key[p];
+        for (int64_t v = prev + 1; v <= cur; ++v) v_off[v] = (uint32_t)p;
+    }
+}
+
 __global__ void k_gather_u(const uint32_t *eids, const uint32_t *eu, uint64_t m, uint32_t *v_adj) {
     for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m;
          p += (uint64_t)gridDim.x * blockDim.x)
         v_adj[p] = eu[eids[p]];
 }
 
-__global__ void k_degrees(const int64_t *u_off, const uint32_t *v_off, uint32_t n_u, uint32_t n_v,
-                          uint32_t *deg, uint32_t *max_deg) {
+constexpr uint32_t DEG_GRID = 1024;
+__global__ __launch_bounds__(256) void k_degrees(const int64_t *u_off, const uint32_t *v_off, uint32_t n_u,
+                                                 uint32_t n_v, uint32_t *deg, uint32_t *max_deg) {
+    __shared__ uint32_t wmax[256 / WAVE];
     uint32_t best = 0;
     for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < (uint64_t)n_u + n_v;
          x += (uint64_t)gridDim.x * blockDim.x) {
@@ -94,7 +109,12 @@ __global__ void k_degrees(const int64_t *u_off, const uint32_t *v_off, uint32_t 
         const uint32_t o = __shfl_xor(best, s, WAVE);
         best = o > best ? o : best;
     }
-    if ((threadIdx.x & (WAVE - 1)) == 0) atomicMax(max_deg, best);
+    if ((threadIdx.x & (WAVE - 1)) == 0) wmax[threadIdx.x / WAVE] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 256 / WAVE; ++i) best = wmax[i] > best ? wmax[i] : best;
+        atomicMax(max_deg, best);
+    }
 }
 
 inline uint32_t grid_for(uint64_t n, uint32_t block = 256, uint32_t cap = 65536) {
@@ -159,8 +179,12 @@ __global__ void k_scatter_rank(const uint32_t *ids, uint64_t n, uint32_t *rank) 
 }
 
 // Complement-coreness rounds.
-__global__ void k_codeg_max(const uint32_t *cur, const uint32_t *alive, uint64_t n, int approx,
-                            uint32_t *best) {
+// The largest key among the remaining vertices (+1, so 0 means none left):
+// reduced in the block first, one atomic per block.
+constexpr uint32_t CODEG_MAX_GRID = 1024;
+__global__ __launch_bounds__(256) void k_codeg_max(const uint32_t *cur, const uint32_t *alive, uint64_t n, int approx,
+                                                   uint32_t *best) {
+    __shared__ uint32_t wmax[256 / WAVE];
     uint32_t b = 0;
     for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
          x += (uint64_t)gridDim.x * blockDim.x)
@@ -172,7 +196,12 @@ __global__ void k_codeg_max(const uint32_t *cur, const uint32_t *alive, uint64_t
         const uint32_t o = __shfl_xor(b, s, WAVE);
         b = o > b ? o : b;
     }
-    if ((threadIdx.x & (WAVE - 1)) == 0 && b) atomicMax(best, b);
+    if ((threadIdx.x & (WAVE - 1)) == 0) wmax[threadIdx.x / WAVE] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 256 / WAVE; ++i) b = wmax[i] > b ? wmax[i] : b;
+        if (b) atomicMax(best, b);
+    }
 }
 
 __global__ void k_codeg_flags(const uint32_t *cur, const uint32_t *alive, uint64_t n, int approx,
@@ -199,16 +228,21 @@ __global__ void k_codeg_assign(const uint32_t *flag, const uint32_t *pos, uint64
 // One block per removed vertex: every neighbour loses one remaining neighbour.
 __global__ void k_codeg_decrement(const uint32_t *front, uint32_t nfront, const int64_t *u_off,
                                   const uint32_t *u_adj, const uint32_t *v_off, const uint32_t *v_adj,
-                                  uint32_t n_u, uint32_t *cur) {
+                                  uint32_t n_u, const uint32_t *alive, uint32_t *cur) {
     for (uint32_t i = blockIdx.x; i < nfront; i += gridDim.x) {
         const uint32_t x = front[i];
+        // a neighbour removed earlier keeps its key; only live ones are updated
         if (x < n_u) {
-            for (int64_t k = u_off[x] + threadIdx.x; k < u_off[x + 1]; k += blockDim.x)
-                atomicSub(&cur[n_u + u_adj[k]], 1u);
+            for (int64_t k = u_off[x] + threadIdx.x; k < u_off[x + 1]; k += blockDim.x) {
+                const uint32_t y = n_u + u_adj[k];
+                if (alive[y]) atomicSub(&cur[y], 1u);
+            }
         } else {
             const uint32_t v = x - n_u;
-            for (uint32_t k = v_off[v] + threadIdx.x; k < v_off[v + 1]; k += blockDim.x)
-                atomicSub(&cur[v_adj[k]], 1u);
+            for (uint32_t k = v_off[v] + threadIdx.x; k < v_off[v + 1]; k += blockDim.x) {
+                const uint32_t y = v_adj[k];
+                if (alive[y]) atomicSub(&cur[y], 1u);
+            }
         }
     }
 }
@@ -232,7 +266,8 @@ pb_status rank_codeg(pb_graph *g, bool approx, uint32_t *rank, hipStream_t s) {
         uint32_t next = 0;
         while (next < n) {
             if ((st = fill<uint32_t>(best, 0u, 1, s)) != PB_OK) break;
-            hipLaunchKernelGGL(k_codeg_max, dim3(grid_for(n)), dim3(256), 0, s, cur, alive, n, (int)approx, best);
+            hipLaunchKernelGGL(k_codeg_max, dim3(grid_for(n, 256, CODEG_MAX_GRID)), dim3(256), 0, s, cur, alive, n,
+                               (int)approx, best);
             hipLaunchKernelGGL(k_codeg_flags, dim3(grid_for(n)), dim3(256), 0, s, cur, alive, n, (int)approx,
                                best, flag);
             if ((st = scan_exclusive<uint32_t, uint32_t>(flag, pos, n, pos + n, ws)) != PB_OK) break;
@@ -246,7 +281,7 @@ pb_status rank_codeg(pb_graph *g, bool approx, uint32_t *rank, hipStream_t s) {
             const uint32_t nf = *host;
             if (nf == 0) { st = PB_ERR_HIP; break; }  // cannot happen while vertices remain
             hipLaunchKernelGGL(k_codeg_decrement, dim3(nf < 65536 ? nf : 65536), dim3(256), 0, s, front, nf,
-                               g->u_off, g->u_adj, g->v_off, g->v_adj, g->n_u, cur);
+                               g->u_off, g->u_adj, g->v_off, g->v_adj, g->n_u, alive, cur);
             if (hipGetLastError() != hipSuccess) { st = PB_ERR_HIP; break; }
             next += nf;
         }
@@ -268,6 +303,7 @@ void pb_opts_default(pb_opts *opts) {
     opts->wg_size = 0;
     opts->flags = 0;
     opts->stats = nullptr;
+    opts->tuning = nullptr;
 }
 
 const char *pb_status_str(pb_status s) {
@@ -315,22 +351,19 @@ pb_status pb_graph_create(const pb_csr *csr, hipStream_t s, pb_graph **out) {
                   hipMalloc(&g->deg, (n ? n : 1) * sizeof(uint32_t)) == hipSuccess &&
                   hipHostMalloc((void **)&hflags, 2 * sizeof(uint32_t), hipHostMallocDefault) == hipSuccess;
         if (!ok) st = PB_ERR_NO_MEMORY;
-        uint32_t *vdeg = ok ? ws.alloc<uint32_t>(g->n_v + 1) : nullptr;
-        if (ok && !vdeg) st = PB_ERR_NO_MEMORY;
         do {
             if (st != PB_OK) break;
             if ((st = fill<uint32_t>(flags, 0u, 2, s)) != PB_OK) break;
-            if ((st = fill<uint32_t>(vdeg, 0u, g->n_v + 1, s)) != PB_OK) break;
             hipLaunchKernelGGL(k_check_offsets, dim3(grid_for(g->n_u + 1ull)), dim3(256), 0, s, g->u_off, g->n_u, m,
                                flags);
             if (m > 0 && g->n_u > 0) {
                 hipLaunchKernelGGL(k_edge_rows, dim3(ceil_div(m, EDGES_PER_BLOCK)), dim3(EDGE_BLOCK), 0, s, g->u_off,
-                                   g->u_adj, g->n_u, g->n_v, m, g->eu, vdeg, flags);
+                                   g->u_adj, g->n_u, g->n_v, m, g->eu, flags);
             }
             if (hipGetLastError() != hipSuccess) { st = PB_ERR_HIP; break; }
-            // V-side CSR: offsets by counting, rows by a stable sort of edge ids by V id.
-            if ((st = scan_exclusive<uint32_t, uint32_t>(vdeg, g->v_off, g->n_v, g->v_off + g->n_v, ws)) != PB_OK)
-                break;
+            // V-side CSR: a stable sort of edge ids by V id gives the rows, and
+            // the sorted ids give the offsets.
+            if (m == 0 && (st = fill<uint32_t>(g->v_off, 0u, g->n_v + 1ull, s)) != PB_OK) break;
             if (m > 0) {
                 uint64_t *k0 = ws.alloc<uint64_t>(m), *k1 = ws.alloc<uint64_t>(m);
                 uint32_t *v0 = ws.alloc<uint32_t>(m), *v1 = ws.alloc<uint32_t>(m);
@@ -342,9 +375,11 @@ pb_status pb_graph_create(const pb_csr *csr, hipStream_t s, pb_graph **out) {
                     PB_OK)
                     break;
                 hipLaunchKernelGGL(k_gather_u, dim3(grid_for(m)), dim3(256), 0, s, vr, g->eu, m, g->v_adj);
+                hipLaunchKernelGGL(k_voff_from_sorted, dim3(grid_for(m + 1)), dim3(256), 0, s, (const uint64_t *)kr, m,
+                                   g->n_v, (const uint32_t *)flags, g->v_off);
             }
-            hipLaunchKernelGGL(k_degrees, dim3(grid_for(n)), dim3(256), 0, s, g->u_off, g->v_off, g->n_u, g->n_v,
-                               g->deg, flags + 1);
+            hipLaunchKernelGGL(k_degrees, dim3(grid_for(n, 256, DEG_GRID)), dim3(256), 0, s, g->u_off, g->v_off,
+                               g->n_u, g->n_v, g->deg, flags + 1);
             if (hipGetLastError() != hipSuccess) { st = PB_ERR_HIP; break; }
             if (hipMemcpyAsync(hflags, flags, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess) {
@@ -390,7 +425,7 @@ pb_status pb_rank(pb_graph *g, pb_rank_kind kind, uint32_t *rank, hipStream_t s)
             if (!sums) return PB_ERR_NO_MEMORY;
             PB_TRY(fill<uint64_t>((uint64_t *)sums, 0ull, 2, s));
             if (kind == PB_RANK_SIDE_AUTO)
-                hipLaunchKernelGGL(k_side_sums, dim3(grid_for(n)), dim3(256), 0, s, g->deg, g->n_u, g->n_v, sums);
+                hipLaunchKernelGGL(k_side_sums, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, g->deg, g->n_u, g->n_v, sums);
             const int mode = kind == PB_RANK_SIDE_U_FIRST ? 0 : kind == PB_RANK_SIDE_V_FIRST ? 1 : 2;
             hipLaunchKernelGGL(k_side_rank, dim3(grid_for(n)), dim3(256), 0, s, g->n_u, g->n_v, mode, sums, rank);
             PB_TRY_HIP(hipGetLastError());

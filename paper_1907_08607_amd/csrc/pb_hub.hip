@@ -254,7 +254,7 @@ pb_status hub_tile(const HubIn &in, HubCounters *hc, const HubOut &out, Workspac
     if (ws.failed) return PB_ERR_NO_MEMORY;
     *gemm_grid = grid;
     hipLaunchKernelGGL(k_hub_rank, dim3(grid_for(n)), dim3(256), 0, s, in.smid, n, in.base, in.end, out.hub_rank);
-    hipLaunchKernelGGL(k_hub_mark, dim3(grid_for(n)), dim3(256), 0, s, in, keep, hc);
+    hipLaunchKernelGGL(k_hub_mark, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, in, keep, hc);
     PB_TRY_HIP(hipGetLastError());
     PB_TRY((scan_exclusive<uint32_t, uint32_t>(keep, coff, n, coff + n, ws)));
     hipLaunchKernelGGL(k_hub_decide, dim3(1), dim3(1), 0, s, (const uint32_t *)(coff + n), hc, in.force);

@@ -66,7 +66,7 @@ def test_fig2_wedges():
 
 
 def test_fig1_any_order_same_counts():
-    """Ordering does not change the counts (Section 4.1): all 720 orders."""
+    """Ordering does not change the counts (Section 4.3): all 720 orders."""
     from itertools import permutations
     d, g = fig1()
     seen_w = set()
