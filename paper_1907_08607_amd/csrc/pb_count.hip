@@ -718,6 +718,7 @@ struct RunShared {
     uint32_t kidx[T];   // its up-slot index
     unsigned long long sum[T];
     unsigned long long tmp64[T / WAVE + 1];
+    uint32_t mark[T];   // per wave: run starts inside the current 64-wedge tile
 };
 
 // Largest i in [lo, n) with off[i] <= f (off strictly increasing, off[lo] <= f).
@@ -768,13 +769,24 @@ __device__ inline void compact_runs(uint32_t k, uint32_t start, uint32_t a, uint
 // Walks the compacted wedge sequence of one chunk (see count_item): pass 1
 // inserts each x2 into the aggregator; pass 2 credits R-1 to the slot
 // (y -> x2) and sums it per run into sh.sum.
-template <int T, int U, class Agg>
-__device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, RunShared<T> &sh, int pass,
-                                 uint32_t total, uint32_t nne) {
+//
+// A wave holds 64 consecutive runs, one per lane (flat start o and slot
+// offset dlt = slot - flat index).  For a tile of 64 consecutive wedges, the
+// runs starting inside the tile are marked in a 64-byte LDS strip and
+// gathered with one ballot; a lane's run is then the run holding the tile's
+// first wedge plus the number of marked starts up to its own position.
+template <int T, int U, int PASS, class Agg>
+__device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, RunShared<T> &sh, uint32_t total,
+                                 uint32_t nne) {
     const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
     const bool edge = A.mode & MODE_EDGE;
-    // runs i0 .. i0+63 held one per lane: o = flat start, bg = slot
-    uint32_t i0 = 0, o = 0, bg = 0, o_end = 0;
+    // Lanes exchange data through this strip within one wave: relaxed
+    // wavefront-scope atomic accesses, so each store and load is issued as
+    // written (LDS runs one wave's operations in order).
+    uint32_t *mark = sh.mark + wv * WAVE;
+    const uint64_t le = lanemask_lt() | (1ull << lane);
+    // runs i0 .. i0+63 held one per lane
+    uint32_t i0 = 0, o = 0xFFFFFFFFu, dlt = 0, o_end = 0;
     for (uint32_t wb = wv * (U * WAVE); wb < total; wb += T * U) {
         uint32_t pidx[U], rel[U], xs[U];
         bool ok[U];
@@ -782,7 +794,7 @@ __device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, 
         for (int u = 0; u < U; ++u) {
             const uint32_t base = wb + u * WAVE;
             ok[u] = base + lane < total;
-            rel[u] = WAVE;
+            rel[u] = 0;
             pidx[u] = 0;
             if (base < total) {  // wave-uniform
                 const uint32_t last = base + WAVE - 1 < total ? base + WAVE - 1 : total - 1;
@@ -792,44 +804,37 @@ __device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, 
                     i0 = last_le(sh.off, i0, nne, base);
                     const uint32_t kk = i0 + lane;
                     o = kk < nne ? sh.off[kk] : 0xFFFFFFFFu;
-                    bg = kk < nne ? sh.begin[kk] : 0u;
+                    dlt = kk < nne ? sh.begin[kk] - o : 0u;
                     o_end = i0 + WAVE < nne ? sh.off[i0 + WAVE] : total;
                 }
                 const uint32_t f = base + lane;
-                uint32_t lo = 0;
-#pragma unroll
-                for (int step = WAVE / 2; step >= 1; step >>= 1) {
-                    const uint32_t cand = lo + step;
-                    if (__shfl(o, cand, WAVE) <= f) lo = cand;
-                }
-                const uint32_t ro = __shfl(o, lo, WAVE), rb = __shfl(bg, lo, WAVE);
-                pidx[u] = rb + (f - ro);
-                if (ok[u]) rel[u] = i0 + lo;
+                const uint32_t before = (uint32_t)__popcll(__ballot(o <= base));  // held runs starting <= base
+                __hip_atomic_store(&mark[lane], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                if (o > base && o - base < WAVE)
+                    __hip_atomic_store(&mark[o - base], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                const uint64_t starts =
+                    __ballot(__hip_atomic_load(&mark[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) != 0);
+                const uint32_t j = before - 1 + (uint32_t)__popcll(starts & le);
+                pidx[u] = __shfl(dlt, j, WAVE) + f;
+                rel[u] = i0 + j;
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (ok[u]) xs[u] = G.nbr[pidx[u]];
-        if (pass == 1) {
+        if (PASS == 1) {
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (ok[u]) agg.insert(xs[u]);
         } else {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (wb + u * WAVE >= total) break;  // wave-uniform
-                uint32_t d = ok[u] ? agg.count(xs[u]) - 1 : 0u;
-                if (d && edge) A.slot_add(pidx[u], d);
-                // segmented sum of d over lanes of the same run (runs are
-                // lane-contiguous); d < 2^22 so 64 of them fit 32 bits
-#pragma unroll
-                for (int sft = 1; sft < WAVE; sft <<= 1) {
-                    const uint32_t t = __shfl_down(d, sft, WAVE);
-                    const uint32_t tr = __shfl_down(rel[u], sft, WAVE);
-                    if (lane + sft < WAVE && tr == rel[u]) d += t;
+                if (!ok[u]) continue;
+                const uint32_t d = agg.count(xs[u]) - 1;
+                if (d) {
+                    if (edge) A.slot_add(pidx[u], d);
+                    atomicAdd(&sh.sum[rel[u]], (unsigned long long)d);
                 }
-                const uint32_t prev = __shfl_up(rel[u], 1, WAVE);
-                if (ok[u] && d && (lane == 0 || prev != rel[u])) atomicAdd(&sh.sum[rel[u]], (unsigned long long)d);
             }
         }
     }
@@ -904,7 +909,8 @@ __device__ bool count_item(const Ranked &G, const Acc &A, uint32_t r, const Agg 
             }
             uint32_t total, nne;
             compact_runs<T>(k, start, a, cnt, sh, &total, &nne);
-            if (pass == 1 || credit) walk_runs<T, U>(G, A, agg, sh, pass, total, nne);
+            if (pass == 1) walk_runs<T, U, 1>(G, A, agg, sh, total, nne);
+            else if (credit) walk_runs<T, U, 2>(G, A, agg, sh, total, nne);
             if (pass == 2) flush_runs<T>(G, A, r, k0, sh, nne);
         }
         if (pass == 1) {
@@ -941,10 +947,10 @@ __device__ void sweep_small(const Ranked &G, const Acc &A, uint32_t r, uint32_t 
         __syncthreads();
         uint32_t total, nne;
         compact_runs<T>(k, start, cur, e - cur, sh, &total, &nne);
-        walk_runs<T, U>(G, A, agg, sh, 1, total, nne);
+        walk_runs<T, U, 1>(G, A, agg, sh, total, nne);
         endpoint_credit<T>(G, A, r, agg, sh);
         if (credit) {
-            walk_runs<T, U>(G, A, agg, sh, 2, total, nne);
+            walk_runs<T, U, 2>(G, A, agg, sh, total, nne);
             flush_runs<T>(G, A, r, k0, sh, nne);
         }
         cur = e;
@@ -1138,7 +1144,7 @@ __global__ __launch_bounds__(T) void k_gh_walk(Ranked G, Acc A, const GhSrc *src
             }
             uint32_t total, nne;
             compact_runs<T>(k, start, 0u, cnt, sh, &total, &nne);
-            walk_runs<T, U>(G, A, agg, sh, PASS, total, nne);
+            walk_runs<T, U, PASS>(G, A, agg, sh, total, nne);
             if (PASS == 2) flush_runs<T>(G, A, sr.r, k0, sh, nne);
         }
     }
@@ -1243,7 +1249,7 @@ __global__ __launch_bounds__(T) void k_count_hub_pass(Ranked G, Acc A, const uin
             }
             uint32_t total, nne;
             compact_runs<T>(k, start, a, cnt, sh, &total, &nne);
-            walk_runs<T, U>(G, A, agg, sh, 2, total, nne);
+            walk_runs<T, U, 2>(G, A, agg, sh, total, nne);
             flush_runs<T>(G, A, r, k0, sh, nne);
         }
     }
