@@ -225,24 +225,61 @@ __global__ void k_codeg_assign(const uint32_t *flag, const uint32_t *pos, uint64
         }
 }
 
-// One block per removed vertex: every neighbour loses one remaining neighbour.
-__global__ void k_codeg_decrement(const uint32_t *front, uint32_t nfront, const int64_t *u_off,
-                                  const uint32_t *u_adj, const uint32_t *v_off, const uint32_t *v_adj,
-                                  uint32_t n_u, const uint32_t *alive, uint32_t *cur) {
-    for (uint32_t i = blockIdx.x; i < nfront; i += gridDim.x) {
-        const uint32_t x = front[i];
-        // a neighbour removed earlier keeps its key; only live ones are updated
+// A removed vertex of degree at most DEC_SMALL is handled by one thread;
+// a larger one is visited in items of DEC_CHUNK neighbours, one workgroup
+// each, so one huge vertex spreads over many workgroups instead of forming
+// one serial chain.
+constexpr uint32_t DEC_SMALL = 64;
+constexpr uint32_t DEC_CHUNK = 2048;
+constexpr uint32_t DEC_GRID = 4096;
+
+__device__ inline void codeg_drop(uint32_t y, const uint32_t *alive, uint32_t *cur) {
+    if (alive[y]) atomicSub(&cur[y], 1u);  // a neighbour removed earlier keeps its key
+}
+
+// Small front vertices (one thread each); chunk counts of the large ones.
+__global__ void k_codeg_small(const uint32_t *front, uint32_t nfront, const uint32_t *deg, const int64_t *u_off,
+                              const uint32_t *u_adj, const uint32_t *v_off, const uint32_t *v_adj, uint32_t n_u,
+                              const uint32_t *alive, uint32_t *cur, uint32_t *cnt) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nfront;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t x = front[i], d = deg[x];
+        if (d > DEC_SMALL) {
+            cnt[i] = (d + DEC_CHUNK - 1) / DEC_CHUNK;
+            continue;
+        }
+        cnt[i] = 0;
         if (x < n_u) {
-            for (int64_t k = u_off[x] + threadIdx.x; k < u_off[x + 1]; k += blockDim.x) {
-                const uint32_t y = n_u + u_adj[k];
-                if (alive[y]) atomicSub(&cur[y], 1u);
-            }
+            for (int64_t k = u_off[x]; k < u_off[x + 1]; ++k) codeg_drop(n_u + u_adj[k], alive, cur);
+        } else {
+            for (uint32_t k = v_off[x - n_u]; k < v_off[x - n_u + 1]; ++k) codeg_drop(v_adj[k], alive, cur);
+        }
+    }
+}
+
+// Large front vertices: every live neighbour loses one remaining neighbour.
+// Item `it` belongs to the front vertex i with coff[i] <= it < coff[i + 1].
+__global__ void k_codeg_decrement(const uint32_t *front, const uint32_t *coff, uint32_t nfront,
+                                  const int64_t *u_off, const uint32_t *u_adj, const uint32_t *v_off,
+                                  const uint32_t *v_adj, uint32_t n_u, const uint32_t *alive, uint32_t *cur) {
+    const uint32_t items = coff[nfront];
+    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+        uint32_t lo = 0, hi = nfront;  // coff[lo] <= it < coff[hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (coff[mid] <= it) lo = mid; else hi = mid;
+        }
+        const uint32_t x = front[lo];
+        const uint64_t skip = (uint64_t)(it - coff[lo]) * DEC_CHUNK;
+        if (x < n_u) {
+            const int64_t b = u_off[x] + (int64_t)skip, e = u_off[x + 1];
+            const int64_t end = b + DEC_CHUNK < e ? b + DEC_CHUNK : e;
+            for (int64_t k = b + threadIdx.x; k < end; k += blockDim.x) codeg_drop(n_u + u_adj[k], alive, cur);
         } else {
             const uint32_t v = x - n_u;
-            for (uint32_t k = v_off[v] + threadIdx.x; k < v_off[v + 1]; k += blockDim.x) {
-                const uint32_t y = v_adj[k];
-                if (alive[y]) atomicSub(&cur[y], 1u);
-            }
+            const uint64_t b = v_off[v] + skip, e = v_off[v + 1];
+            const uint64_t end = b + DEC_CHUNK < e ? b + DEC_CHUNK : e;
+            for (uint64_t k = b + threadIdx.x; k < end; k += blockDim.x) codeg_drop(v_adj[k], alive, cur);
         }
     }
 }
@@ -253,6 +290,7 @@ pb_status rank_codeg(pb_graph *g, bool approx, uint32_t *rank, hipStream_t s) {
     uint32_t *cur = ws.alloc<uint32_t>(n), *alive = ws.alloc<uint32_t>(n);
     uint32_t *flag = ws.alloc<uint32_t>(n), *pos = ws.alloc<uint32_t>(n + 1);
     uint32_t *front = ws.alloc<uint32_t>(n), *best = ws.alloc<uint32_t>(1);
+    uint32_t *ccnt = ws.alloc<uint32_t>(n + 1), *coff = ws.alloc<uint32_t>(n + 1);
     uint32_t *host = nullptr;
     if (ws.failed) return PB_ERR_NO_MEMORY;
     PB_TRY_HIP(hipHostMalloc((void **)&host, sizeof(uint32_t), hipHostMallocDefault));
@@ -280,8 +318,13 @@ pb_status rank_codeg(pb_graph *g, bool approx, uint32_t *rank, hipStream_t s) {
             }
             const uint32_t nf = *host;
             if (nf == 0) { st = PB_ERR_HIP; break; }  // cannot happen while vertices remain
-            hipLaunchKernelGGL(k_codeg_decrement, dim3(nf < 65536 ? nf : 65536), dim3(256), 0, s, front, nf,
-                               g->u_off, g->u_adj, g->v_off, g->v_adj, g->n_u, alive, cur);
+            hipLaunchKernelGGL(k_codeg_small, dim3(grid_for(nf)), dim3(256), 0, s, (const uint32_t *)front, nf,
+                               (const uint32_t *)g->deg, g->u_off, g->u_adj, g->v_off, g->v_adj, g->n_u,
+                               (const uint32_t *)alive, cur, ccnt);
+            if ((st = scan_exclusive<uint32_t, uint32_t>(ccnt, coff, nf, coff + nf, ws)) != PB_OK) break;
+            hipLaunchKernelGGL(k_codeg_decrement, dim3(DEC_GRID), dim3(256), 0, s, (const uint32_t *)front,
+                               (const uint32_t *)coff, nf, g->u_off, g->u_adj, g->v_off, g->v_adj, g->n_u,
+                               (const uint32_t *)alive, cur);
             if (hipGetLastError() != hipSuccess) { st = PB_ERR_HIP; break; }
             next += nf;
         }

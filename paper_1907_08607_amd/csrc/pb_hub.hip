@@ -70,25 +70,23 @@ __global__ void k_hub_rank(const uint32_t *smid, uint64_t n, uint32_t base, uint
 }
 
 __global__ void k_hub_mark(HubIn in, uint32_t *keep, HubCounters *hc) {
-    for (uint64_t b0 = (uint64_t)blockIdx.x * blockDim.x; b0 < in.n; b0 += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t r = b0 + threadIdx.x;
+    unsigned long long paths = 0;
+    HUB_GRID_STRIDE(r, in.n) {
         uint32_t flag = 0;
-        unsigned long long paths = 0;
-        if (r < in.n) {
-            if (other_side(in, in.smid[r])) {
-                const uint32_t o = in.roff[r], deg = in.roff[r + 1] - o;
-                const uint32_t hi = in.upoff[r + 1] - in.upoff[r];  // neighbours ranked above y
-                const uint32_t k = deg - tail_start(in.nbr + o, 0, deg, in.end);
-                if (k >= 2 && hi < deg) {
-                    flag = 1;
-                    paths = (unsigned long long)k * (k - 1) / 2;
-                }
+        if (other_side(in, in.smid[r])) {
+            const uint32_t o = in.roff[r], deg = in.roff[r + 1] - o;
+            const uint32_t hi = in.upoff[r + 1] - in.upoff[r];  // neighbours ranked above y
+            const uint32_t k = deg - tail_start(in.nbr + o, 0, deg, in.end);
+            if (k >= 2 && hi < deg) {
+                flag = 1;
+                paths += (unsigned long long)k * (k - 1) / 2;
             }
-            keep[r] = flag;
         }
-        paths = wave_sum(paths);
-        if ((threadIdx.x & (WAVE - 1)) == 0 && paths) atomicAdd(&hc->paths, paths);
+        keep[r] = flag;
     }
+    // one atomic per wave for the whole kernel
+    paths = wave_sum(paths);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && paths) atomicAdd(&hc->paths, paths);
 }
 
 __global__ void k_hub_decide(const uint32_t *cols, HubCounters *hc, bool force) {
