@@ -84,6 +84,77 @@ __global__ void k_slot_keys(const uint32_t *eu, const uint32_t *u_adj, const uin
     }
 }
 
+// Destination-major slot keys for one graph: destinations in decreasing rank
+// order, each followed by its slots (x -> y) for every neighbour x, taken
+// from y's row of its own side's CSR.  Row of destination rank d starts at
+// 2m - roff[d + 1].  A stable sort of these keys on the source-rank bits alone
+// then leaves every row in decreasing neighbour rank, as the full key
+// (source rank, complemented destination rank) requires.
+struct DestRows {
+    const uint32_t *order, *roff, *rank;
+    const int64_t *u_off;
+    const uint32_t *u_adj, *v_off, *v_adj, *v_eid;
+    uint32_t n_u;
+    uint64_t ns;
+    int b;
+};
+constexpr uint32_t DEST_SMALL = 64;    // rows up to this long: one thread each
+constexpr uint32_t DEST_CHUNK = 2048;  // longer rows: items of this many entries
+constexpr uint32_t DEST_GRID = 4096;
+
+__device__ inline void dest_entries(const DestRows &D, uint32_t d, uint64_t j0, uint64_t j1, uint64_t *keys,
+                                    uint32_t *vals, uint32_t stride) {
+    const uint64_t mask = (uint64_t(1) << D.b) - 1;
+    const uint32_t y = D.order[d];
+    const uint64_t q0 = D.ns - D.roff[d + 1];
+    const uint64_t low = mask - d;
+    if (y < D.n_u) {
+        const int64_t e0 = D.u_off[y];
+        for (uint64_t j = j0; j < j1; j += stride) {
+            const uint64_t e = (uint64_t)e0 + j;
+            keys[q0 + j] = ((uint64_t)D.rank[D.n_u + D.u_adj[e]] << D.b) | low;
+            vals[q0 + j] = (uint32_t)(2 * e + 1);  // slot (v -> u)
+        }
+    } else {
+        const uint32_t p0 = D.v_off[y - D.n_u];
+        for (uint64_t j = j0; j < j1; j += stride) {
+            const uint32_t p = p0 + (uint32_t)j;
+            keys[q0 + j] = ((uint64_t)D.rank[D.v_adj[p]] << D.b) | low;
+            vals[q0 + j] = 2 * D.v_eid[p];  // slot (u -> v)
+        }
+    }
+}
+
+// Short rows, one thread each; cnt = items of the long rows.
+__global__ void k_dest_small(DestRows D, uint64_t n, uint64_t *keys, uint32_t *vals, uint32_t *cnt) {
+    GRID_STRIDE(d, n) {
+        const uint32_t len = D.roff[d + 1] - D.roff[d];
+        if (len > DEST_SMALL) {
+            cnt[d] = (len + DEST_CHUNK - 1) / DEST_CHUNK;
+        } else {
+            cnt[d] = 0;
+            dest_entries(D, (uint32_t)d, 0, len, keys, vals, 1);
+        }
+    }
+}
+
+// Long rows: item `it` belongs to destination rank d with coff[d] <= it < coff[d + 1].
+__global__ void k_dest_long(DestRows D, uint64_t n, const uint32_t *coff, uint64_t *keys, uint32_t *vals) {
+    const uint32_t items = coff[n];
+    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
+        uint64_t lo = 0, hi = n;  // coff[lo] <= it < coff[hi]
+        while (hi - lo > 1) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (coff[mid] <= it) lo = mid; else hi = mid;
+        }
+        const uint32_t d = (uint32_t)lo;
+        const uint64_t len = D.roff[d + 1] - D.roff[d];
+        const uint64_t j0 = (uint64_t)(it - coff[d]) * DEST_CHUNK;
+        const uint64_t j1 = j0 + DEST_CHUNK < len ? j0 + DEST_CHUNK : len;
+        dest_entries(D, d, j0 + threadIdx.x, j1, keys, vals, blockDim.x);
+    }
+}
+
 __global__ void k_slots(const uint64_t *keys, const uint32_t *vals, uint64_t ns, int b, const uint32_t *smid,
                         const uint32_t *roff, uint32_t *nbr, uint32_t *eslot, uint32_t *hideg) {
     const uint64_t mask = (uint64_t(1) << b) - 1;
@@ -1331,6 +1402,9 @@ struct CoreIn {
     const uint32_t *rank;  // n
     uint32_t max_deg;
     BatchLayout bl;        // ng = 1 for one graph
+    // one graph: both sides' CSRs (null for a batch)
+    const int64_t *u_off;
+    const uint32_t *u_adj, *v_off, *v_adj, *v_eid;
 };
 
 bool policy_from(const pb_opts &o, Policy *p) {
@@ -1465,12 +1539,26 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         uint64_t *k0 = ws.alloc<uint64_t>(ns), *k1 = ws.alloc<uint64_t>(ns);
         uint32_t *v0 = ws.alloc<uint32_t>(ns), *v1 = ws.alloc<uint32_t>(ns);
         if (ws.failed) return PB_ERR_NO_MEMORY;
-        hipLaunchKernelGGL(k_slot_keys, dim3(grid_for(m)), dim3(256), 0, s, in.eu, in.ev, in.rank, m, in.n_u, b, k0,
-                           v0);
-        PB_TRY_HIP(hipGetLastError());
         uint64_t *ks;
         uint32_t *vs;
-        PB_TRY(radix_sort_pairs(k0, v0, k1, v1, ns, 2 * b, ws, &ks, &vs));
+        if (in.v_off) {
+            // one graph: destination-major keys, then a sort on the source bits only
+            uint32_t *dcnt = ws.alloc<uint32_t>(n + 1), *dcoff = ws.alloc<uint32_t>(n + 1);
+            if (ws.failed) return PB_ERR_NO_MEMORY;
+            const DestRows D{order, roff, in.rank, in.u_off, in.u_adj, in.v_off, in.v_adj, in.v_eid, in.n_u, ns, b};
+            hipLaunchKernelGGL(k_dest_small, dim3(grid_for(n)), dim3(256), 0, s, D, n, k0, v0, dcnt);
+            PB_TRY((scan_exclusive<uint32_t, uint32_t>(dcnt, dcoff, n, dcoff + n, ws)));
+            hipLaunchKernelGGL(k_dest_long, dim3(DEST_GRID), dim3(256), 0, s, D, n, (const uint32_t *)dcoff, k0, v0);
+            PB_TRY_HIP(hipGetLastError());
+            ws.release(dcoff);
+            ws.release(dcnt);
+            PB_TRY(radix_sort_pairs_bits(k0, v0, k1, v1, ns, b, 2 * b, ws, &ks, &vs));
+        } else {
+            hipLaunchKernelGGL(k_slot_keys, dim3(grid_for(m)), dim3(256), 0, s, in.eu, in.ev, in.rank, m, in.n_u, b,
+                               k0, v0);
+            PB_TRY_HIP(hipGetLastError());
+            PB_TRY(radix_sort_pairs(k0, v0, k1, v1, ns, 2 * b, ws, &ks, &vs));
+        }
 
         uint32_t *nbr = ws.alloc<uint32_t>(ns + NBR_PAD);
         eslot = ws.alloc<uint32_t>(ns);
@@ -1755,7 +1843,7 @@ pb_status count_impl(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, 
     PB_TRY(check_opts(opts_in, &opts, &pol));
     const int mode = (gout ? MODE_GLOBAL : 0) | (vout ? MODE_VERTEX : 0) | (eout ? MODE_EDGE : 0);
     CoreIn in{(uint64_t)g->n_u + g->n_v, g->n_u, g->m, g->eu, g->u_adj, g->deg, rank, g->max_deg,
-              BatchLayout{1, nullptr, nullptr, nullptr, nullptr}};
+              BatchLayout{1, nullptr, nullptr, nullptr, nullptr}, g->u_off, g->u_adj, g->v_off, g->v_adj, g->v_eid};
     CoreOut out{gout, vout, eout, nullptr, nullptr, nullptr};
     return count_core(in, out, mode, opts, pol, s, nullptr);
 }
@@ -1872,7 +1960,8 @@ pb_status build_batch(pb_graph *const *gs, const uint32_t *const *ranks, uint32_
     PB_TRY_HIP(hipStreamSynchronize(s));
     if (hflag & FLAG_BAD_RANK) return PB_ERR_BAD_RANK;
     bb->mode = (gouts ? MODE_GLOBAL : 0) | (vouts ? MODE_VERTEX : 0) | (eouts ? MODE_EDGE : 0);
-    bb->in = CoreIn{N, (uint32_t)U, M, eu, ev, deg, rank, max_deg, BatchLayout{count, d_ub, d_vb, d_rb, d_eb}};
+    bb->in = CoreIn{N, (uint32_t)U, M, eu, ev, deg, rank, max_deg, BatchLayout{count, d_ub, d_vb, d_rb, d_eb},
+                    nullptr, nullptr, nullptr, nullptr, nullptr};
     bb->out = CoreOut{nullptr, nullptr, nullptr, d_outs[0], d_outs[1], d_outs[2]};
     return PB_OK;
 }

@@ -86,10 +86,13 @@ __global__ void k_voff_from_sorted(const uint64_t *key, uint64_t m, uint32_t n_v
     }
 }
 
-__global__ void k_gather_u(const uint32_t *eids, const uint32_t *eu, uint64_t m, uint32_t *v_adj) {
+__global__ void k_gather_u(const uint32_t *eids, const uint32_t *eu, uint64_t m, uint32_t *v_adj, uint32_t *v_eid) {
     for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m;
-         p += (uint64_t)gridDim.x * blockDim.x)
-        v_adj[p] = eu[eids[p]];
+         p += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t e = eids[p];
+        v_adj[p] = eu[e];
+        v_eid[p] = e;
+    }
 }
 
 constexpr uint32_t DEG_GRID = 1024;
@@ -391,6 +394,7 @@ pb_status pb_graph_create(const pb_csr *csr, hipStream_t s, pb_graph **out) {
         bool ok = flags && hipMalloc(&g->eu, (m ? m : 1) * sizeof(uint32_t)) == hipSuccess &&
                   hipMalloc(&g->v_off, (g->n_v + 1) * sizeof(uint32_t)) == hipSuccess &&
                   hipMalloc(&g->v_adj, (m ? m : 1) * sizeof(uint32_t)) == hipSuccess &&
+                  hipMalloc(&g->v_eid, (m ? m : 1) * sizeof(uint32_t)) == hipSuccess &&
                   hipMalloc(&g->deg, (n ? n : 1) * sizeof(uint32_t)) == hipSuccess &&
                   hipHostMalloc((void **)&hflags, 2 * sizeof(uint32_t), hipHostMallocDefault) == hipSuccess;
         if (!ok) st = PB_ERR_NO_MEMORY;
@@ -417,7 +421,7 @@ pb_status pb_graph_create(const pb_csr *csr, hipStream_t s, pb_graph **out) {
                 if ((st = radix_sort_pairs(k0, v0, k1, v1, m, bits_for(g->n_v ? g->n_v - 1 : 0), ws, &kr, &vr)) !=
                     PB_OK)
                     break;
-                hipLaunchKernelGGL(k_gather_u, dim3(grid_for(m)), dim3(256), 0, s, vr, g->eu, m, g->v_adj);
+                hipLaunchKernelGGL(k_gather_u, dim3(grid_for(m)), dim3(256), 0, s, vr, g->eu, m, g->v_adj, g->v_eid);
                 hipLaunchKernelGGL(k_voff_from_sorted, dim3(grid_for(m + 1)), dim3(256), 0, s, (const uint64_t *)kr, m,
                                    g->n_v, (const uint32_t *)flags, g->v_off);
             }
@@ -451,6 +455,7 @@ void pb_graph_destroy(pb_graph *g) {
     if (g->eu) (void)hipFree(g->eu);
     if (g->v_off) (void)hipFree(g->v_off);
     if (g->v_adj) (void)hipFree(g->v_adj);
+    if (g->v_eid) (void)hipFree(g->v_eid);
     if (g->deg) (void)hipFree(g->deg);
     delete g;
 }

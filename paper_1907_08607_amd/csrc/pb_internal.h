@@ -87,6 +87,10 @@ pb_status scan_exclusive(const Tin *in, Tout *out, uint64_t n, Tout *total, Work
 // whichever pair holds the sorted result.  n < 2^32.
 pb_status radix_sort_pairs(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, uint64_t n,
                            int nbits, Workspace &ws, uint64_t **kres, uint32_t **vres);
+// The same over key bits [lo_bit, hi_bit) only (a stable sort, so pairs
+// equal in those bits keep their input order).
+pb_status radix_sort_pairs_bits(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, uint64_t n, int lo_bit,
+                                int hi_bit, Workspace &ws, uint64_t **kres, uint32_t **vres);
 
 template <class T>
 pb_status fill(T *p, T value, uint64_t n, hipStream_t s);
@@ -218,6 +222,7 @@ struct pb_graph {
     uint32_t *eu = nullptr;          // m: U endpoint of each edge
     uint32_t *v_off = nullptr;       // n_v + 1: V-side row offsets
     uint32_t *v_adj = nullptr;       // m: U ids, increasing within a row
+    uint32_t *v_eid = nullptr;       // m: edge id (position in u_adj) of each V-side entry
     uint32_t *deg = nullptr;         // n: degree per unified id
     uint32_t max_deg = 0;
     hipStream_t last_stream = nullptr;

@@ -186,16 +186,21 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *kin, 
 
 pb_status radix_sort_pairs(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, uint64_t n,
                            int nbits, Workspace &ws, uint64_t **kres, uint32_t **vres) {
+    return radix_sort_pairs_bits(k0, v0, k1, v1, n, 0, nbits, ws, kres, vres);
+}
+
+pb_status radix_sort_pairs_bits(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, uint64_t n, int lo_bit,
+                                int hi_bit, Workspace &ws, uint64_t **kres, uint32_t **vres) {
     *kres = k0;
     *vres = v0;
-    if (n <= 1 || nbits <= 0) return PB_OK;
+    if (n <= 1 || hi_bit <= lo_bit) return PB_OK;
     if (n >= (uint64_t(1) << 32)) return PB_ERR_INVALID_ARG;
     const uint32_t nb = ceil_div(n, RS_TILE);
     uint32_t *hist = ws.alloc<uint32_t>((uint64_t)nb * 256);
     if (!hist) return PB_ERR_NO_MEMORY;
     uint64_t *ks = k0, *kd = k1;
     uint32_t *vs = v0, *vd = v1;
-    for (int shift = 0; shift < nbits; shift += 8) {
+    for (int shift = lo_bit; shift < hi_bit; shift += 8) {
         hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_THREADS), 0, ws.stream, ks, n, shift, hist, nb);
         PB_TRY_HIP(hipGetLastError());
         PB_TRY((scan_exclusive<uint32_t, uint32_t>(hist, hist, (uint64_t)nb * 256, nullptr, ws)));

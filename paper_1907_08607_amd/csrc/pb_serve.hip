@@ -38,7 +38,7 @@ uint64_t scratch_bytes(const pb_graph *g) {
 uint64_t resident_bytes(const pb_graph *g) {
     const uint64_t n = (uint64_t)g->n_u + g->n_v, m = g->m;
     return 8 * ((uint64_t)g->n_u + 1) + 4 * m      // caller CSR
-           + 4 * m + 4 * ((uint64_t)g->n_v + 1) + 4 * m + 4 * n  // eu, v_off, v_adj, deg
+           + 4 * m + 4 * ((uint64_t)g->n_v + 1) + 8 * m + 4 * n  // eu, v_off, v_adj, v_eid, deg
            + 4 * n;                                // rank
 }
 

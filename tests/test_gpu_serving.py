@@ -83,7 +83,7 @@ def test_admission_by_footprint():
     Gs = [pb.Graph.from_csr(g) for g in gs]
     ranks = [pb.pb_rank(G, "degree") for G in Gs]
     # a budget that holds the pool but no scratch: every request is refused
-    resident = sum(8 * (G.n_u + 1) + 4 * G.m + 8 * G.m + 4 * (G.n_v + 1) + 8 * G.n for G in Gs)
+    resident = sum(8 * (G.n_u + 1) + 4 * G.m + 12 * G.m + 4 * (G.n_v + 1) + 8 * G.n for G in Gs)
     srv = pb.Server(hbm_budget=resident + 1024, slots=2, max_batch=4)
     gids = [srv.add_graph(G, r) for G, r in zip(Gs, ranks)]
     with pytest.raises(pb.PBError) as e:
