@@ -993,43 +993,6 @@ __device__ bool count_item(const Ranked &G, const Acc &A, uint32_t r, const Agg 
     return true;
 }
 
-// A heavy source with at most T up-slots: every thread keeps one run (slot
-// start, length, cursor and the value at the cursor) in registers across the
-// whole sweep of windows, and pass 2 reuses pass 1's compacted run table.
-template <int T, int U>
-__device__ void sweep_small(const Ranked &G, const Acc &A, uint32_t r, uint32_t *words, bool half, uint32_t ws,
-                            RunShared<T> &sh) {
-    const uint32_t tid = threadIdx.x;
-    const uint32_t k0 = G.upoff[r], k1 = G.upoff[r + 1];
-    const uint32_t k = k0 + tid;
-    const bool have = k < k1;
-    const uint32_t start = have ? G.uprun[k] : 0u, pos = have ? G.uplen[k] : 0u;
-    const uint32_t *p = G.nbr + start;
-    uint32_t cur = 0, val = pos ? p[0] : 0u;
-    const bool credit = A.mode & (MODE_VERTEX | MODE_EDGE);
-    const uint32_t lo_min = G.lo(r);
-    uint32_t hi = G.cend[r];
-    while (hi > lo_min) {
-        const uint32_t lo = hi - lo_min > ws ? hi - ws : lo_min;
-        DenseAgg<T> agg{words, lo, hi - lo, half, A.err};
-        agg.init();
-        uint32_t e = cur, ev = val;
-        if (cur < pos && val >= lo) e = probe_below(G.nbr, start, cur, pos, lo, &ev);
-        __syncthreads();
-        uint32_t total, nne;
-        compact_runs<T>(k, start, cur, e - cur, sh, &total, &nne);
-        walk_runs<T, U, 1>(G, A, agg, sh, total, nne);
-        endpoint_credit<T>(G, A, r, agg, sh);
-        if (credit) {
-            walk_runs<T, U, 2>(G, A, agg, sh, total, nne);
-            flush_runs<T>(G, A, r, k0, sh, nne);
-        }
-        cur = e;
-        val = ev;
-        hi = lo;
-    }
-}
-
 template <int T, int U, int CAP>
 __global__ __launch_bounds__(T) void k_count_hash(Ranked G, Acc A, const uint32_t *list, uint32_t count) {
     __shared__ uint32_t keys[CAP];
@@ -1058,31 +1021,219 @@ __global__ __launch_bounds__(T) void k_count_hash_win(Ranked G, Acc A, const uin
     }
 }
 
+// ---------------------------------------------------------------- wave-independent heavy sweep
+
+// Per-wave scratch of the wave-independent sweep.
+struct WaveRuns {
+    uint32_t mark[WAVE];             // run starts inside the current 64-wedge tile
+    unsigned long long sum[WAVE];    // pass-2 credit of each run
+};
+
+// Wave-level compaction of one chunk of 64 up-slots (lane = up-slot): the
+// non-empty run parts are laid end to end; lane i then holds the i-th one's
+// flat start `o`, slot offset `dlt` (slot = dlt + flat index) and up-slot
+// `kc`.  Lanes past the last part get o = ~0.
+__device__ inline void wave_compact(uint32_t cnt, uint32_t first_slot, uint32_t k, uint32_t lane, uint32_t &o,
+                                    uint32_t &dlt, uint32_t &kc, uint32_t &nne, uint32_t &total) {
+    const uint32_t incl = wave_inclusive_sum(cnt);
+    total = __builtin_amdgcn_readfirstlane(__shfl(incl, WAVE - 1, WAVE));
+    const uint32_t excl = incl - cnt;
+    const uint64_t ne = __ballot(cnt > 0);
+    nne = (uint32_t)__popcll(ne);
+    const uint32_t below = (uint32_t)__popcll(ne & lanemask_lt());
+    // a full permutation: parts to lanes 0 .. nne-1 in order, empty lanes after
+    const int tgt = (int)(4 * (cnt > 0 ? below : nne + (lane - below)));
+    o = (uint32_t)__builtin_amdgcn_ds_permute(tgt, (int)excl);
+    dlt = (uint32_t)__builtin_amdgcn_ds_permute(tgt, (int)(first_slot - excl));
+    kc = (uint32_t)__builtin_amdgcn_ds_permute(tgt, (int)k);
+    if (lane >= nne) o = 0xFFFFFFFFu;
+}
+
+// Walks the wedges of one compacted chunk (wave_compact) with no block
+// synchronisation: the same tile scheme as walk_runs, with every run held in
+// the wave from the start.
+template <int U, int PASS, class Agg>
+__device__ inline void wave_walk(const Ranked &G, const Acc &A, const Agg &agg, WaveRuns &wr, uint32_t o,
+                                 uint32_t dlt, uint32_t total, uint32_t lane) {
+    const bool edge = A.mode & MODE_EDGE;
+    const uint64_t le = lanemask_lt() | (1ull << lane);
+    if (PASS == 2) __hip_atomic_store(&wr.sum[lane], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    for (uint32_t wb = 0; wb < total; wb += U * WAVE) {
+        uint32_t pidx[U], rel[U], xs[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t base = wb + u * WAVE;
+            ok[u] = base + lane < total;
+            rel[u] = 0;
+            pidx[u] = 0;
+            if (base < total) {  // wave-uniform
+                const uint32_t before = (uint32_t)__popcll(__ballot(o <= base));
+                __hip_atomic_store(&wr.mark[lane], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                if (o > base && o - base < WAVE)
+                    __hip_atomic_store(&wr.mark[o - base], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                const uint64_t starts = __ballot(
+                    __hip_atomic_load(&wr.mark[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) != 0);
+                const uint32_t j = before - 1 + (uint32_t)__popcll(starts & le);
+                pidx[u] = __shfl(dlt, j, WAVE) + base + lane;
+                rel[u] = j;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (ok[u]) xs[u] = G.nbr[pidx[u]];
+        if (PASS == 1) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (ok[u]) agg.insert(xs[u]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (!ok[u]) continue;
+                const uint32_t d = agg.count(xs[u]) - 1;
+                if (d) {
+                    if (edge) A.slot_add(pidx[u], d);
+                    __hip_atomic_fetch_add(&wr.sum[rel[u]], (unsigned long long)d, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+                }
+            }
+        }
+    }
+}
+
+// Pass-2 run sums of one wave chunk: centre credit and slot (r -> y).
+__device__ inline void wave_flush(const Ranked &G, const Acc &A, uint32_t r, uint32_t k0, WaveRuns &wr, uint32_t kc,
+                                  uint32_t nne, uint32_t lane) {
+    if (lane < nne) {
+        const unsigned long long sm =
+            __hip_atomic_load(&wr.sum[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        if (sm) {
+            const uint32_t up = G.roff[r] + (kc - k0);  // slot (r -> y)
+            if (A.mode & MODE_VERTEX) atomicAdd(&A.v[G.nbr[up]], sm);
+            if (A.mode & MODE_EDGE) A.slot_add(up, sm);
+        }
+    }
+}
+
+// Endpoint step of one window, every wave on its own share of the counters.
+template <int T>
+__device__ inline void wave_endpoint(const Ranked &G, const Acc &A, uint32_t r, const DenseAgg<T> &agg,
+                                     uint32_t lane) {
+    unsigned long long local = 0;
+    const bool vert = A.mode & MODE_VERTEX;
+    agg.for_each([&](uint32_t key, uint32_t cc) {
+        if (cc >= 2) {
+            const unsigned long long t = (unsigned long long)cc * (cc - 1) / 2;
+            local += t;
+            if (vert) atomicAdd(&A.v[key], t);
+        }
+    });
+    local = wave_sum(local);
+    if (lane == 0 && local) {
+        if (A.mode & MODE_GLOBAL) atomicAdd(&A.g[G.gid ? G.gid[r] : 0u], local);
+        if (vert) atomicAdd(&A.v[G.smid[r]], local);
+    }
+}
+
 // Heavy sources: one workgroup per source sweeps the source's candidate range
 // from the top in windows that fit 128 KB of LDS counters (65536 ids with
 // 16-bit counters when the source has fewer than 65536 up-neighbours, since
-// R(x1, x2) <= deg_x1(x1); else 32768 ids).
+// R(x1, x2) <= deg_x1(x1); else 32768 ids).  Within a window the up-slots are
+// walked in one of two ways:
+//   * wave-independent (wave_compact / wave_walk): every wave takes its own
+//     chunks of 64 up-slots and the workgroup synchronises only between the
+//     window's passes -- for sources with at most T up-slots (each lane then
+//     keeps its run and cursor in registers for the whole sweep) and for
+//     sources whose runs are short (fewer than SHORT_RUN wedges per
+//     up-slot), where per-chunk block synchronisation would dominate;
+//   * block-wide chunks of T up-slots (count_item) for long runs, which keeps
+//     whole chunks' wedges in one balanced flat walk.
+constexpr uint64_t SHORT_RUN = 64;
+
 template <int T, int U>
-__global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32_t *list, uint32_t *cur, uint32_t *nxt,
-                                                   uint32_t *cval, uint32_t *nval, uint32_t count) {
+__global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32_t *list, const uint64_t *wsrc,
+                                                   uint32_t *cur, uint32_t *nxt, uint32_t *cval, uint32_t *nval,
+                                                   uint32_t count) {
+    constexpr uint32_t NW = T / WAVE;
+    static_assert(sizeof(WaveRuns) * NW <= sizeof(RunShared<T>), "wave scratch shares the run table's LDS");
     __shared__ uint32_t words[WIN_WORDS];
     __shared__ RunShared<T> sh;
+    const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
+    WaveRuns &wr = reinterpret_cast<WaveRuns *>(&sh)[wv];
     const bool two_pass = A.mode & (MODE_VERTEX | MODE_EDGE);
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
         const uint32_t r = list[i];
-        const bool half = G.upoff[r + 1] - G.upoff[r] <= 0xFFFFu;
-        const uint32_t ws = half ? 2 * WIN_WORDS : WIN_WORDS;
-        if (G.upoff[r + 1] - G.upoff[r] <= (uint32_t)T) {
-            sweep_small<T, U>(G, A, r, words, half, ws, sh);
-            continue;
-        }
+        const uint32_t k0 = G.upoff[r], k1 = G.upoff[r + 1], ups = k1 - k0;
+        const bool half = ups <= 0xFFFFu;
+        const uint32_t wsz = half ? 2 * WIN_WORDS : WIN_WORDS;
+        const bool small = ups <= (uint32_t)T;
+        const bool waves = small || wsrc[i] < SHORT_RUN * ups;
+        // small sources: lane state for up-slot k0 + tid
+        const uint32_t ks = k0 + tid;
+        const bool have = small && ks < k1;
+        const uint32_t s_start = have ? G.uprun[ks] : 0u, s_pos = have ? G.uplen[ks] : 0u;
+        uint32_t s_cur = 0, s_val = s_pos ? G.nbr[s_start] : 0u;
         const uint32_t lo_min = G.lo(r);
         uint32_t hi = G.cend[r];
         bool first = true;
+        __syncthreads();  // the previous source is done with the shared tables
         while (hi > lo_min) {
-            const uint32_t lo = hi - lo_min > ws ? hi - ws : lo_min;
-            DenseAgg<T> agg{words, lo, hi - lo, half, A.err};
-            count_item<T, U>(G, A, r, agg, CursorRange{cur, nxt, cval, nval, lo, first, two_pass}, sh, A.passes());
+            const uint32_t lo = hi - lo_min > wsz ? hi - wsz : lo_min;
+            const DenseAgg<T> agg{words, lo, hi - lo, half, A.err};
+            const CursorRange rng{cur, nxt, cval, nval, lo, first, two_pass};
+            if (!waves) {
+                count_item<T, U>(G, A, r, agg, rng, sh, A.passes());
+            } else {
+                {
+                    const uint32_t nwords = half ? (hi - lo + 1) >> 1 : hi - lo;
+                    for (uint32_t w = tid; w < nwords; w += T) words[w] = 0;
+                }
+                __syncthreads();
+                if (small) {
+                    uint32_t e = s_cur, ev = s_val;
+                    if (s_cur < s_pos && s_val >= lo) e = probe_below(G.nbr, s_start, s_cur, s_pos, lo, &ev);
+                    uint32_t o, dlt, kc, nne, total;
+                    wave_compact(e - s_cur, s_start + s_cur, ks, lane, o, dlt, kc, nne, total);
+                    wave_walk<U, 1>(G, A, agg, wr, o, dlt, total, lane);
+                    __syncthreads();
+                    if (two_pass) {
+                        wave_walk<U, 2>(G, A, agg, wr, o, dlt, total, lane);
+                        wave_flush(G, A, r, k0, wr, kc, nne, lane);
+                    }
+                    s_cur = e;
+                    s_val = ev;
+                } else {
+                    for (uint32_t c = k0 + wv * WAVE; c < k1; c += NW * WAVE) {
+                        const uint32_t k = c + lane;
+                        uint32_t a = 0, cnt = 0, start = 0;
+                        if (k < k1) {
+                            start = G.uprun[k];
+                            rng(G, 1, k, start, G.uplen[k], a, cnt);
+                        }
+                        uint32_t o, dlt, kc, nne, total;
+                        wave_compact(cnt, start + a, k, lane, o, dlt, kc, nne, total);
+                        wave_walk<U, 1>(G, A, agg, wr, o, dlt, total, lane);
+                    }
+                    __syncthreads();
+                    if (two_pass) {
+                        for (uint32_t c = k0 + wv * WAVE; c < k1; c += NW * WAVE) {
+                            const uint32_t k = c + lane;
+                            uint32_t a = 0, cnt = 0, start = 0;
+                            if (k < k1) {
+                                start = G.uprun[k];
+                                rng(G, 2, k, start, G.uplen[k], a, cnt);
+                            }
+                            uint32_t o, dlt, kc, nne, total;
+                            wave_compact(cnt, start + a, k, lane, o, dlt, kc, nne, total);
+                            wave_walk<U, 2>(G, A, agg, wr, o, dlt, total, lane);
+                            wave_flush(G, A, r, k0, wr, kc, nne, lane);
+                        }
+                    }
+                }
+                __syncthreads();
+                wave_endpoint<T>(G, A, r, agg, lane);
+                __syncthreads();
+            }
             hi = lo;
             first = false;
         }
@@ -1715,7 +1866,8 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
             if (c) {
                 switch (l) {
                     case L_DENSE_HEAVY:
-                        launch_items(k_count_heavy<1024, 4>, c, 1024, s, G, A, sorted_src[2], cur, nxt, cval, nval);
+                        launch_items(k_count_heavy<1024, 4>, c, 1024, s, G, A, sorted_src[2], sorted_w[2], cur, nxt,
+                                     cval, nval);
                         break;
                     case L_SORT_HEAVY:
                         launch_items(k_count_sort_heavy<256, 4, SORT_W>, c, 256, s, G, A, sorted_src[1], sorted_w[1],
