@@ -123,11 +123,15 @@ def cpu_baseline(g, wedges, target_s):
     deg_v = np.bincount(g.u_adj, minlength=g.n_v).astype(np.float64)
     # oracle work ~ 2 * sum over the centre side of deg^2 (it picks the smaller side)
     work = 2.0 * min(float((deg_u ** 2).sum()), float((deg_v ** 2).sum()))
-    probe_stride = max(1, int(work / 2e8))
-    t_probe = oracle.count_sample(g, probe_stride)
-    est_full = t_probe * probe_stride
-    stride = max(1, int(est_full / target_s))
-    t = oracle.count_sample(g, stride) if stride != probe_stride else t_probe
+    stride = max(1, int(work / 2e8))
+    t = oracle.count_sample(g, stride)
+    # the sampled endpoints are heavy-tailed: re-aim the stride until the
+    # sample itself takes between half and twice the target
+    for _ in range(3):
+        if stride == 1 or 0.5 * target_s <= t <= 2.0 * target_s:
+            break
+        stride = max(1, int(round(t * stride / target_s)))
+        t = oracle.count_sample(g, stride)
     est = t * stride
     return {"value": wedges / est, "unit": "wedges/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle dense 2-hop counter (global+vertex+edge) on every {stride}-th endpoint "
@@ -215,7 +219,23 @@ def run_batch(args):
                    "one_graph_per_launch_graphs_per_s": len(Gs) / single,
                    "speedup_vs_one_graph_per_launch": single / batched,
                    "same_results_as_one_graph_per_launch": same},
+        "cpu_baseline": None,
     }
+    if not args.no_cpu_baseline:
+        # the oracle on the batch's graphs in order, for about the target time
+        import oracle
+        print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
+        done, t_cpu = 0, 0.0
+        for g in graphs:
+            t1 = time.perf_counter()
+            oracle.count(g, want_vertex=False, want_edge=True)
+            t_cpu += time.perf_counter() - t1
+            done += 1
+            if t_cpu >= args.cpu_target_s:
+                break
+        record["cpu_baseline"] = {"value": done / t_cpu, "unit": "graphs/s", "cores": 1, "kind": "oracle",
+                                  "sample": f"oracle dense 2-hop counter (per-edge) on the first {done} of the "
+                                            f"{len(graphs)} graphs, one after another: {t_cpu:.1f} s"}
     print(json.dumps(record), flush=True)
 
 
@@ -234,6 +254,7 @@ def run_serve(args):
     print(f"[bench] pool of {len(graphs)} graphs generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     Gs = upload(graphs, pb)
     ranks = [pb.pb_rank(G, "degree") for G in Gs]
+    print(f"[bench] pool resident and ranked ({sum(G.m for G in Gs)} edges)", file=sys.stderr, flush=True)
     # one output set per graph (every request on a graph writes the same values)
     outs = [(torch.empty(1, dtype=torch.int64, device="cuda"), torch.empty(G.n, dtype=torch.int64, device="cuda"),
              torch.empty(max(G.m, 1), dtype=torch.int64, device="cuda")) for G in Gs]
@@ -253,6 +274,8 @@ def run_serve(args):
     gids = [srv.add_graph(G, r) for G, r in zip(Gs, ranks)]
     t_base = time.perf_counter()
     for i in range(n_req):
+        if i and i % 20000 == 0:
+            print(f"[bench] served {i} of {n_req} arrivals", file=sys.stderr, flush=True)
         wait = arrivals[i] - (time.perf_counter() - t_base)
         if wait > 0:
             time.sleep(wait)
@@ -272,7 +295,10 @@ def run_serve(args):
     names = {pb.WANT["global"]: (True, False, False), pb.WANT["vertex"]: (False, True, False),
              pb.WANT["edge"]: (False, False, True)}
     n_seq = min(n_req, args.seq_requests)
+    print("[bench] sequential replay", file=sys.stderr, flush=True)
     for i in range(n_seq):
+        if i and i % 5000 == 0:
+            print(f"[bench] sequential {i} of {n_seq}", file=sys.stderr, flush=True)
         now = time.perf_counter() - t_base
         if arrivals[i] > now:
             time.sleep(arrivals[i] - now)

@@ -856,27 +856,41 @@ __device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, 
     // written (LDS runs one wave's operations in order).
     uint32_t *mark = sh.mark + wv * WAVE;
     const uint64_t le = lanemask_lt() | (1ull << lane);
+    // each wave walks one contiguous share of whole 64-wedge tiles, so the
+    // held runs move forward with a ballot instead of a search
+    constexpr uint32_t NW = T / WAVE;
+    total = __builtin_amdgcn_readfirstlane(total);
+    nne = __builtin_amdgcn_readfirstlane(nne);
+    const uint32_t tiles = (total + WAVE - 1) / WAVE, per = (tiles + NW - 1) / NW;
+    const uint32_t t0 = wv * per < tiles ? wv * per : tiles, t1 = t0 + per < tiles ? t0 + per : tiles;
+    const uint32_t f1 = t1 * WAVE < total ? t1 * WAVE : total;
     // runs i0 .. i0+63 held one per lane
     uint32_t i0 = 0, o = 0xFFFFFFFFu, dlt = 0, o_end = 0;
-    for (uint32_t wb = wv * (U * WAVE); wb < total; wb += T * U) {
+    for (uint32_t wb = t0 * WAVE; wb < f1; wb += U * WAVE) {
         uint32_t pidx[U], rel[U], xs[U];
         bool ok[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t base = wb + u * WAVE;
-            ok[u] = base + lane < total;
+            ok[u] = base + lane < f1;
             rel[u] = 0;
             pidx[u] = 0;
-            if (base < total) {  // wave-uniform
-                const uint32_t last = base + WAVE - 1 < total ? base + WAVE - 1 : total - 1;
+            if (base < f1) {  // wave-uniform
+                const uint32_t last = base + WAVE - 1 < f1 ? base + WAVE - 1 : f1 - 1;
                 if (last >= o_end) {
                     // reload: the 64 runs from the one holding `base` always
-                    // cover [base, base + 64)
-                    i0 = last_le(sh.off, i0, nne, base);
+                    // cover [base, base + 64); that run is found among the
+                    // held ones when it is there
+                    const uint32_t c = (uint32_t)__popcll(__ballot(o <= base));
+                    uint32_t ni;
+                    if (c == 0) ni = last_le(sh.off, 0, nne, base);
+                    else if (c < WAVE) ni = i0 + c - 1;
+                    else ni = last_le(sh.off, i0 + WAVE - 1, nne, base);
+                    i0 = __builtin_amdgcn_readfirstlane(ni);
                     const uint32_t kk = i0 + lane;
                     o = kk < nne ? sh.off[kk] : 0xFFFFFFFFu;
                     dlt = kk < nne ? sh.begin[kk] - o : 0u;
-                    o_end = i0 + WAVE < nne ? sh.off[i0 + WAVE] : total;
+                    o_end = __builtin_amdgcn_readfirstlane(i0 + WAVE < nne ? sh.off[i0 + WAVE] : total);
                 }
                 const uint32_t f = base + lane;
                 const uint32_t before = (uint32_t)__popcll(__ballot(o <= base));  // held runs starting <= base
