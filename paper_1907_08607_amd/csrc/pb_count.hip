@@ -837,6 +837,19 @@ __device__ inline void compact_runs(uint32_t k, uint32_t start, uint32_t a, uint
     __syncthreads();
 }
 
+// Adds each lane's d to the run it belongs to: one prefix sum over the wave,
+// then the last lane of every run segment adds the segment's total.  `first`
+// is the lane where the lane's segment starts in this tile (0 if the run
+// began in an earlier tile).  Needs 64 * max d < 2^32.
+__device__ inline void segment_add(uint32_t d, bool ok, uint32_t first, bool last, unsigned long long *dst,
+                                   uint32_t lane) {
+    const uint32_t incl = wave_inclusive_sum(ok ? d : 0u);
+    const uint32_t before = __shfl(incl, first ? first - 1 : 0, WAVE);
+    const uint32_t seg = incl - (first ? before : 0u);
+    if (ok && last && seg)
+        __hip_atomic_fetch_add(dst, (unsigned long long)seg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Walks the compacted wedge sequence of one chunk (see count_item): pass 1
 // inserts each x2 into the aggregator; pass 2 credits R-1 to the slot
 // (y -> x2) and sums it per run into sh.sum.
@@ -868,10 +881,12 @@ __device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, 
     uint32_t i0 = 0, o = 0xFFFFFFFFu, dlt = 0, o_end = 0;
     for (uint32_t wb = t0 * WAVE; wb < f1; wb += U * WAVE) {
         uint32_t pidx[U], rel[U], xs[U];
+        uint64_t st[U];
         bool ok[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t base = wb + u * WAVE;
+            st[u] = 0;
             ok[u] = base + lane < f1;
             rel[u] = 0;
             pidx[u] = 0;
@@ -902,6 +917,7 @@ __device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, 
                 const uint32_t j = before - 1 + (uint32_t)__popcll(starts & le);
                 pidx[u] = __shfl(dlt, j, WAVE) + f;
                 rel[u] = i0 + j;
+                st[u] = starts;
             }
         }
 #pragma unroll
@@ -914,12 +930,13 @@ __device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, 
         } else {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (!ok[u]) continue;
-                const uint32_t d = agg.count(xs[u]) - 1;
-                if (d) {
-                    if (edge) A.slot_add(pidx[u], d);
-                    atomicAdd(&sh.sum[rel[u]], (unsigned long long)d);
-                }
+                if (wb + u * WAVE >= f1) break;  // wave-uniform
+                const uint32_t d = ok[u] ? agg.count(xs[u]) - 1 : 0u;
+                if (d && edge) A.slot_add(pidx[u], d);
+                const uint64_t sm = st[u] & le;
+                const uint32_t first = sm ? 63u - (uint32_t)__clzll(sm) : 0u;
+                const bool last = lane == WAVE - 1 || ((st[u] >> (lane + 1)) & 1) || !(wb + u * WAVE + lane + 1 < f1);
+                segment_add(d, ok[u], first, last, &sh.sum[rel[u]], lane);
             }
         }
     }
