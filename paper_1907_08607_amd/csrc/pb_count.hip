@@ -206,6 +206,7 @@ enum : int {
     L_DENSE_HEAVY,     // 1024-thread dense LDS windows swept with cursors
     L_DENSE_SMALL,     // 256-thread dense counters, candidate range <= 4096
     L_DENSE_GLOBAL,    // giant sources: dense histogram in global scratch, split over workgroups
+    L_HASH_PACKED,     // 1024-thread packed LDS hash: few wedges over a wide candidate range
     NLISTS
 };
 constexpr int NSORTED = 4;  // lists dispatched most-wedges-first
@@ -234,7 +235,17 @@ constexpr uint32_t GH_WG_PER_XCD = 256;
 struct Policy {
     uint32_t light_max, medium_max;
     int agg[3];
+    bool packed;  // AUTO: heavy-bucket sources with few wedges may take the packed hash
 };
+
+constexpr uint32_t PH_SLOTS = 32768;        // packed hash: 128 KB of LDS
+constexpr uint32_t PH_MAX_W = PH_SLOTS / 2;  // load factor at most one half
+
+__host__ __device__ inline uint32_t bit_width(uint32_t x) {
+    uint32_t b = 0;
+    while (b < 32 && (x >> b)) ++b;
+    return b;
+}
 
 struct PlanCounts {
     uint32_t list[NLISTS];
@@ -295,11 +306,18 @@ __global__ __launch_bounds__(256) void k_plan(const uint32_t *upoff, const uint6
                     case PB_AGG_RADIX_SORT:
                         which = w <= SORT_LIGHT_W ? L_SORT_LIGHT : w <= SORT_W ? L_SORT_MEDIUM : L_SORT_HEAVY;
                         break;
-                    default:
-                        which = range <= SMALL_WIN                          ? L_DENSE_SMALL
-                                : upoff[r + 1] - upoff[r] >= GH_MIN_UPS ? L_DENSE_GLOBAL
-                                                                        : L_DENSE_HEAVY;
+                    default: {
+                        const uint32_t ups = upoff[r + 1] - upoff[r];
+                        which = range <= SMALL_WIN    ? L_DENSE_SMALL
+                                : ups >= GH_MIN_UPS ? L_DENSE_GLOBAL
+                                                    : L_DENSE_HEAVY;
+                        // a source with few wedges over a wide range: one
+                        // pass of a packed hash instead of many windows
+                        if (which == L_DENSE_HEAVY && pol.packed && w <= PH_MAX_W &&
+                            bit_width(range) + bit_width(ups) <= 32)
+                            which = L_HASH_PACKED;
                         break;
+                    }
                 }
                 local = atomicAdd(&cnt[which], 1u);
                 atomicAdd(&wsum[which], (unsigned long long)w);
@@ -591,6 +609,58 @@ struct HashAgg {
         for (uint32_t i = threadIdx.x; i < CAP; i += T) {
             const uint32_t k = keys[i];
             if (k != EMPTY) f(k, cnts[i]);
+        }
+    }
+};
+
+// Linear-probing hash of (candidate, count) packed into one word,
+// (key + 1) << cbits | count with key = x2 - lo, 0 = empty.  Valid when
+// bits(range) + cbits <= 32 and cbits = bits(up-slots): a count never
+// exceeds the source's up-slots, since R(x1, x2) <= deg_x1(x1).
+template <int T, int CAP>
+struct PackedHashAgg {
+    uint32_t *w;
+    uint32_t lo, cbits;
+    uint32_t *err;
+    __device__ static uint32_t slot(uint32_t key) { return (key * 2654435769u) >> (32 - __builtin_ctz(CAP)); }
+    __device__ void init() const {
+        for (uint32_t i = threadIdx.x; i < CAP; i += T) w[i] = 0;
+    }
+    // The planner keeps the wedges (an upper bound on the keys) at most CAP/2.
+    __device__ void insert(uint32_t x) const {
+        const uint32_t key = x - lo, tag = key + 1;
+        uint32_t h = slot(key);
+        for (int probe = 0; probe < CAP; ++probe) {
+            uint32_t e = __hip_atomic_load(&w[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (e == 0) {
+                e = atomicCAS(&w[h], 0u, (tag << cbits) | 1u);
+                if (e == 0) return;
+            }
+            if ((e >> cbits) == tag) {
+                atomicAdd(&w[h], 1u);
+                return;
+            }
+            h = (h + 1) & (CAP - 1);
+        }
+        atomicOr(err, FLAG_INTERNAL);
+    }
+    __device__ bool finalize() const { return true; }
+    __device__ uint32_t count(uint32_t x) const {
+        const uint32_t key = x - lo, tag = key + 1;
+        uint32_t h = slot(key);
+        for (int probe = 0; probe < CAP; ++probe) {
+            const uint32_t e = w[h];
+            if ((e >> cbits) == tag) return e & ((1u << cbits) - 1);
+            if (e == 0) break;
+            h = (h + 1) & (CAP - 1);
+        }
+        return 1u;
+    }
+    template <class F>
+    __device__ void for_each(F f) const {
+        for (uint32_t i = threadIdx.x; i < CAP; i += T) {
+            const uint32_t e = w[i];
+            if (e) f(lo + (e >> cbits) - 1, e & ((1u << cbits) - 1));
         }
     }
 };
@@ -1328,6 +1398,19 @@ __global__ __launch_bounds__(T) void k_count_sort_heavy(Ranked G, Acc A, const u
     }
 }
 
+// Sources with few wedges over a wide candidate range: the whole source in one
+// pass of a packed LDS hash (no windows).
+template <int T, int U>
+__global__ __launch_bounds__(T) void k_count_phash(Ranked G, Acc A, const uint32_t *list, uint32_t count) {
+    __shared__ uint32_t words[PH_SLOTS];
+    __shared__ RunShared<T> sh;
+    for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
+        const uint32_t r = list[i];
+        const PackedHashAgg<T, PH_SLOTS> agg{words, G.lo(r), bit_width(G.upoff[r + 1] - G.upoff[r]), A.err};
+        count_item<T, U>(G, A, r, agg, full_range(G, r), sh, A.passes());
+    }
+}
+
 // Whole-range dense counting for sources whose candidate range fits WINSZ.
 template <int T, int U, int WINSZ>
 __global__ __launch_bounds__(T) void k_count_dense_src(Ranked G, Acc A, const uint32_t *list, uint32_t count) {
@@ -1590,7 +1673,7 @@ struct CoreIn {
 };
 
 bool policy_from(const pb_opts &o, Policy *p) {
-    *p = Policy{LIGHT_D, MEDIUM_D, {PB_AGG_LDS_HASH, PB_AGG_LDS_HASH, PB_AGG_DENSE_HIST}};
+    *p = Policy{LIGHT_D, MEDIUM_D, {PB_AGG_LDS_HASH, PB_AGG_LDS_HASH, PB_AGG_DENSE_HIST}, true};
     if (o.agg == PB_AGG_AUTO) {
         if (!o.tuning) return true;
         const pb_tuning &t = *o.tuning;
@@ -1598,11 +1681,12 @@ bool policy_from(const pb_opts &o, Policy *p) {
         for (int i = 0; i < 3; ++i)
             if (a[i] != PB_AGG_LDS_HASH && a[i] != PB_AGG_DENSE_HIST && a[i] != PB_AGG_RADIX_SORT) return false;
         if (t.light_max > LIGHT_D || t.medium_max > MEDIUM_D || t.light_max > t.medium_max) return false;
-        *p = Policy{t.light_max, t.medium_max, {a[0], a[1], a[2]}};
+        *p = Policy{t.light_max, t.medium_max, {a[0], a[1], a[2]}, true};
         return true;
     }
     if (o.agg != PB_AGG_LDS_HASH && o.agg != PB_AGG_DENSE_HIST && o.agg != PB_AGG_RADIX_SORT) return false;
     p->agg[0] = p->agg[1] = p->agg[2] = o.agg;
+    p->packed = false;  // a forced aggregator serves every source
     return true;
 }
 
@@ -1923,6 +2007,9 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
                     case L_DENSE_SMALL:
                         launch_items(k_count_dense_src<256, 4, SMALL_WIN>, c, 256, s, G, A, list_of(l));
                         break;
+                    case L_HASH_PACKED:
+                        launch_items(k_count_phash<1024, 4>, c, 1024, s, G, A, list_of(l));
+                        break;
                     case L_DENSE_GLOBAL: {
                         const dim3 grid(NXCD * GH_WG_PER_XCD);
                         PB_TRY(fill<uint32_t>(gh_hist, 0u, gh_total, s));
@@ -1979,11 +2066,13 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         pb_stats &st = *opts.stats;
         st.wedges = wtotal;
         st.sources = plan.sources;
-        st.sources_hash = plan.list[L_HASH_LIGHT] + plan.list[L_HASH_MEDIUM] + plan.list[L_HASH_WIN];
+        st.sources_hash =
+            plan.list[L_HASH_LIGHT] + plan.list[L_HASH_MEDIUM] + plan.list[L_HASH_WIN] + plan.list[L_HASH_PACKED];
         st.sources_dense = plan.list[L_DENSE_HEAVY] + plan.list[L_DENSE_SMALL] + plan.list[L_DENSE_GLOBAL];
         st.sources_sort = plan.list[L_SORT_LIGHT] + plan.list[L_SORT_MEDIUM] + plan.list[L_SORT_HEAVY];
         st.window_items = plan.items + plan.list[L_DENSE_HEAVY] + plan.list[L_SORT_HEAVY];
-        st.wedges_hash = plan.wedges[L_HASH_LIGHT] + plan.wedges[L_HASH_MEDIUM] + plan.wedges[L_HASH_WIN];
+        st.wedges_hash = plan.wedges[L_HASH_LIGHT] + plan.wedges[L_HASH_MEDIUM] + plan.wedges[L_HASH_WIN] +
+                         plan.wedges[L_HASH_PACKED];
         st.wedges_dense = plan.wedges[L_DENSE_HEAVY] + plan.wedges[L_DENSE_SMALL] + plan.wedges[L_DENSE_GLOBAL];
         st.wedges_sort = plan.wedges[L_SORT_LIGHT] + plan.wedges[L_SORT_MEDIUM] + plan.wedges[L_SORT_HEAVY];
         st.workspace_bytes = ws.peak;
@@ -1999,7 +2088,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
             st.ms_hub_gemm = t_gemm;
             st.ms_hub_pass = t_hub_pass;
             st.ms_prepare = t[0];
-            st.ms_hash = t[1 + L_HASH_LIGHT] + t[1 + L_HASH_MEDIUM] + t[1 + L_HASH_WIN];
+            st.ms_hash = t[1 + L_HASH_LIGHT] + t[1 + L_HASH_MEDIUM] + t[1 + L_HASH_WIN] + t[1 + L_HASH_PACKED];
             st.ms_dense = t[1 + L_DENSE_HEAVY] + t[1 + L_DENSE_SMALL] + t[1 + L_DENSE_GLOBAL];
             st.ms_sort = t[1 + L_SORT_LIGHT] + t[1 + L_SORT_MEDIUM] + t[1 + L_SORT_HEAVY];
             st.ms_output = t[1 + NLISTS];
@@ -2214,7 +2303,7 @@ pb_status pb_autotune(pb_graph *const *graphs, const uint32_t *const *ranks, uin
     BatchBuild bb;
     PB_TRY(build_batch(graphs, ranks, count, gp.data(), nullptr, ep.data(), ws, stream, &bb));
 
-    Policy best = Policy{LIGHT_D, MEDIUM_D, {PB_AGG_LDS_HASH, PB_AGG_LDS_HASH, PB_AGG_DENSE_HIST}};
+    Policy best = Policy{LIGHT_D, MEDIUM_D, {PB_AGG_LDS_HASH, PB_AGG_LDS_HASH, PB_AGG_DENSE_HIST}, true};
     auto time_policy = [&](const Policy &p, float *ms) -> pb_status {
         std::vector<float> runs;
         for (uint32_t rep = 0; rep < repeats; ++rep) {

@@ -214,3 +214,22 @@ def test_workspace_cap_too_small():
         pb.pb_count(G, r, workspace_cap=4096)
     assert e.value.status == -5
     G.close()
+
+
+def test_packed_hash_source():
+    """One source with a few thousand wedges over a wide candidate range: AUTO
+    counts it in one pass of the packed LDS hash (more than the 4096 distinct
+    endpoints of the medium hash, far fewer wedges than its dense windows would
+    sweep); the forced aggregators must agree."""
+    n_u, n_v = 9000, 8000
+    u = [0] * n_v + [1 + (v % 3000) for v in range(n_v)]
+    v = list(range(n_v)) * 2
+    g = gg.from_edges(n_u, n_v, u, v)
+    want = oracle.count(g)
+    rank = oracle.rank(g, "degree")
+    stats = pb.pb_stats()
+    assert_same(gpu_counts(g, rank, "auto", stats), want, "auto")
+    # U0's 8000 wedges (one per V neighbour) take a hash list in AUTO mode
+    assert stats.wedges_hash >= n_v
+    for agg in ("dense", "hash", "sort"):
+        assert_same(gpu_counts(g, rank, agg), want, agg)
