@@ -209,10 +209,10 @@ enum : int {
     L_HASH_PACKED,     // 1024-thread packed LDS hash: few wedges over a wide candidate range
     NLISTS
 };
-constexpr int NSORTED = 4;  // lists dispatched most-wedges-first
+constexpr int NSORTED = 5;  // lists dispatched most-wedges-first
 __host__ __device__ inline int sorted_slot(int list) {
     return list == L_HASH_WIN ? 0 : list == L_SORT_HEAVY ? 1 : list == L_DENSE_HEAVY ? 2
-                                  : list == L_DENSE_GLOBAL ? 3 : -1;
+                                  : list == L_DENSE_GLOBAL ? 3 : list == L_HASH_PACKED ? 4 : -1;
 }
 
 constexpr uint32_t LIGHT_D = 512;       // 1-wave hash: 1024 slots
@@ -238,8 +238,13 @@ struct Policy {
     bool packed;  // AUTO: heavy-bucket sources with few wedges may take the packed hash
 };
 
-constexpr uint32_t PH_SLOTS = 32768;        // packed hash: 128 KB of LDS
-constexpr uint32_t PH_MAX_W = PH_SLOTS / 2;  // load factor at most one half
+constexpr uint32_t PH_SLOTS = 32768;          // packed hash: 128 KB of LDS
+constexpr uint32_t PH_FULL = PH_SLOTS / 4 * 3;  // keys at which a window is refused and narrowed
+constexpr uint32_t PH_TARGET = 12288;          // keys a window is sized for
+// Sources with at most PH_SLOTS / 2 wedges (about one window), or sparser
+// than PH_DENSITY wedges per candidate, take packed-hash windows sized to
+// their wedges instead of dense windows sized to the LDS.
+constexpr double PH_DENSITY = 0.05;
 
 __host__ __device__ inline uint32_t bit_width(uint32_t x) {
     uint32_t b = 0;
@@ -311,9 +316,10 @@ __global__ __launch_bounds__(256) void k_plan(const uint32_t *upoff, const uint6
                         which = range <= SMALL_WIN    ? L_DENSE_SMALL
                                 : ups >= GH_MIN_UPS ? L_DENSE_GLOBAL
                                                     : L_DENSE_HEAVY;
-                        // a source with few wedges over a wide range: one
-                        // pass of a packed hash instead of many windows
-                        if (which == L_DENSE_HEAVY && pol.packed && w <= PH_MAX_W &&
+                        // few wedges over a wide range: packed-hash windows
+                        // sized to the wedges instead of many dense windows
+                        if (which == L_DENSE_HEAVY && pol.packed &&
+                            (w <= PH_SLOTS / 2 || (double)w < PH_DENSITY * range) &&
                             bit_width(range) + bit_width(ups) <= 32)
                             which = L_HASH_PACKED;
                         break;
@@ -617,24 +623,31 @@ struct HashAgg {
 // (key + 1) << cbits | count with key = x2 - lo, 0 = empty.  Valid when
 // bits(range) + cbits <= 32 and cbits = bits(up-slots): a count never
 // exceeds the source's up-slots, since R(x1, x2) <= deg_x1(x1).
-template <int T, int CAP>
+template <int T, int CAP, int FULL>
 struct PackedHashAgg {
     uint32_t *w;
+    uint32_t *keys;  // shared: keys inserted so far
     uint32_t lo, cbits;
     uint32_t *err;
     __device__ static uint32_t slot(uint32_t key) { return (key * 2654435769u) >> (32 - __builtin_ctz(CAP)); }
     __device__ void init() const {
         for (uint32_t i = threadIdx.x; i < CAP; i += T) w[i] = 0;
+        if (threadIdx.x == 0) *keys = 0;
     }
-    // The planner keeps the wedges (an upper bound on the keys) at most CAP/2.
+    // Once FULL keys are in (the table is then 3/4 full), further new keys are
+    // dropped and finalize() refuses the window: the caller narrows it.
     __device__ void insert(uint32_t x) const {
         const uint32_t key = x - lo, tag = key + 1;
         uint32_t h = slot(key);
         for (int probe = 0; probe < CAP; ++probe) {
             uint32_t e = __hip_atomic_load(&w[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (e == 0) {
+                if (__hip_atomic_load(keys, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= FULL) return;
                 e = atomicCAS(&w[h], 0u, (tag << cbits) | 1u);
-                if (e == 0) return;
+                if (e == 0) {
+                    atomicAdd(keys, 1u);
+                    return;
+                }
             }
             if ((e >> cbits) == tag) {
                 atomicAdd(&w[h], 1u);
@@ -644,7 +657,12 @@ struct PackedHashAgg {
         }
         atomicOr(err, FLAG_INTERNAL);
     }
-    __device__ bool finalize() const { return true; }
+    __device__ bool finalize() const {
+        __syncthreads();
+        const bool ok = *keys < FULL;
+        __syncthreads();  // everyone has read the count before anyone re-inits
+        return ok;
+    }
     __device__ uint32_t count(uint32_t x) const {
         const uint32_t key = x - lo, tag = key + 1;
         uint32_t h = slot(key);
@@ -860,6 +878,7 @@ struct RunShared {
     unsigned long long sum[T];
     unsigned long long tmp64[T / WAVE + 1];
     uint32_t mark[T];   // per wave: run starts inside the current 64-wedge tile
+    uint32_t keys;      // packed hash: keys inserted in the current window
 };
 
 // Largest i in [lo, n) with off[i] <= f (off strictly increasing, off[lo] <= f).
@@ -1398,16 +1417,35 @@ __global__ __launch_bounds__(T) void k_count_sort_heavy(Ranked G, Acc A, const u
     }
 }
 
-// Sources with few wedges over a wide candidate range: the whole source in one
-// pass of a packed LDS hash (no windows).
+// Sources with few wedges over a wide candidate range: packed-LDS-hash windows
+// from the top of the range, each first tried at a width that should hold
+// about PH_TARGET distinct endpoints and halved while it overflows (the
+// cursors advance only once a window has been counted, so always two passes).
 template <int T, int U>
-__global__ __launch_bounds__(T) void k_count_phash(Ranked G, Acc A, const uint32_t *list, uint32_t count) {
+__global__ __launch_bounds__(T) void k_count_phash(Ranked G, Acc A, const uint32_t *list, const uint64_t *wsrc,
+                                                   uint32_t *cur, uint32_t *nxt, uint32_t *cval, uint32_t *nval,
+                                                   uint32_t count) {
     __shared__ uint32_t words[PH_SLOTS];
     __shared__ RunShared<T> sh;
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
         const uint32_t r = list[i];
-        const PackedHashAgg<T, PH_SLOTS> agg{words, G.lo(r), bit_width(G.upoff[r + 1] - G.upoff[r]), A.err};
-        count_item<T, U>(G, A, r, agg, full_range(G, r), sh, A.passes());
+        const uint32_t cbits = bit_width(G.upoff[r + 1] - G.upoff[r]);
+        const uint32_t lo_min = G.lo(r);
+        uint32_t hi = G.cend[r];
+        const uint64_t w = wsrc[i] ? wsrc[i] : 1;
+        const uint64_t guess = (uint64_t)(hi - lo_min) * PH_TARGET / w;
+        uint32_t width = guess < 1 ? 1u : guess > hi - lo_min ? hi - lo_min : (uint32_t)guess;
+        bool first = true;
+        while (hi > lo_min) {
+            const uint32_t lo = hi - lo_min > width ? hi - width : lo_min;
+            const PackedHashAgg<T, PH_SLOTS, PH_FULL> agg{words, &sh.keys, lo, cbits, A.err};
+            if (!count_item<T, U>(G, A, r, agg, CursorRange{cur, nxt, cval, nval, lo, first, true}, sh, 2)) {
+                width = (hi - lo) / 2 ? (hi - lo) / 2 : 1u;
+                continue;
+            }
+            hi = lo;
+            first = false;
+        }
     }
 }
 
@@ -1909,7 +1947,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
                 if (ws.failed) return PB_ERR_NO_MEMORY;
                 PB_TRY((scan_exclusive<uint32_t, uint32_t>(hnw, hoff, nh, hoff + nh, ws)));
                 hipLaunchKernelGGL(k_heavy_expand, dim3(grid_for(nh)), dim3(256), 0, s, hsrc, hnw, hoff, nh, items);
-            } else if (!cur && (l == L_DENSE_HEAVY || l == L_SORT_HEAVY)) {
+            } else if (!cur && (l == L_DENSE_HEAVY || l == L_SORT_HEAVY || l == L_HASH_PACKED)) {
                 cur = ws.alloc<uint32_t>(m);
                 nxt = ws.alloc<uint32_t>(m);
                 cval = ws.alloc<uint32_t>(m);
@@ -2008,7 +2046,8 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
                         launch_items(k_count_dense_src<256, 4, SMALL_WIN>, c, 256, s, G, A, list_of(l));
                         break;
                     case L_HASH_PACKED:
-                        launch_items(k_count_phash<1024, 4>, c, 1024, s, G, A, list_of(l));
+                        launch_items(k_count_phash<1024, 4>, c, 1024, s, G, A, sorted_src[sorted_slot(l)],
+                                     sorted_w[sorted_slot(l)], cur, nxt, cval, nval);
                         break;
                     case L_DENSE_GLOBAL: {
                         const dim3 grid(NXCD * GH_WG_PER_XCD);

@@ -216,20 +216,22 @@ def test_workspace_cap_too_small():
     G.close()
 
 
-def test_packed_hash_source():
-    """One source with a few thousand wedges over a wide candidate range: AUTO
-    counts it in one pass of the packed LDS hash (more than the 4096 distinct
-    endpoints of the medium hash, far fewer wedges than its dense windows would
-    sweep); the forced aggregators must agree."""
-    n_u, n_v = 9000, 8000
-    u = [0] * n_v + [1 + (v % 3000) for v in range(n_v)]
-    v = list(range(n_v)) * 2
+@pytest.mark.parametrize("n_u,n_v,per_v,pool", [(100_001, 8000, 1, 3000), (1_300_001, 2000, 30, 30_000)])
+def test_packed_hash_source(n_u, n_v, per_v, pool):
+    """One source (U0, adjacent to every V vertex) with few wedges over a wide
+    candidate range: AUTO counts it in packed-LDS-hash windows sized to its
+    wedges.  Each V vertex also has per_v neighbours from a pool of U
+    vertices.  In the second graph all 30000 distinct endpoints fall into one
+    window, which overflows the table and is narrowed.  The forced
+    aggregators must agree."""
+    u = [0] * n_v + [1 + ((v * per_v + j) % pool) for v in range(n_v) for j in range(per_v)]
+    v = list(range(n_v)) + [v for v in range(n_v) for _ in range(per_v)]
     g = gg.from_edges(n_u, n_v, u, v)
     want = oracle.count(g)
     rank = oracle.rank(g, "degree")
     stats = pb.pb_stats()
     assert_same(gpu_counts(g, rank, "auto", stats), want, "auto")
-    # U0's 8000 wedges (one per V neighbour) take a hash list in AUTO mode
-    assert stats.wedges_hash >= n_v
+    # U0's wedges (per_v per V neighbour) are counted by a hash list in AUTO mode
+    assert stats.wedges_hash >= n_v * per_v
     for agg in ("dense", "hash", "sort"):
         assert_same(gpu_counts(g, rank, agg), want, agg)
