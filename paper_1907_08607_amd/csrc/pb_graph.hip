@@ -391,11 +391,11 @@ pb_status pb_graph_create(const pb_csr *csr, hipStream_t s, pb_graph **out) {
     {
         Workspace ws(s, 0);
         uint32_t *flags = ws.alloc<uint32_t>(2);  // [0] flags, [1] max degree
-        bool ok = flags && hipMalloc(&g->eu, (m ? m : 1) * sizeof(uint32_t)) == hipSuccess &&
-                  hipMalloc(&g->v_off, (g->n_v + 1) * sizeof(uint32_t)) == hipSuccess &&
-                  hipMalloc(&g->v_adj, (m ? m : 1) * sizeof(uint32_t)) == hipSuccess &&
-                  hipMalloc(&g->v_eid, (m ? m : 1) * sizeof(uint32_t)) == hipSuccess &&
-                  hipMalloc(&g->deg, (n ? n : 1) * sizeof(uint32_t)) == hipSuccess &&
+        bool ok = flags && hipMallocAsync((void **)&g->eu, (m ? m : 1) * sizeof(uint32_t), s) == hipSuccess &&
+                  hipMallocAsync((void **)&g->v_off, (g->n_v + 1) * sizeof(uint32_t), s) == hipSuccess &&
+                  hipMallocAsync((void **)&g->v_adj, (m ? m : 1) * sizeof(uint32_t), s) == hipSuccess &&
+                  hipMallocAsync((void **)&g->v_eid, (m ? m : 1) * sizeof(uint32_t), s) == hipSuccess &&
+                  hipMallocAsync((void **)&g->deg, (n ? n : 1) * sizeof(uint32_t), s) == hipSuccess &&
                   hipHostMalloc((void **)&hflags, 2 * sizeof(uint32_t), hipHostMallocDefault) == hipSuccess;
         if (!ok) st = PB_ERR_NO_MEMORY;
         do {
@@ -452,11 +452,14 @@ pb_status pb_graph_create(const pb_csr *csr, hipStream_t s, pb_graph **out) {
 void pb_graph_destroy(pb_graph *g) {
     if (!g) return;
     (void)hipDeviceSynchronize();
-    if (g->eu) (void)hipFree(g->eu);
-    if (g->v_off) (void)hipFree(g->v_off);
-    if (g->v_adj) (void)hipFree(g->v_adj);
-    if (g->v_eid) (void)hipFree(g->v_eid);
-    if (g->deg) (void)hipFree(g->deg);
+    // after the device-wide wait nothing uses the arrays: back to the pool of
+    // the device they came from
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != g->device) (void)hipSetDevice(g->device);
+    for (uint32_t *p : {g->eu, g->v_off, g->v_adj, g->v_eid, g->deg})
+        if (p) (void)hipFreeAsync(p, nullptr);
+    if (cur != g->device) (void)hipSetDevice(cur);
     delete g;
 }
 

@@ -24,6 +24,13 @@ constexpr int WAVE = 64;
         if (pb_s_ != PB_OK) return pb_s_;                 \
     } while (0)
 
+// Keeps memory freed by hipFreeAsync in the current device's default
+// stream-ordered pool instead of returning it to the system at every
+// synchronisation (where freeing and re-mapping large scratch costs
+// milliseconds per call).  Once per device; the pool is trimmed by the
+// runtime when the process ends.
+void keep_pool_memory();
+
 // Stream-ordered scratch for one library call.  Every allocation is released
 // (stream-ordered) when the Workspace goes out of scope.  `cap` bounds the
 // total bytes (0 = unbounded).
@@ -35,7 +42,7 @@ struct Workspace {
     bool failed = false;
     std::vector<std::pair<void *, uint64_t>> ptrs;
 
-    Workspace(hipStream_t s, uint64_t cap_bytes) : stream(s), cap(cap_bytes) {}
+    Workspace(hipStream_t s, uint64_t cap_bytes) : stream(s), cap(cap_bytes) { keep_pool_memory(); }
     Workspace(const Workspace &) = delete;
     Workspace &operator=(const Workspace &) = delete;
     ~Workspace() { release_all(); }

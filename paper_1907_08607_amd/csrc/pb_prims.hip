@@ -2,6 +2,8 @@
 // (The paper's prefix sum and integer sort, Section 2 "Parallel primitives".)
 #include "pb_internal.h"
 
+#include <atomic>
+
 namespace pb {
 
 // ---------------------------------------------------------------- scan
@@ -182,6 +184,21 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *kin, 
         }
         __syncthreads();
     }
+}
+
+void keep_pool_memory() {
+    constexpr int MAX_DEV = 64;
+    static std::atomic<bool> done[MAX_DEV];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEV) return;
+    if (done[dev].load(std::memory_order_acquire)) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    (void)hipGetLastError();
+    done[dev].store(true, std::memory_order_release);
 }
 
 pb_status radix_sort_pairs(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, uint64_t n,
