@@ -391,11 +391,11 @@ pb_status pb_graph_create(const pb_csr *csr, hipStream_t s, pb_graph **out) {
     {
         Workspace ws(s, 0);
         uint32_t *flags = ws.alloc<uint32_t>(2);  // [0] flags, [1] max degree
-        bool ok = flags && hipMallocAsync((void **)&g->eu, (m ? m : 1) * sizeof(uint32_t), s) == hipSuccess &&
-                  hipMallocAsync((void **)&g->v_off, (g->n_v + 1) * sizeof(uint32_t), s) == hipSuccess &&
-                  hipMallocAsync((void **)&g->v_adj, (m ? m : 1) * sizeof(uint32_t), s) == hipSuccess &&
-                  hipMallocAsync((void **)&g->v_eid, (m ? m : 1) * sizeof(uint32_t), s) == hipSuccess &&
-                  hipMallocAsync((void **)&g->deg, (n ? n : 1) * sizeof(uint32_t), s) == hipSuccess &&
+        bool ok = flags && (g->eu = (uint32_t *)scratch_get(s, (m ? m : 1) * sizeof(uint32_t))) != nullptr &&
+                  (g->v_off = (uint32_t *)scratch_get(s, (g->n_v + 1) * sizeof(uint32_t))) != nullptr &&
+                  (g->v_adj = (uint32_t *)scratch_get(s, (m ? m : 1) * sizeof(uint32_t))) != nullptr &&
+                  (g->v_eid = (uint32_t *)scratch_get(s, (m ? m : 1) * sizeof(uint32_t))) != nullptr &&
+                  (g->deg = (uint32_t *)scratch_get(s, (n ? n : 1) * sizeof(uint32_t))) != nullptr &&
                   hipHostMalloc((void **)&hflags, 2 * sizeof(uint32_t), hipHostMallocDefault) == hipSuccess;
         if (!ok) st = PB_ERR_NO_MEMORY;
         do {
@@ -452,13 +452,12 @@ pb_status pb_graph_create(const pb_csr *csr, hipStream_t s, pb_graph **out) {
 void pb_graph_destroy(pb_graph *g) {
     if (!g) return;
     (void)hipDeviceSynchronize();
-    // after the device-wide wait nothing uses the arrays: back to the pool of
-    // the device they came from
+    // after the device-wide wait nothing uses the arrays: back to the
+    // library's scratch cache of the device they came from
     int cur = 0;
     (void)hipGetDevice(&cur);
     if (cur != g->device) (void)hipSetDevice(g->device);
-    for (uint32_t *p : {g->eu, g->v_off, g->v_adj, g->v_eid, g->deg})
-        if (p) (void)hipFreeAsync(p, nullptr);
+    for (uint32_t *p : {g->eu, g->v_off, g->v_adj, g->v_eid, g->deg}) scratch_put(nullptr, p);
     if (cur != g->device) (void)hipSetDevice(cur);
     delete g;
 }

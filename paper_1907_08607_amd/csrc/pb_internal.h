@@ -24,16 +24,18 @@ constexpr int WAVE = 64;
         if (pb_s_ != PB_OK) return pb_s_;                 \
     } while (0)
 
-// Keeps memory freed by hipFreeAsync in the current device's default
-// stream-ordered pool instead of returning it to the system at every
-// synchronisation (where freeing and re-mapping large scratch costs
-// milliseconds per call).  Once per device; the pool is trimmed by the
-// runtime when the process ends.
-void keep_pool_memory();
+// Device scratch cache.  Blocks handed back by a Workspace stay with the
+// library for the life of the process and are reused by later calls on any
+// stream: each cached block carries an event recorded on the stream that
+// released it, and a stream that takes the block waits for that event first
+// (stream-ordered, no host wait).  A new block is allocated only when no
+// cached block of the current device fits.  Thread safe.
+void *scratch_get(hipStream_t s, uint64_t bytes);
+void scratch_put(hipStream_t s, void *p);
 
-// Stream-ordered scratch for one library call.  Every allocation is released
-// (stream-ordered) when the Workspace goes out of scope.  `cap` bounds the
-// total bytes (0 = unbounded).
+// Stream-ordered scratch for one library call.  Every allocation goes back to
+// the cache when the Workspace goes out of scope.  `cap` bounds the total
+// bytes (0 = unbounded).
 struct Workspace {
     hipStream_t stream;
     uint64_t cap;
@@ -42,7 +44,7 @@ struct Workspace {
     bool failed = false;
     std::vector<std::pair<void *, uint64_t>> ptrs;
 
-    Workspace(hipStream_t s, uint64_t cap_bytes) : stream(s), cap(cap_bytes) { keep_pool_memory(); }
+    Workspace(hipStream_t s, uint64_t cap_bytes) : stream(s), cap(cap_bytes) {}
     Workspace(const Workspace &) = delete;
     Workspace &operator=(const Workspace &) = delete;
     ~Workspace() { release_all(); }
@@ -51,9 +53,8 @@ struct Workspace {
         if (bytes == 0) bytes = 256;
         bytes = (bytes + 255) & ~uint64_t(255);
         if (cap && used + bytes > cap) { failed = true; return nullptr; }
-        void *p = nullptr;
-        if (hipMallocAsync(&p, bytes, stream) != hipSuccess || !p) {
-            (void)hipGetLastError();
+        void *p = scratch_get(stream, bytes);
+        if (!p) {
             failed = true;
             return nullptr;
         }
@@ -65,18 +66,18 @@ struct Workspace {
     template <class T>
     T *alloc(uint64_t count) { return static_cast<T *>(alloc_bytes(count * sizeof(T))); }
 
-    // Frees one allocation early (stream-ordered).
+    // Hands one allocation back early (stream-ordered).
     void release(void *p) {
         for (size_t i = 0; i < ptrs.size(); ++i)
             if (ptrs[i].first == p) {
-                (void)hipFreeAsync(p, stream);
+                scratch_put(stream, p);
                 used -= ptrs[i].second;
                 ptrs.erase(ptrs.begin() + i);
                 return;
             }
     }
     void release_all() {
-        for (auto &p : ptrs) (void)hipFreeAsync(p.first, stream);
+        for (auto &p : ptrs) scratch_put(stream, p.first);
         ptrs.clear();
         used = 0;
     }

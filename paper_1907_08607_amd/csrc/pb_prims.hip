@@ -2,7 +2,9 @@
 // (The paper's prefix sum and integer sort, Section 2 "Parallel primitives".)
 #include "pb_internal.h"
 
-#include <atomic>
+#include <map>
+#include <mutex>
+#include <unordered_map>
 
 namespace pb {
 
@@ -186,19 +188,109 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *kin, 
     }
 }
 
-void keep_pool_memory() {
-    constexpr int MAX_DEV = 64;
-    static std::atomic<bool> done[MAX_DEV];
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEV) return;
-    if (done[dev].load(std::memory_order_acquire)) return;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t keep = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+// ---------------------------------------------------------------- scratch cache
+
+namespace {
+
+struct Block {
+    uint64_t bytes;
+    int dev;
+    hipEvent_t ev;  // recorded on the stream that handed the block back
+};
+
+struct Cache {
+    std::mutex mu;
+    std::multimap<uint64_t, std::pair<void *, Block>> idle;  // by size
+    std::unordered_map<void *, Block> busy;
+};
+
+Cache &cache() {
+    static Cache *c = new Cache;  // lives to the end of the process
+    return *c;
+}
+
+// Size classes: powers of two up to 1 MiB, then multiples of 2 MiB.
+uint64_t size_class(uint64_t b) {
+    if (b <= (uint64_t(1) << 20)) {
+        uint64_t r = 256;
+        while (r < b) r <<= 1;
+        return r;
     }
-    (void)hipGetLastError();
-    done[dev].store(true, std::memory_order_release);
+    const uint64_t g = uint64_t(2) << 20;
+    return (b + g - 1) / g * g;
+}
+
+}  // namespace
+
+void *scratch_get(hipStream_t s, uint64_t bytes) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    const uint64_t want = size_class(bytes);
+    Cache &c = cache();
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        // the smallest idle block of this device that is not wastefully large
+        for (auto it = c.idle.lower_bound(want); it != c.idle.end() && it->first <= 2 * want; ++it) {
+            if (it->second.second.dev != dev) continue;
+            void *p = it->second.first;
+            const Block b = it->second.second;
+            c.idle.erase(it);
+            if (hipStreamWaitEvent(s, b.ev, 0) != hipSuccess) {
+                (void)hipGetLastError();
+                (void)hipEventSynchronize(b.ev);
+            }
+            c.busy[p] = b;
+            return p;
+        }
+    }
+    void *p = nullptr;
+    if (hipMallocAsync(&p, want, s) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        // out of memory: give this device's idle blocks back, then retry once
+        std::vector<std::pair<void *, Block>> drop;
+        {
+            std::lock_guard<std::mutex> lk(c.mu);
+            for (auto it = c.idle.begin(); it != c.idle.end();) {
+                if (it->second.second.dev == dev) {
+                    drop.push_back(it->second);
+                    it = c.idle.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+        }
+        for (auto &d : drop) {
+            (void)hipStreamWaitEvent(s, d.second.ev, 0);
+            (void)hipFreeAsync(d.first, s);
+            (void)hipEventDestroy(d.second.ev);
+        }
+        p = nullptr;
+        if (hipMallocAsync(&p, want, s) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFreeAsync(p, s);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(c.mu);
+    c.busy[p] = Block{want, dev, ev};
+    return p;
+}
+
+void scratch_put(hipStream_t s, void *p) {
+    if (!p) return;
+    Cache &c = cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    auto it = c.busy.find(p);
+    if (it == c.busy.end()) return;
+    const Block b = it->second;
+    c.busy.erase(it);
+    if (hipEventRecord(b.ev, s) != hipSuccess) (void)hipGetLastError();
+    c.idle.emplace(b.bytes, std::make_pair(p, b));
 }
 
 pb_status radix_sort_pairs(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, uint64_t n,
