@@ -127,6 +127,20 @@ __device__ inline T wave_inclusive_sum(T v) {
     return v;
 }
 
+// 32-bit lanes: the same scan in registers with DPP row shifts and row
+// broadcasts (wave64 on gfx9), no LDS round trips.  Every lane of the wave
+// must be active.
+template <>
+__device__ inline uint32_t wave_inclusive_sum<uint32_t>(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15 -> rows 1, 3
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31 -> rows 2, 3
+    return v;
+}
+
 template <class T>
 __device__ inline T wave_sum(T v) {
 #pragma unroll
