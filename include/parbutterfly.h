@@ -239,6 +239,44 @@ pb_status pb_count_vertex(pb_graph *g, const uint32_t *rank, const pb_opts *opts
 pb_status pb_count_edge(pb_graph *g, const uint32_t *rank, const pb_opts *opts, int64_t *out,
                         hipStream_t stream);
 
+/* Approximate total counts by graph sparsification (Section 4.6
+ * "Approximate counting"): a kept graph is drawn, counted exactly, and the
+ * count scaled to an unbiased estimate.  Only the total can be estimated.
+ *   EDGE   each edge is kept independently with probability p; scale 1 / p^4
+ *   COLOR  every vertex takes one of c = ceil(1/p) colours and an edge is kept
+ *          when its two endpoints share a colour; scale c^3 (a butterfly
+ *          survives when its other three vertices take the first one's colour)
+ * Random numbers come from SplitMix64 (Steele, Lea and Flood, OOPSLA 2014)
+ * started at state `seed`: x(i) = its output number i + 1 =
+ * mix(seed + (i + 1) * 0x9E3779B97F4A7C15) with its 64-bit finaliser mix.
+ * EDGE keeps edge e (its position in u_adj) when x(e) < floor(p * 2^64), or
+ * every edge when p = 1; COLOR gives unified vertex id i the colour
+ * floor(x(i) * c / 2^64).  The same (graph, kind, p, seed) always keeps the
+ * same edges. */
+typedef enum {
+    PB_SPARSIFY_EDGE = 0,
+    PB_SPARSIFY_COLOR = 1
+} pb_sparsify_kind;
+
+/* Writes the kept graph as a U-side CSR over the same vertices, kept edges
+ * in input order: out_u_off (device int64[n_u + 1]) and out_u_adj (device
+ * uint32, room for m entries; may be NULL when m = 0); *kept (host) gets the
+ * number of kept edges.  p must lie in (0, 1], and for COLOR also p >= 2^-32.
+ * Synchronises `stream` once, to read the kept count.
+ * Errors: INVALID_ARG, NO_MEMORY, HIP. */
+pb_status pb_sparsify(pb_graph *g, pb_sparsify_kind kind, double p, uint64_t seed, int64_t *out_u_off,
+                      uint32_t *out_u_adj, uint64_t *kept, hipStream_t stream);
+
+/* Sparsifies as pb_sparsify, then counts the kept graph exactly under the
+ * ordering `rank_kind` with `opts` (NULL = defaults) and scales.  Host
+ * outputs: *count_out the kept graph's butterflies, *estimate_out the scaled
+ * estimate of the total, *kept_out (optional) the kept edges.  All scratch is
+ * the library's; the call synchronises `stream` before it returns.
+ * Errors: those of pb_sparsify, pb_graph_create, pb_rank and pb_count_global. */
+pb_status pb_count_approx(pb_graph *g, pb_sparsify_kind kind, double p, uint64_t seed, pb_rank_kind rank_kind,
+                          const pb_opts *opts, int64_t *count_out, double *estimate_out, uint64_t *kept_out,
+                          hipStream_t stream);
+
 /* Batched counting: `count` independent graphs in one pass of the pipeline.
  * The batch is counted as the disjoint union of the graphs (no wedge spans two
  * graphs), so relabelling, planning and each counting kernel run as single

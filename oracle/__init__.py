@@ -39,6 +39,9 @@ def _load():
         lib.orc_edge_one.argtypes = [_I, _I, _P, _P, _P, _P, _I, _P]
         lib.orc_wedges.argtypes = [_I, _I, _P, _P, _P, _P, _P]
         lib.orc_rank.argtypes = [_I, _I, _P, _P, ctypes.c_int, _P]
+        lib.orc_splitmix.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        lib.orc_splitmix.restype = ctypes.c_uint64
+        lib.orc_sparsify.argtypes = [_I, _I, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, _P, _P, _P]
         _lib = lib
     return _lib
 
@@ -139,3 +142,53 @@ def rank(g, kind: str) -> np.ndarray:
     _check(_load().orc_rank(g.n_u, g.n_v, _ptr(off), _ptr(adj), RANK_KINDS[kind], _ptr(out)),
            "orc_rank")
     return out
+
+
+SPARSIFY_KINDS = {"edge": 0, "color": 1}
+
+
+class Kept:
+    """The graph a sparsification keeps (U-side CSR, same fields as the inputs)."""
+
+    def __init__(self, n_u: int, n_v: int, u_off: np.ndarray, u_adj: np.ndarray):
+        self.n_u, self.n_v = n_u, n_v
+        self.u_off, self.u_adj = u_off, u_adj
+        self.m = int(u_off[-1]) if len(u_off) else 0
+
+
+def splitmix(seed: int, i: int) -> int:
+    """SplitMix64 output number i + 1 from state ``seed``."""
+    return int(_load().orc_splitmix(seed & (2**64 - 1), i & (2**64 - 1)))
+
+
+def sparsify(g, kind: str, p: float, seed: int) -> Kept:
+    """Edge (keep each edge with probability p) or colorful (ceil(1/p) colours,
+    keep same-coloured edges) sparsification, Section 4.6."""
+    off, adj = _csr(g)
+    out_off = np.zeros(g.n_u + 1, dtype=np.int64)
+    out_adj = np.zeros(max(g.m, 1), dtype=np.uint32)
+    kept = np.zeros(1, dtype=np.int64)
+    _check(_load().orc_sparsify(g.n_u, g.n_v, _ptr(off), _ptr(adj), SPARSIFY_KINDS[kind], float(p),
+                                seed & (2**64 - 1), _ptr(out_off), _ptr(out_adj), _ptr(kept)), "orc_sparsify")
+    return Kept(g.n_u, g.n_v, out_off, out_adj[:int(kept[0])].copy())
+
+
+def scale(kind: str, p: float) -> float:
+    """Factor that makes the kept graph's count an unbiased estimate: 1/p^4 for
+    edge sparsification; c^3 with c = ceil(1/p) colours for colorful (a
+    butterfly survives when its other three vertices take the first one's
+    colour, probability (1/c)^3)."""
+    import math
+    if p >= 1.0:
+        return 1.0
+    if kind == "edge":
+        return 1.0 / (p * p * p * p)
+    c = float(math.ceil(1.0 / p))
+    return c * c * c
+
+
+def count_approx(g, kind: str, p: float, seed: int):
+    """(exact count of the kept graph, scaled estimate, kept edges)."""
+    k = sparsify(g, kind, p, seed)
+    c = count(k, want_vertex=False, want_edge=False)[0]
+    return c, c * scale(kind, p), k.m

@@ -27,9 +27,12 @@
  *   orc_count  the oracle proper: dense 2-hop counts per endpoint, O(sum deg^2)
  *   orc_wedges number of wedges the ranked framework retrieves for a ranking
  *   orc_rank   the reference vertex orderings (Section 3.1.1)
+ *   orc_sparsify  the kept graph of edge or colorful sparsification (Section
+ *              4.6 "Approximate counting")
  * Every function returns 0 on success and a negative value on bad input or
  * allocation failure.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -510,4 +513,61 @@ done:
     free(deg);
     free_vside(&vs);
     return rc;
+}
+
+/*
+ * Sparsification (Section 4.6 "Approximate counting").  Edge sparsification
+ * keeps each edge independently with probability p; colorful sparsification
+ * gives every vertex one of c = ceil(1/p) colours and keeps the edges whose
+ * two endpoints have the same colour.  The kept graph is then counted exactly.
+ *
+ * Random numbers: SplitMix64 (Steele, Lea and Flood, "Fast splittable
+ * pseudorandom number generators", OOPSLA 2014) from state `seed`: its output
+ * number i + 1 is x(i) = mix(seed + (i + 1) * 0x9E3779B97F4A7C15), mix being
+ * its 64-bit finaliser.  Edge e (its position in u_adj) is kept when x(e) <
+ * floor(p * 2^64) (every edge when p >= 1).  Vertex i (unified id) has colour
+ * floor(x(i) * c / 2^64).
+ */
+uint64_t orc_splitmix(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* high 64 bits of the 128-bit product x * c, from 32-bit halves */
+static uint64_t mul_hi(uint64_t x, uint64_t c) {
+    const uint64_t x0 = x & 0xFFFFFFFFull, x1 = x >> 32, c0 = c & 0xFFFFFFFFull, c1 = c >> 32;
+    const uint64_t p00 = x0 * c0, p01 = x0 * c1, p10 = x1 * c0, p11 = x1 * c1;
+    const uint64_t mid = (p00 >> 32) + (p01 & 0xFFFFFFFFull) + (p10 & 0xFFFFFFFFull);
+    return p11 + (p01 >> 32) + (p10 >> 32) + (mid >> 32);
+}
+
+/* kind 0: edge sparsification, 1: colorful.  Writes the kept edges in input
+ * order as a U-side CSR (out_off[n_u + 1], out_adj[m] capacity) and their
+ * number in *kept. */
+int orc_sparsify(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_adj, int kind, double p,
+                 uint64_t seed, int64_t *out_off, uint32_t *out_adj, int64_t *kept) {
+    if (check_csr(n_u, n_v, u_off, u_adj) != 0 || !(p > 0.0) || kind < 0 || kind > 1) return -1;
+    const int all = p >= 1.0;
+    const uint64_t thr = all ? 0 : (uint64_t)ldexp(p, 64);
+    const uint64_t c = all ? 1 : (uint64_t)ceil(1.0 / p);
+    int64_t k = 0;
+    out_off[0] = 0;
+    for (int64_t u = 0; u < n_u; ++u) {
+        const uint64_t cu = mul_hi(orc_splitmix(seed, (uint64_t)u), c);
+        for (int64_t e = u_off[u]; e < u_off[u + 1]; ++e) {
+            int keep;
+            if (kind == 0) {
+                keep = all || orc_splitmix(seed, (uint64_t)e) < thr;
+            } else {
+                const uint64_t cv = mul_hi(orc_splitmix(seed, (uint64_t)(n_u + u_adj[e])), c);
+                keep = cu == cv;
+            }
+            if (keep) out_adj[k++] = u_adj[e];
+        }
+        out_off[u + 1] = k;
+    }
+    *kept = k;
+    return 0;
 }

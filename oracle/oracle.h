@@ -31,4 +31,7 @@ int orc_wedges(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u
                const uint32_t *rank, int64_t *total, int64_t *per_source);
 int orc_rank(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_adj, int kind,
              uint32_t *rank);
+uint64_t orc_splitmix(uint64_t seed, uint64_t i);
+int orc_sparsify(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_adj, int kind, double p,
+                 uint64_t seed, int64_t *out_off, uint32_t *out_adj, int64_t *kept);
 #endif

@@ -108,6 +108,13 @@ def load_library():
     lib.pb_autotune.argtypes = [PP, PP, ctypes.c_uint32, ctypes.POINTER(pb_opts), ctypes.c_uint32,
                                 ctypes.POINTER(pb_tuning), P]
     lib.pb_autotune.restype = ctypes.c_int
+    lib.pb_sparsify.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, P, P,
+                                ctypes.POINTER(ctypes.c_uint64), P]
+    lib.pb_sparsify.restype = ctypes.c_int
+    lib.pb_count_approx.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.c_int,
+                                    ctypes.POINTER(pb_opts), ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64), P]
+    lib.pb_count_approx.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -254,6 +261,35 @@ def pb_count_vertex(g, rank, agg="auto", hub="auto", workspace_cap=0, stats=None
 
 def pb_count_edge(g, rank, agg="auto", hub="auto", workspace_cap=0, stats=None, stream=None):
     return _single("pb_count_edge", g, rank, g.m, agg, hub, workspace_cap, stats, stream)
+
+
+SPARSIFY_KINDS = {"edge": 0, "color": 1}
+
+
+def pb_sparsify(g: Graph, kind="edge", p=0.5, seed=0, stream=None):
+    """The kept graph of edge or colorful sparsification: (u_off int64 CUDA
+    tensor [n_u + 1], u_adj int32 CUDA tensor [kept])."""
+    torch = _torch()
+    off = torch.empty(g.n_u + 1, dtype=torch.int64, device="cuda")
+    adj = torch.empty(max(g.m, 1), dtype=torch.int32, device="cuda")
+    kept = ctypes.c_uint64()
+    _check(load_library().pb_sparsify(g.handle, SPARSIFY_KINDS[kind], float(p), int(seed) & (2**64 - 1),
+                                      _dev_ptr(off, torch.int64, "out_u_off"),
+                                      ctypes.c_void_p(adj.data_ptr()) if g.m else None, ctypes.byref(kept),
+                                      _stream(stream)), "pb_sparsify")
+    return off, adj[:kept.value]
+
+
+def pb_count_approx(g: Graph, kind="edge", p=0.5, seed=0, rank="degree", agg="auto", hub="auto",
+                    stats=None, stream=None):
+    """(kept graph's exact count, scaled estimate of the total, kept edges)."""
+    opts = make_opts(agg, hub, 0, stats)
+    count, est, kept = ctypes.c_int64(), ctypes.c_double(), ctypes.c_uint64()
+    k = RANK_KINDS[rank] if isinstance(rank, str) else int(rank)
+    _check(load_library().pb_count_approx(g.handle, SPARSIFY_KINDS[kind], float(p), int(seed) & (2**64 - 1), k,
+                                          ctypes.byref(opts), ctypes.byref(count), ctypes.byref(est),
+                                          ctypes.byref(kept), _stream(stream)), "pb_count_approx")
+    return count.value, est.value, kept.value
 
 
 def _ptr_array(items):

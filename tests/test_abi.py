@@ -29,7 +29,7 @@ def test_header_declares_the_calls():
     names = declared_functions()
     for want in ("pb_graph_create", "pb_graph_destroy", "pb_rank", "pb_count", "pb_count_global",
                  "pb_count_vertex", "pb_count_edge", "pb_count_batched", "pb_autotune", "pb_status_str",
-                 "pb_opts_default"):
+                 "pb_opts_default", "pb_sparsify", "pb_count_approx"):
         assert want in names
 
 
@@ -99,3 +99,12 @@ def test_server_argument_checks(lib):
     assert lib.pb_server_poll(None, None, 0, ctypes.byref(n)) == -1
     assert lib.pb_server_drain(None) == -1
     lib.pb_server_destroy(None)
+
+
+def test_sparsify_argument_checks(lib):
+    k = ctypes.c_uint64()
+    c, e = ctypes.c_int64(), ctypes.c_double()
+    # no graph: rejected before any device work
+    assert lib.pb_sparsify(None, 0, ctypes.c_double(0.5), ctypes.c_uint64(1), None, None, ctypes.byref(k), None) == -1
+    assert lib.pb_count_approx(None, 1, ctypes.c_double(0.5), ctypes.c_uint64(1), 3, None, ctypes.byref(c),
+                               ctypes.byref(e), None, None) == -1
