@@ -31,16 +31,19 @@ INT8_MFMA_PEAK_TOPS = 5000.0  # dense int8 matrix-core peak of the MI355X
 PROFILES = os.path.join(ROOT, "profiles")
 
 
+# The files the counting kernels (and so every profiled kernel) are built from.
+KERNEL_SOURCES = ("pb_count.hip", "pb_hub.hip", "pb_internal.h")
+
+
 def kernel_source_hash():
-    """sha256 over the library's kernel sources (a measured HBM traffic figure
-    is only quoted for the sources it was measured on)."""
+    """sha256 over the counting kernels' sources (a measured HBM traffic
+    figure is only quoted for the sources it was measured on)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1907_08607_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
