@@ -74,7 +74,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="powerlaw_50m",
-                    choices=["powerlaw_50m", "hub_100m", "er_1k", "batch", "serve", "copy", "approx"])
+                    choices=["powerlaw_50m", "hub_100m", "er_1k", "batch", "serve", "copy", "approx", "choose"])
     ap.add_argument("--p", type=float, default=0.1, help="approx: sampling rate")
     ap.add_argument("--graphs", type=int, default=4096, help="batch: graphs in the batch")
     ap.add_argument("--pool-small", type=int, default=10_000, help="serve: resident small graphs")
@@ -240,6 +240,50 @@ def run_approx(args):
                                 "sample": f"one edge-sparsification estimate at p={args.p} "
                                           f"(sparsify + dense 2-hop count of the kept graph): {dt:.1f} s"}
     print(json.dumps(line), flush=True)
+
+
+def run_choose(args):
+    """The ranking chooser of Section 6.2 on both single-graph workloads: W
+    under side order and under each degree-like order, the metric f, the
+    choice, and the time of one choice (ranking both ways + two wedge counts).
+    `value` is input edges per second of the wedge count (pb_wedges) on the
+    powerlaw_50m graph under degree order."""
+    import argparse as _ap
+    import torch
+
+    import paper_1907_08607_amd as pb
+    out, wedge_rate = {}, None
+    for w in ("powerlaw_50m", "hub_100m"):
+        g, desc, _ = make_graph(_ap.Namespace(**{**vars(args), "workload": w, "rank": None}))
+        G = pb.Graph.from_csr(g)
+        res = {}
+        for other in ("approx_degree", "degree", "approx_codeg"):
+            pb.pb_rank_choose(G, other)
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                _, chosen, ws, wr = pb.pb_rank_choose(G, other)
+            ms = 1e3 * (time.perf_counter() - t0) / args.steps
+            res[other] = {"chosen": chosen, "w_side": ws, "w_other": wr, "f": (ws - wr) / ws if ws else 0.0,
+                          "ms_choose": ms}
+        rk = pb.pb_rank(G, "degree")
+        torch.cuda.synchronize()
+        pb.pb_wedges(G, rk)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            pb.pb_wedges(G, rk)
+        ms_w = 1e3 * (time.perf_counter() - t0) / args.steps
+        res["ms_wedges_degree"] = ms_w
+        if w == "powerlaw_50m":
+            wedge_rate = (g.m / (ms_w * 1e-3), ms_w)
+        out[w] = res
+        G.close()
+        print(f"[bench] {w}: {res}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "edges/s", "value": wedge_rate[0], "unit": "edges/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": 1, "ms_per_step": wedge_rate[1], "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+                      "config": {"workload": "rank_choose", "results": out,
+                                 "note": "value: pb_wedges on powerlaw_50m under degree order (host-timed, "
+                                         "includes its one synchronisation)"}}), flush=True)
 
 
 def upload(graphs, pb):
@@ -421,6 +465,8 @@ def main():
         return run_copy(args)
     if args.workload == "approx":
         return run_approx(args)
+    if args.workload == "choose":
+        return run_choose(args)
     t0 = time.time()
     g, desc, rank_kind = make_graph(args)
     print(f"[bench] graph {desc} built in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)

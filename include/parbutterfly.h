@@ -212,6 +212,21 @@ void pb_graph_destroy(pb_graph *g);
  * Errors: INVALID_ARG, NO_MEMORY, HIP. */
 pb_status pb_rank(pb_graph *g, pb_rank_kind kind, uint32_t *rank_out, hipStream_t stream);
 
+/* The number of wedges the framework retrieves under `rank` (Algorithm 2),
+ * W(rank) = sum over vertices y of h*d - h*(h+1)/2, where d = deg(y) and h =
+ * the neighbours of y ranked above y.  *w_out is host memory.  Synchronises
+ * `stream` once.  Errors: INVALID_ARG, NO_MEMORY, HIP. */
+pb_status pb_wedges(pb_graph *g, const uint32_t *rank, uint64_t *w_out, hipStream_t stream);
+
+/* The ranking chooser of Section 6.2: with w_s the wedges under side order
+ * (SIDE_AUTO) and w_r those under `other`, the metric f = (w_s - w_r) / w_s;
+ * when f < 0.1 side order is used, otherwise `other`.  Writes the chosen
+ * ordering into rank_out (device, n entries) and its kind into *chosen; the
+ * two wedge counts go to *w_side and *w_other (host, each may be NULL).
+ * Synchronises `stream`.  Errors: those of pb_rank and pb_wedges. */
+pb_status pb_rank_choose(pb_graph *g, pb_rank_kind other, uint32_t *rank_out, pb_rank_kind *chosen,
+                         uint64_t *w_side, uint64_t *w_other, hipStream_t stream);
+
 /* Counts butterflies (framework steps 2-4) under the caller's ranking.
  * `rank` (device, n entries) may be any permutation of [0, n) — the result
  * does not depend on it, only the work does.  Any subset of the outputs may

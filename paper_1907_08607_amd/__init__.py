@@ -108,6 +108,11 @@ def load_library():
     lib.pb_autotune.argtypes = [PP, PP, ctypes.c_uint32, ctypes.POINTER(pb_opts), ctypes.c_uint32,
                                 ctypes.POINTER(pb_tuning), P]
     lib.pb_autotune.restype = ctypes.c_int
+    lib.pb_wedges.argtypes = [P, P, ctypes.POINTER(ctypes.c_uint64), P]
+    lib.pb_wedges.restype = ctypes.c_int
+    lib.pb_rank_choose.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(ctypes.c_int),
+                                   ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64), P]
+    lib.pb_rank_choose.restype = ctypes.c_int
     lib.pb_sparsify.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, P, P,
                                 ctypes.POINTER(ctypes.c_uint64), P]
     lib.pb_sparsify.restype = ctypes.c_int
@@ -261,6 +266,28 @@ def pb_count_vertex(g, rank, agg="auto", hub="auto", workspace_cap=0, stats=None
 
 def pb_count_edge(g, rank, agg="auto", hub="auto", workspace_cap=0, stats=None, stream=None):
     return _single("pb_count_edge", g, rank, g.m, agg, hub, workspace_cap, stats, stream)
+
+
+def pb_wedges(g: Graph, rank, stream=None) -> int:
+    """W(rank): the wedges the framework retrieves under `rank`."""
+    torch = _torch()
+    w = ctypes.c_uint64()
+    _check(load_library().pb_wedges(g.handle, _dev_ptr(rank, torch.int32, "rank"), ctypes.byref(w),
+                                    _stream(stream)), "pb_wedges")
+    return w.value
+
+
+def pb_rank_choose(g: Graph, other="approx_degree", out=None, stream=None):
+    """Section 6.2's chooser: (rank tensor, chosen kind name, w_side, w_other)."""
+    torch = _torch()
+    k = RANK_KINDS[other] if isinstance(other, str) else int(other)
+    if out is None:
+        out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    chosen, ws, wr = ctypes.c_int(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(load_library().pb_rank_choose(g.handle, k, _dev_ptr(out, torch.int32, "rank"), ctypes.byref(chosen),
+                                         ctypes.byref(ws), ctypes.byref(wr), _stream(stream)), "pb_rank_choose")
+    name = {v: n for n, v in RANK_KINDS.items()}[chosen.value]
+    return out, name, ws.value, wr.value
 
 
 SPARSIFY_KINDS = {"edge": 0, "color": 1}

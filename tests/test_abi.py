@@ -29,7 +29,7 @@ def test_header_declares_the_calls():
     names = declared_functions()
     for want in ("pb_graph_create", "pb_graph_destroy", "pb_rank", "pb_count", "pb_count_global",
                  "pb_count_vertex", "pb_count_edge", "pb_count_batched", "pb_autotune", "pb_status_str",
-                 "pb_opts_default", "pb_sparsify", "pb_count_approx"):
+                 "pb_opts_default", "pb_sparsify", "pb_count_approx", "pb_wedges", "pb_rank_choose"):
         assert want in names
 
 
@@ -108,3 +108,10 @@ def test_sparsify_argument_checks(lib):
     assert lib.pb_sparsify(None, 0, ctypes.c_double(0.5), ctypes.c_uint64(1), None, None, ctypes.byref(k), None) == -1
     assert lib.pb_count_approx(None, 1, ctypes.c_double(0.5), ctypes.c_uint64(1), 3, None, ctypes.byref(c),
                                ctypes.byref(e), None, None) == -1
+
+
+def test_wedges_and_chooser_argument_checks(lib):
+    w = ctypes.c_uint64()
+    chosen = ctypes.c_int()
+    assert lib.pb_wedges(None, None, ctypes.byref(w), None) == -1
+    assert lib.pb_rank_choose(None, 4, None, ctypes.byref(chosen), None, None, None) == -1
