@@ -145,15 +145,34 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *keys, ui
     hist[(uint64_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
 }
 
+// Stable scatter of one tile of RS_TILE keys.  `hist` holds the exclusive
+// scan over (digit, tile) of the per-tile digit counts, with the total at
+// hist[256 * nb], so this tile's count of digit d is the difference of two
+// neighbouring entries.  The tile is first ordered by digit in LDS (each key at
+// its digit's tile-local start plus the number of equal digits before it in
+// the tile), then written out run by run, so consecutive lanes store to
+// consecutive addresses of one bucket.
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *kin, const uint32_t *vin,
                                                            uint64_t n, int shift,
                                                            const uint32_t *hist, uint32_t nb,
                                                            uint64_t *kout, uint32_t *vout) {
-    __shared__ uint32_t s_base[256];
+    __shared__ uint64_t s_key[RS_TILE];
+    __shared__ uint32_t s_val[RS_TILE];
+    __shared__ uint32_t s_gbase[256];  // global start of this tile's part of bucket d
+    __shared__ uint32_t s_lbase[256];  // tile-local start of digit d
+    __shared__ uint32_t s_run[256];    // next tile-local slot of digit d
     __shared__ uint32_t s_w[RS_WAVES][256];
+    __shared__ uint32_t s_tmp[RS_WAVES + 1];
     const int tid = threadIdx.x;
     const int w = tid / WAVE;
-    s_base[tid] = hist[(uint64_t)tid * nb + blockIdx.x];
+    const uint64_t hb = (uint64_t)tid * nb + blockIdx.x;
+    const uint32_t g0 = hist[hb];
+    const uint32_t cnt = hist[hb + 1] - g0;
+    uint32_t tile_n;
+    const uint32_t l0 = block_exclusive_sum<RS_THREADS>(cnt, s_tmp, &tile_n);
+    s_gbase[tid] = g0;
+    s_lbase[tid] = l0;
+    s_run[tid] = l0;
     const uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
     for (int it = 0; it < RS_ITEMS; ++it) {
         const uint64_t idx = base + (uint64_t)it * RS_THREADS + tid;
@@ -169,22 +188,29 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *kin, 
         if (valid && rank_in_wave == 0) s_w[w][d] = (uint32_t)__popcll(m);
         __syncthreads();
         {
-            uint32_t run = s_base[tid];
+            uint32_t run = s_run[tid];
 #pragma unroll
             for (int q = 0; q < RS_WAVES; ++q) {
                 const uint32_t c = s_w[q][tid];
                 s_w[q][tid] = run;
                 run += c;
             }
-            s_base[tid] = run;
+            s_run[tid] = run;
         }
         __syncthreads();
         if (valid) {
-            const uint32_t dst = s_w[w][d] + rank_in_wave;
-            kout[dst] = k;
-            vout[dst] = v;
+            const uint32_t lp = s_w[w][d] + rank_in_wave;
+            s_key[lp] = k;
+            s_val[lp] = v;
         }
-        __syncthreads();
+        __syncthreads();  // s_w is cleared again by the next round
+    }
+    for (uint32_t i = tid; i < tile_n; i += RS_THREADS) {
+        const uint64_t k = s_key[i];
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const uint32_t dst = s_gbase[d] + (i - s_lbase[d]);
+        kout[dst] = k;
+        vout[dst] = s_val[i];
     }
 }
 
@@ -305,14 +331,14 @@ pb_status radix_sort_pairs_bits(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32
     if (n <= 1 || hi_bit <= lo_bit) return PB_OK;
     if (n >= (uint64_t(1) << 32)) return PB_ERR_INVALID_ARG;
     const uint32_t nb = ceil_div(n, RS_TILE);
-    uint32_t *hist = ws.alloc<uint32_t>((uint64_t)nb * 256);
+    uint32_t *hist = ws.alloc<uint32_t>((uint64_t)nb * 256 + 1);
     if (!hist) return PB_ERR_NO_MEMORY;
     uint64_t *ks = k0, *kd = k1;
     uint32_t *vs = v0, *vd = v1;
     for (int shift = lo_bit; shift < hi_bit; shift += 8) {
         hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_THREADS), 0, ws.stream, ks, n, shift, hist, nb);
         PB_TRY_HIP(hipGetLastError());
-        PB_TRY((scan_exclusive<uint32_t, uint32_t>(hist, hist, (uint64_t)nb * 256, nullptr, ws)));
+        PB_TRY((scan_exclusive<uint32_t, uint32_t>(hist, hist, (uint64_t)nb * 256, hist + (uint64_t)nb * 256, ws)));
         hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RS_THREADS), 0, ws.stream, ks, vs, n, shift,
                            hist, nb, kd, vd);
         PB_TRY_HIP(hipGetLastError());
