@@ -111,10 +111,13 @@ template pb_status fill<int64_t>(int64_t *, int64_t, uint64_t, hipStream_t);
 
 // ---------------------------------------------------------------- radix sort
 
-constexpr int RS_THREADS = 256;
+constexpr int RS_THREADS = 256;  // histogram kernel: one thread per digit
 constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
 constexpr int RS_WAVES = RS_THREADS / WAVE;
+constexpr int RSS_THREADS = 512;  // scatter kernel
+constexpr int RSS_ITEMS = RS_TILE / RSS_THREADS;
+constexpr int RSS_WAVES = RSS_THREADS / WAVE;
 
 // Lanes of this wave whose (valid) digit equals this lane's digit.
 __device__ inline uint64_t match_digit(uint32_t d, bool valid) {
@@ -152,45 +155,53 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *keys, ui
 // its digit's tile-local start plus the number of equal digits before it in
 // the tile), then written out run by run, so consecutive lanes store to
 // consecutive addresses of one bucket.
-__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *kin, const uint32_t *vin,
-                                                           uint64_t n, int shift,
-                                                           const uint32_t *hist, uint32_t nb,
-                                                           uint64_t *kout, uint32_t *vout) {
+__global__ __launch_bounds__(RSS_THREADS) void k_rs_scatter(const uint64_t *kin, const uint32_t *vin,
+                                                            uint64_t n, int shift,
+                                                            const uint32_t *hist, uint32_t nb,
+                                                            uint64_t *kout, uint32_t *vout) {
     __shared__ uint64_t s_key[RS_TILE];
     __shared__ uint32_t s_val[RS_TILE];
     __shared__ uint32_t s_gbase[256];  // global start of this tile's part of bucket d
     __shared__ uint32_t s_lbase[256];  // tile-local start of digit d
     __shared__ uint32_t s_run[256];    // next tile-local slot of digit d
-    __shared__ uint32_t s_w[RS_WAVES][256];
-    __shared__ uint32_t s_tmp[RS_WAVES + 1];
+    __shared__ uint32_t s_w[RSS_WAVES][256];
+    __shared__ uint32_t s_tmp[RSS_WAVES + 1];
     const int tid = threadIdx.x;
     const int w = tid / WAVE;
-    const uint64_t hb = (uint64_t)tid * nb + blockIdx.x;
-    const uint32_t g0 = hist[hb];
-    const uint32_t cnt = hist[hb + 1] - g0;
+    const bool dig = tid < 256;  // the first 256 threads own one digit each
+    uint32_t g0 = 0, cnt = 0;
+    if (dig) {
+        const uint64_t hb = (uint64_t)tid * nb + blockIdx.x;
+        g0 = hist[hb];
+        cnt = hist[hb + 1] - g0;
+    }
     uint32_t tile_n;
-    const uint32_t l0 = block_exclusive_sum<RS_THREADS>(cnt, s_tmp, &tile_n);
-    s_gbase[tid] = g0;
-    s_lbase[tid] = l0;
-    s_run[tid] = l0;
+    const uint32_t l0 = block_exclusive_sum<RSS_THREADS>(cnt, s_tmp, &tile_n);
+    if (dig) {
+        s_gbase[tid] = g0;
+        s_lbase[tid] = l0;
+        s_run[tid] = l0;
+    }
     const uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
-    for (int it = 0; it < RS_ITEMS; ++it) {
-        const uint64_t idx = base + (uint64_t)it * RS_THREADS + tid;
+    for (int it = 0; it < RSS_ITEMS; ++it) {
+        const uint64_t idx = base + (uint64_t)it * RSS_THREADS + tid;
         const bool valid = idx < n;
         const uint64_t k = valid ? kin[idx] : 0;
         const uint32_t v = valid ? vin[idx] : 0;
         const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        if (dig) {
 #pragma unroll
-        for (int q = 0; q < RS_WAVES; ++q) s_w[q][tid] = 0;
+            for (int q = 0; q < RSS_WAVES; ++q) s_w[q][tid] = 0;
+        }
         __syncthreads();
         const uint64_t m = match_digit(d, valid);
         const uint32_t rank_in_wave = (uint32_t)__popcll(m & lanemask_lt());
         if (valid && rank_in_wave == 0) s_w[w][d] = (uint32_t)__popcll(m);
         __syncthreads();
-        {
+        if (dig) {
             uint32_t run = s_run[tid];
 #pragma unroll
-            for (int q = 0; q < RS_WAVES; ++q) {
+            for (int q = 0; q < RSS_WAVES; ++q) {
                 const uint32_t c = s_w[q][tid];
                 s_w[q][tid] = run;
                 run += c;
@@ -205,7 +216,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *kin, 
         }
         __syncthreads();  // s_w is cleared again by the next round
     }
-    for (uint32_t i = tid; i < tile_n; i += RS_THREADS) {
+    for (uint32_t i = tid; i < tile_n; i += RSS_THREADS) {
         const uint64_t k = s_key[i];
         const uint32_t d = (uint32_t)(k >> shift) & 255u;
         const uint32_t dst = s_gbase[d] + (i - s_lbase[d]);
@@ -339,7 +350,7 @@ pb_status radix_sort_pairs_bits(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32
         hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_THREADS), 0, ws.stream, ks, n, shift, hist, nb);
         PB_TRY_HIP(hipGetLastError());
         PB_TRY((scan_exclusive<uint32_t, uint32_t>(hist, hist, (uint64_t)nb * 256, hist + (uint64_t)nb * 256, ws)));
-        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RS_THREADS), 0, ws.stream, ks, vs, n, shift,
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RSS_THREADS), 0, ws.stream, ks, vs, n, shift,
                            hist, nb, kd, vd);
         PB_TRY_HIP(hipGetLastError());
         uint64_t *tk = ks; ks = kd; kd = tk;
