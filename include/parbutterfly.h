@@ -155,6 +155,9 @@ typedef struct {
     uint64_t hub_mfma_ops;    /* int8 operations issued on matrix cores */
     double ms_hub_gemm;       /* the matrix-core kernel (included in ms_prepare) */
     double ms_hub_pass;       /* the hub pairs' centre and edge credit pass */
+    /* Giant sources (global-histogram path; included in the dense figures). */
+    uint64_t wedges_global;   /* wedges they hold */
+    double ms_global;         /* their time: histogram clear, walks and endpoint step (PB_FLAG_TIMING) */
 } pb_stats;
 
 /* opts.flags bits */

@@ -2116,6 +2116,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         st.wedges_sort = plan.wedges[L_SORT_LIGHT] + plan.wedges[L_SORT_MEDIUM] + plan.wedges[L_SORT_HEAVY];
         st.workspace_bytes = ws.peak;
         st.wedges_heavy = plan.wedges[L_DENSE_HEAVY];
+        st.wedges_global = plan.wedges[L_DENSE_GLOBAL];
         if (hub_grid && plan.hub.on) {
             st.wedges_hub = plan.hub.wedges;
             st.hub_rows = hub_end - hub_base;
@@ -2124,6 +2125,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         }
         if (timing && ev.ok) {
             st.ms_heavy = t[1 + L_DENSE_HEAVY];
+            st.ms_global = t[1 + L_DENSE_GLOBAL];
             st.ms_hub_gemm = t_gemm;
             st.ms_hub_pass = t_hub_pass;
             st.ms_prepare = t[0];
