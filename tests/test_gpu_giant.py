@@ -62,6 +62,34 @@ def test_giant_sources(giant, hub, agg):
     assert st.wedges_hash + st.wedges_dense + st.wedges_sort + st.wedges_hub == st.wedges
 
 
+@pytest.fixture(scope="module")
+def giant_long():
+    # the same shape with 12 background neighbours per U vertex: the giant
+    # sources' runs average about 12 wedges instead of about 2
+    g = gg.giant_hubs(90_000, 6_000, 3, 70_000, 12, 9)
+    return g, oracle.count(g)
+
+
+@pytest.mark.parametrize("hub", ["off", "force"])
+@pytest.mark.parametrize("agg", ["auto", "dense"])
+def test_giant_sources_long_runs(giant_long, hub, agg):
+    g, want = giant_long
+    rank = oracle.rank(g, "degree")
+    got, st = run(g, rank, hub=hub, agg=agg)
+    assert_same(got, want, f"long runs {hub} {agg}")
+    assert st.wedges == oracle.wedges(g, rank)
+    assert st.wedges_global >= 8 * 3 * 65_536  # giant sources present, runs of 8 or more on average
+
+
+def test_giant_sources_reported(giant):
+    g, _ = giant
+    rank = oracle.rank(g, "degree")
+    _, st = run(g, rank)
+    _, per = oracle.wedges(g, rank, per_source=True)
+    # the four giant sources (70000 up-slots each) hold these wedges
+    assert st.wedges_global == int(np.sort(per)[-4:].sum())
+
+
 def test_giant_single_outputs(giant):
     g, want = giant
     G = pb.Graph.from_csr(g)
