@@ -295,6 +295,30 @@ pb_status pb_count_approx(pb_graph *g, pb_sparsify_kind kind, double p, uint64_t
                           const pb_opts *opts, int64_t *count_out, double *estimate_out, uint64_t *kept_out,
                           hipStream_t stream);
 
+/* Tip decomposition by vertex peeling (Section 3.2 "Peeling Framework",
+ * Algorithm 5 PEEL-V / UPDATE-V).  One side X is peeled: U, V, or with AUTO
+ * the side whose vertices, as wedge endpoints, give the fewest wedges (U when
+ * sum over V of C(deg, 2) <= sum over U of C(deg, 2)).  Starting from the
+ * per-vertex butterfly counts B, each round sets k = max(k, smallest B of the
+ * remaining X vertices), peels every remaining X vertex with B <= k (its tip
+ * number is k) and lowers each remaining B(u2) by C(c, 2) for every peeled
+ * u1, c = the centres u1 and u2 share.
+ *   tip_out    device int64[n_u + n_v]: tip numbers of X, -1 on the other side
+ *   side_out   host, optional: the side peeled (PB_PEEL_SIDE_U or _V)
+ *   rounds_out host, optional: peeling rounds
+ * `opts` (NULL = defaults) applies to the initial count.  Synchronises
+ * `stream` once per round.  Uses device scratch of up to 4 GiB of counters
+ * beside the counting call's own.
+ * Errors: INVALID_ARG, NO_MEMORY, HIP, and those of pb_count_vertex. */
+typedef enum {
+    PB_PEEL_SIDE_AUTO = 0,
+    PB_PEEL_SIDE_U = 1,
+    PB_PEEL_SIDE_V = 2
+} pb_peel_side;
+
+pb_status pb_tip_decompose(pb_graph *g, pb_peel_side side, const pb_opts *opts, int64_t *tip_out,
+                           pb_peel_side *side_out, uint64_t *rounds_out, hipStream_t stream);
+
 /* Batched counting: `count` independent graphs in one pass of the pipeline.
  * The batch is counted as the disjoint union of the graphs (no wedge spans two
  * graphs), so relabelling, planning and each counting kernel run as single

@@ -42,6 +42,7 @@ def _load():
         lib.orc_splitmix.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         lib.orc_splitmix.restype = ctypes.c_uint64
         lib.orc_sparsify.argtypes = [_I, _I, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, _P, _P, _P]
+        lib.orc_tip.argtypes = [_I, _I, _P, _P, ctypes.c_int, _P, _P]
         _lib = lib
     return _lib
 
@@ -192,3 +193,16 @@ def count_approx(g, kind: str, p: float, seed: int):
     k = sparsify(g, kind, p, seed)
     c = count(k, want_vertex=False, want_edge=False)[0]
     return c, c * scale(kind, p), k.m
+
+
+PEEL_SIDES = {"auto": 0, "u": 1, "v": 2}
+
+
+def tip(g, side: str = "auto"):
+    """Tip numbers by vertex peeling (Section 3.2, Algorithm 5): (tip int64[n]
+    with -1 on the side not peeled, rounds)."""
+    off, adj = _csr(g)
+    out = np.zeros(g.n_u + g.n_v, dtype=np.int64)
+    rounds = np.zeros(1, dtype=np.int64)
+    _check(_load().orc_tip(g.n_u, g.n_v, _ptr(off), _ptr(adj), PEEL_SIDES[side], _ptr(out), _ptr(rounds)), "orc_tip")
+    return out, int(rounds[0])

@@ -29,6 +29,7 @@
  *   orc_rank   the reference vertex orderings (Section 3.1.1)
  *   orc_sparsify  the kept graph of edge or colorful sparsification (Section
  *              4.6 "Approximate counting")
+ *   orc_tip    tip numbers by vertex peeling (Section 3.2, Algorithm 5)
  * Every function returns 0 on success and a negative value on bad input or
  * allocation failure.
  */
@@ -569,5 +570,90 @@ int orc_sparsify(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t 
         out_off[u + 1] = k;
     }
     *kept = k;
+    return 0;
+}
+
+/*
+ * Tip decomposition by vertex peeling (Section 3.2 "Peeling Framework" and
+ * Algorithm 5, PEEL-V / UPDATE-V).  One side X is peeled (side 1 = U, 2 = V,
+ * 0 = the side whose vertices, as wedge endpoints, give the fewest wedges:
+ * U when sum over V of C(deg, 2) <= sum over U of C(deg, 2)).  B starts as
+ * the per-vertex butterfly counts.  Each round sets k = max(k, smallest B
+ * among the remaining X vertices), peels every remaining X vertex with B <= k
+ * (its tip number is k), and for every peeled u1 and every remaining u2 of X
+ * lowers B(u2) by C(c, 2), c = the number of common neighbours of u1 and u2
+ * (the butterflies the peeled vertices take with them).  tip[x] is written for
+ * every unified id; the other side gets -1.  *rounds_out counts the rounds.
+ */
+int orc_tip(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_adj, int side, int64_t *tip,
+            int64_t *rounds_out) {
+    if (check_csr(n_u, n_v, u_off, u_adj) != 0 || side < 0 || side > 2) return -1;
+    const int64_t n = n_u + n_v, m = n_u ? u_off[n_u] : 0;
+    vside vs;
+    if (build_vside(n_u, n_v, u_off, u_adj, &vs) != 0) return -2;
+    int64_t *glob = malloc(sizeof(int64_t)), *vert = calloc((size_t)(n ? n : 1), sizeof(int64_t));
+    int64_t *edge = calloc((size_t)(m ? m : 1), sizeof(int64_t));
+    if (!glob || !vert || !edge || orc_count(n_u, n_v, u_off, u_adj, glob, vert, edge) != 0) {
+        free(glob); free(vert); free(edge); free_vside(&vs);
+        return -2;
+    }
+    if (side == 0) {
+        int64_t su = 0, sv = 0;  /* wedges with U endpoints (V centres), with V endpoints */
+        for (int64_t v = 0; v < n_v; ++v) su += choose2(vs.off[v + 1] - vs.off[v]);
+        for (int64_t u = 0; u < n_u; ++u) sv += choose2(u_off[u + 1] - u_off[u]);
+        side = su <= sv ? 1 : 2;
+    }
+    /* X = peeled side: its vertices' lists (off/adj into the other side) and
+     * the other side's lists back into X; ids local to each side */
+    const int64_t nx = side == 1 ? n_u : n_v, base = side == 1 ? 0 : n_u;
+    const int64_t *xoff = side == 1 ? u_off : vs.off, *yoff = side == 1 ? vs.off : u_off;
+    const uint32_t *xadj = side == 1 ? u_adj : vs.adj, *yadj = side == 1 ? vs.adj : u_adj;
+    int64_t *b = malloc(sizeof(int64_t) * (size_t)(nx ? nx : 1));
+    int64_t *c = calloc((size_t)(nx ? nx : 1), sizeof(int64_t));
+    char *gone = calloc((size_t)(nx ? nx : 1), 1);
+    int64_t *front = malloc(sizeof(int64_t) * (size_t)(nx ? nx : 1));
+    if (!b || !c || !gone || !front) {
+        free(b); free(c); free(gone); free(front); free(glob); free(vert); free(edge); free_vside(&vs);
+        return -2;
+    }
+    for (int64_t x = 0; x < n; ++x) tip[x] = -1;
+    for (int64_t x = 0; x < nx; ++x) b[x] = vert[base + x];
+    int64_t left = nx, k = 0, rounds = 0;
+    while (left > 0) {
+        int64_t mn = -1;
+        for (int64_t x = 0; x < nx; ++x)
+            if (!gone[x] && (mn < 0 || b[x] < mn)) mn = b[x];
+        if (mn > k) k = mn;
+        int64_t nf = 0;
+        for (int64_t x = 0; x < nx; ++x)
+            if (!gone[x] && b[x] <= k) front[nf++] = x;
+        for (int64_t i = 0; i < nf; ++i) {
+            gone[front[i]] = 1;
+            tip[base + front[i]] = k;
+        }
+        /* UPDATE-V: 2-hop counts from each peeled vertex to the remaining ones */
+        for (int64_t i = 0; i < nf; ++i) {
+            const int64_t u1 = front[i];
+            for (int64_t p = xoff[u1]; p < xoff[u1 + 1]; ++p) {
+                const uint32_t y = xadj[p];
+                for (int64_t q = yoff[y]; q < yoff[y + 1]; ++q)
+                    if (!gone[yadj[q]]) c[yadj[q]]++;
+            }
+            for (int64_t p = xoff[u1]; p < xoff[u1 + 1]; ++p) {
+                const uint32_t y = xadj[p];
+                for (int64_t q = yoff[y]; q < yoff[y + 1]; ++q) {
+                    const uint32_t u2 = yadj[q];
+                    if (c[u2]) {
+                        b[u2] -= choose2(c[u2]);
+                        c[u2] = 0;
+                    }
+                }
+            }
+        }
+        left -= nf;
+        ++rounds;
+    }
+    *rounds_out = rounds;
+    free(b); free(c); free(gone); free(front); free(glob); free(vert); free(edge); free_vside(&vs);
     return 0;
 }

@@ -114,6 +114,9 @@ def load_library():
     lib.pb_rank_choose.argtypes = [P, ctypes.c_int, P, ctypes.POINTER(ctypes.c_int),
                                    ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64), P]
     lib.pb_rank_choose.restype = ctypes.c_int
+    lib.pb_tip_decompose.argtypes = [P, ctypes.c_int, ctypes.POINTER(pb_opts), P, ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_uint64), P]
+    lib.pb_tip_decompose.restype = ctypes.c_int
     lib.pb_sparsify.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, P, P,
                                 ctypes.POINTER(ctypes.c_uint64), P]
     lib.pb_sparsify.restype = ctypes.c_int
@@ -289,6 +292,23 @@ def pb_rank_choose(g: Graph, other="approx_degree", out=None, stream=None):
                                          ctypes.byref(ws), ctypes.byref(wr), _stream(stream)), "pb_rank_choose")
     name = {v: n for n, v in RANK_KINDS.items()}[chosen.value]
     return out, name, ws.value, wr.value
+
+
+PEEL_SIDES = {"auto": 0, "u": 1, "v": 2}
+
+
+def pb_tip_decompose(g: Graph, side="auto", agg="auto", hub="auto", out=None, stream=None):
+    """Tip numbers by vertex peeling: (int64 CUDA tensor [n], -1 on the side
+    not peeled; the side peeled, "u" or "v"; rounds)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(g.n, dtype=torch.int64, device="cuda")
+    opts = make_opts(agg, hub)
+    s_out, rounds = ctypes.c_int(), ctypes.c_uint64()
+    _check(load_library().pb_tip_decompose(g.handle, PEEL_SIDES[side], ctypes.byref(opts),
+                                           _dev_ptr(out, torch.int64, "tip_out"), ctypes.byref(s_out),
+                                           ctypes.byref(rounds), _stream(stream)), "pb_tip_decompose")
+    return out, {1: "u", 2: "v"}.get(s_out.value, "u"), rounds.value
 
 
 SPARSIFY_KINDS = {"edge": 0, "color": 1}

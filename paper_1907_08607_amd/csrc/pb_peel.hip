@@ -1,0 +1,298 @@
+// Tip decomposition by vertex peeling (Section 3.2 "Peeling Framework",
+// Algorithm 5 PEEL-V / UPDATE-V), level-synchronous on the device.
+//
+// One side X is peeled.  B starts as the per-vertex butterfly counts (the
+// counting path).  Each round sets k = max(k, the smallest B among the
+// remaining X vertices), peels every remaining X vertex with B <= k (tip
+// number k) and runs UPDATE-V: for each peeled u1 and each remaining u2 the
+// two share c centres, and the C(c, 2) butterflies through u1 leave B(u2).
+//
+// UPDATE-V gives each peeled vertex to one workgroup, which walks its 2-hop
+// neighbourhood twice over a private dense counter slice of |X| words.  The
+// 2-hop entries are taken as one flat sequence, 1024 neighbour lists at a
+// time (a block scan of their lengths, then each thread finds its list by
+// binary search), so a vertex with long lists spreads over all the threads.
+// The first walk counts c(u1, u2) with atomic adds, the second takes each
+// count with an atomic exchange (which also clears the slice for the next
+// vertex) and subtracts C(c, 2) from B(u2) once per u2.
+//
+// The round state (k, the round's minimum, vertices left, rounds) stays on
+// the device, so rounds are queued in batches with one host synchronisation
+// per batch; a round with no vertex left does nothing.
+#include "pb_internal.h"
+
+using namespace pb;
+
+namespace {
+
+constexpr uint32_t PEEL_T = 1024;                      // threads per workgroup in the update
+constexpr uint32_t PEEL_MAX_GRID = 256;                // update workgroups (counter slices) at most
+constexpr uint64_t PEEL_SCRATCH = uint64_t(1) << 32;  // bytes of counter slices at most
+constexpr uint32_t PEEL_BATCH = 64;                    // rounds queued per host synchronisation
+
+struct PeelState {
+    int64_t k;                 // the level reached by the previous rounds
+    unsigned long long mn;     // this round's smallest B (~0: none left)
+    unsigned long long left;   // X vertices not yet peeled
+    unsigned long long rounds; // rounds that peeled something
+};
+
+struct Side {
+    // X vertices are unified ids base .. base + nx - 1.  Their lists (ids on
+    // the other side, local) and the other side's lists (local X ids).
+    const int64_t *xoff64;  // U-CSR row offsets when X = U
+    const uint32_t *xoff32; // V-CSR row offsets when X = V
+    const uint32_t *xadj;
+    const int64_t *yoff64;
+    const uint32_t *yoff32;
+    const uint32_t *yadj;
+    uint32_t base, nx;
+    __device__ uint64_t xb(uint32_t x) const { return xoff64 ? (uint64_t)xoff64[x] : xoff32[x]; }
+    __device__ uint64_t yb(uint32_t y) const { return yoff64 ? (uint64_t)yoff64[y] : yoff32[y]; }
+};
+
+// smallest B among remaining X vertices into *best (which starts at ~0: none left)
+__global__ __launch_bounds__(256) void k_peel_min(const int64_t *b, const uint32_t *gone, uint32_t nx,
+                                                  unsigned long long *best) {
+    __shared__ unsigned long long tmp[256 / WAVE];
+    unsigned long long mn = ~0ull;
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nx; x += gridDim.x * blockDim.x)
+        if (!gone[x]) {
+            const unsigned long long v = (unsigned long long)b[x];
+            mn = v < mn ? v : mn;
+        }
+    for (int s = WAVE / 2; s >= 1; s >>= 1) {
+        const unsigned long long o = __shfl_xor(mn, s, WAVE);
+        mn = o < mn ? o : mn;
+    }
+    if ((threadIdx.x & (WAVE - 1)) == 0) tmp[threadIdx.x / WAVE] = mn;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 256 / WAVE; ++i) mn = tmp[i] < mn ? tmp[i] : mn;
+        if (mn != ~0ull) atomicMin(best, mn);
+    }
+}
+
+// this round's level: max(k, the round's minimum)
+__device__ inline int64_t round_k(const PeelState *st) {
+    const unsigned long long mn = st->mn;
+    return mn != ~0ull && (int64_t)mn > st->k ? (int64_t)mn : st->k;
+}
+
+// flag[x] = remaining and B <= k
+__global__ void k_peel_flags(const int64_t *b, const uint32_t *gone, uint32_t nx, const PeelState *st,
+                             uint32_t *flag) {
+    const int64_t k = round_k(st);
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nx; x += gridDim.x * blockDim.x)
+        flag[x] = !gone[x] && b[x] <= k;
+}
+
+// the round's peeled vertices, in id order; their tip number is k
+__global__ void k_peel_take(const uint32_t *flag, const uint32_t *pos, uint32_t nx, uint32_t base,
+                            const PeelState *st, uint32_t *gone, uint32_t *front, int64_t *tip) {
+    const int64_t k = round_k(st);
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nx; x += gridDim.x * blockDim.x)
+        if (flag[x]) {
+            front[pos[x]] = x;
+            gone[x] = 1;
+            tip[base + x] = k;
+        }
+}
+
+// closes a round (one thread): k advances, the peeled vertices leave `left`,
+// and the next round's minimum starts empty
+__global__ void k_peel_close(const uint32_t *nfront, PeelState *st) {
+    const uint32_t nf = *nfront;
+    st->k = round_k(st);
+    st->left -= nf;
+    st->rounds += nf ? 1 : 0;
+    st->mn = ~0ull;
+}
+
+// UPDATE-V: one workgroup per peeled vertex (see the file comment).  `cnt`
+// holds gridDim.x slices of nx words, all zero on entry and on exit.
+__global__ __launch_bounds__(PEEL_T) void k_peel_update(Side S, const uint32_t *front, const uint32_t *nfront,
+                                                        const uint32_t *gone, uint32_t *cnt, int64_t *b) {
+    __shared__ uint32_t s_off[PEEL_T];  // flat start of each list of the chunk
+    __shared__ uint32_t s_y0[PEEL_T];   // first entry of each list
+    __shared__ uint32_t s_tmp[PEEL_T / WAVE + 1];
+    const uint32_t t = threadIdx.x;
+    uint32_t *c = cnt + (uint64_t)blockIdx.x * S.nx;
+    const uint32_t nf = *nfront;
+    for (uint32_t i = blockIdx.x; i < nf; i += gridDim.x) {
+        const uint32_t u1 = front[i];
+        const uint64_t p0 = S.xb(u1), p1 = S.xb(u1 + 1);
+        for (int pass = 1; pass <= 2; ++pass) {
+            for (uint64_t pc = p0; pc < p1; pc += PEEL_T) {
+                const uint64_t p = pc + t;
+                uint32_t len = 0, y0 = 0;
+                if (p < p1) {
+                    const uint32_t y = S.xadj[p];
+                    y0 = (uint32_t)S.yb(y);
+                    len = (uint32_t)(S.yb(y + 1) - y0);
+                }
+                uint32_t total;
+                const uint32_t off = block_exclusive_sum<PEEL_T>(len, s_tmp, &total);
+                s_off[t] = off;
+                s_y0[t] = y0;
+                __syncthreads();
+                const uint32_t nl = p1 - pc < PEEL_T ? (uint32_t)(p1 - pc) : PEEL_T;
+                for (uint32_t f = t; f < total; f += PEEL_T) {
+                    uint32_t lo = 0, hi = nl;  // largest j < nl with s_off[j] <= f
+                    while (hi - lo > 1) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (s_off[mid] <= f) lo = mid; else hi = mid;
+                    }
+                    const uint32_t u2 = S.yadj[s_y0[lo] + (f - s_off[lo])];
+                    if (gone[u2]) continue;
+                    if (pass == 1) {
+                        atomicAdd(&c[u2], 1u);
+                    } else {
+                        const uint32_t cc = atomicExch(&c[u2], 0u);
+                        if (cc >= 2) {
+                            const unsigned long long tt = (unsigned long long)cc * (cc - 1) / 2;
+                            atomicAdd(reinterpret_cast<unsigned long long *>(&b[u2]), 0ull - tt);
+                        }
+                    }
+                }
+                __syncthreads();  // s_off / s_y0 are refilled by the next chunk; pass 2 follows pass 1
+            }
+        }
+    }
+}
+
+// tip = -1 everywhere; B = the X side's per-vertex counts
+__global__ void k_peel_init(const int64_t *vcount, uint32_t base, uint32_t nx, uint64_t n, int64_t *tip,
+                            int64_t *b) {
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (uint64_t)gridDim.x * blockDim.x) {
+        tip[x] = -1;
+        if (x >= base && x - base < nx) b[x - base] = vcount[x];
+    }
+}
+
+// wedges with endpoints on U (centres on V) and with endpoints on V
+__global__ __launch_bounds__(256) void k_side_wedges(const uint32_t *deg, uint32_t n_u, uint64_t n,
+                                                     unsigned long long *sums) {
+    __shared__ unsigned long long tmp[256 / WAVE];
+    unsigned long long su = 0, sv = 0;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (uint64_t)gridDim.x * blockDim.x) {
+        const unsigned long long d = deg[x], w = d * (d - (d ? 1 : 0)) / 2;
+        if (x < n_u) sv += w; else su += w;
+    }
+    su = block_sum<256>(su, tmp);
+    sv = block_sum<256>(sv, tmp);
+    if (threadIdx.x == 0) {
+        if (su) atomicAdd(&sums[0], su);
+        if (sv) atomicAdd(&sums[1], sv);
+    }
+}
+
+uint32_t grid_of(uint64_t n, uint32_t cap) {
+    const uint64_t g = (n + 255) / 256;
+    return (uint32_t)(g == 0 ? 1 : g > cap ? cap : g);
+}
+
+struct HostBuf {
+    void *p = nullptr;
+    ~HostBuf() { if (p) (void)hipHostFree(p); }
+};
+
+pb_status peel_impl(pb_graph *g, pb_peel_side side, const pb_opts *opts, int64_t *tip, pb_peel_side *side_out,
+                    uint64_t *rounds_out, hipStream_t s) {
+    if (!g || !tip) return PB_ERR_INVALID_ARG;
+    if ((int)side < PB_PEEL_SIDE_AUTO || (int)side > PB_PEEL_SIDE_V) return PB_ERR_INVALID_ARG;
+    const uint64_t n = (uint64_t)g->n_u + g->n_v;
+    if (n == 0) {
+        if (side_out) *side_out = side == PB_PEEL_SIDE_V ? PB_PEEL_SIDE_V : PB_PEEL_SIDE_U;
+        if (rounds_out) *rounds_out = 0;
+        return PB_OK;
+    }
+    Workspace ws(s, 0);
+    HostBuf hb;
+    PB_TRY_HIP(hipHostMalloc(&hb.p, 64, hipHostMallocDefault));
+    unsigned long long *h = static_cast<unsigned long long *>(hb.p);
+    unsigned long long *dsum = ws.alloc<unsigned long long>(4);
+    if (ws.failed) return PB_ERR_NO_MEMORY;
+    if (side == PB_PEEL_SIDE_AUTO) {
+        PB_TRY(fill<uint64_t>((uint64_t *)dsum, 0ull, 2, s));
+        hipLaunchKernelGGL(k_side_wedges, dim3(grid_of(n, 1024)), dim3(256), 0, s, (const uint32_t *)g->deg, g->n_u, n,
+                           dsum);
+        PB_TRY_HIP(hipGetLastError());
+        PB_TRY_HIP(hipMemcpyAsync(h, dsum, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        PB_TRY_HIP(hipStreamSynchronize(s));
+        side = h[0] <= h[1] ? PB_PEEL_SIDE_U : PB_PEEL_SIDE_V;
+    }
+    const bool on_u = side == PB_PEEL_SIDE_U;
+    Side S{};
+    S.base = on_u ? 0u : g->n_u;
+    S.nx = on_u ? g->n_u : g->n_v;
+    if (on_u) {
+        S.xoff64 = g->u_off; S.xadj = g->u_adj; S.yoff32 = g->v_off; S.yadj = g->v_adj;
+    } else {
+        S.xoff32 = g->v_off; S.xadj = g->v_adj; S.yoff64 = g->u_off; S.yadj = g->u_adj;
+    }
+    // per-vertex butterfly counts under degree order (the counts do not depend on it)
+    uint32_t *rank = ws.alloc<uint32_t>(n);
+    int64_t *vcount = ws.alloc<int64_t>(n);
+    if (ws.failed) return PB_ERR_NO_MEMORY;
+    PB_TRY(pb_rank(g, PB_RANK_DEGREE, rank, s));
+    PB_TRY(pb_count_vertex(g, rank, opts, vcount, s));
+    ws.release(rank);
+    const uint32_t nx = S.nx;
+    int64_t *b = ws.alloc<int64_t>(nx);
+    uint32_t *gone = ws.alloc<uint32_t>(nx), *flag = ws.alloc<uint32_t>(nx), *pos = ws.alloc<uint32_t>((uint64_t)nx + 1);
+    uint32_t *front = ws.alloc<uint32_t>(nx);
+    if (ws.failed) return PB_ERR_NO_MEMORY;
+    hipLaunchKernelGGL(k_peel_init, dim3(grid_of(n, 65536)), dim3(256), 0, s, (const int64_t *)vcount, S.base, nx, n,
+                       tip, b);
+    PB_TRY_HIP(hipGetLastError());
+    ws.release(vcount);
+    uint64_t rounds = 0;
+    if (nx) {
+        // counter slices: one per update workgroup, as many as fit the scratch bound
+        const uint64_t slice = (uint64_t)nx * sizeof(uint32_t);
+        uint64_t grid = PEEL_SCRATCH / slice;
+        grid = grid > PEEL_MAX_GRID ? PEEL_MAX_GRID : grid < 1 ? 1 : grid;
+        const uint32_t ugrid = (uint32_t)grid;
+        uint32_t *cnt = ws.alloc<uint32_t>((uint64_t)ugrid * nx);
+        PeelState *st = ws.alloc<PeelState>(1);
+        if (ws.failed) return PB_ERR_NO_MEMORY;
+        PB_TRY(fill<uint32_t>(cnt, 0u, (uint64_t)ugrid * nx, s));
+        PB_TRY(fill<uint32_t>(gone, 0u, nx, s));
+        const PeelState st0{0, ~0ull, nx, 0};
+        PB_TRY_HIP(hipMemcpyAsync(st, &st0, sizeof(st0), hipMemcpyHostToDevice, s));
+        PeelState *hst = static_cast<PeelState *>(hb.p);
+        for (;;) {
+            for (uint32_t r = 0; r < PEEL_BATCH; ++r) {
+                hipLaunchKernelGGL(k_peel_min, dim3(grid_of(nx, 1024)), dim3(256), 0, s, (const int64_t *)b,
+                                   (const uint32_t *)gone, nx, &st->mn);
+                hipLaunchKernelGGL(k_peel_flags, dim3(grid_of(nx, 65536)), dim3(256), 0, s, (const int64_t *)b,
+                                   (const uint32_t *)gone, nx, (const PeelState *)st, flag);
+                PB_TRY_HIP(hipGetLastError());
+                PB_TRY((scan_exclusive<uint32_t, uint32_t>(flag, pos, nx, pos + nx, ws)));
+                hipLaunchKernelGGL(k_peel_take, dim3(grid_of(nx, 65536)), dim3(256), 0, s, (const uint32_t *)flag,
+                                   (const uint32_t *)pos, nx, S.base, (const PeelState *)st, gone, front, tip);
+                hipLaunchKernelGGL(k_peel_update, dim3(ugrid), dim3(PEEL_T), 0, s, S, (const uint32_t *)front,
+                                   (const uint32_t *)(pos + nx), (const uint32_t *)gone, cnt, b);
+                hipLaunchKernelGGL(k_peel_close, dim3(1), dim3(1), 0, s, (const uint32_t *)(pos + nx), st);
+                PB_TRY_HIP(hipGetLastError());
+            }
+            PB_TRY_HIP(hipMemcpyAsync(hst, st, sizeof(PeelState), hipMemcpyDeviceToHost, s));
+            PB_TRY_HIP(hipStreamSynchronize(s));
+            if (hst->left == 0) break;
+            if (hst->left > nx) return PB_ERR_HIP;  // cannot happen: each round takes at most what is left
+        }
+        rounds = hst->rounds;
+    }
+    PB_TRY_HIP(hipStreamSynchronize(s));
+    if (side_out) *side_out = side;
+    if (rounds_out) *rounds_out = rounds;
+    return PB_OK;
+}
+
+}  // namespace
+
+extern "C" pb_status pb_tip_decompose(pb_graph *g, pb_peel_side side, const pb_opts *opts, int64_t *tip_out,
+                                      pb_peel_side *side_out, uint64_t *rounds_out, hipStream_t stream) {
+    return peel_impl(g, side, opts, tip_out, side_out, rounds_out, stream);
+}

@@ -114,7 +114,6 @@ template pb_status fill<int64_t>(int64_t *, int64_t, uint64_t, hipStream_t);
 constexpr int RS_THREADS = 256;  // histogram kernel: one thread per digit
 constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
-constexpr int RS_WAVES = RS_THREADS / WAVE;
 constexpr int RSS_THREADS = 1024;  // scatter kernel
 constexpr int RSS_ITEMS = RS_TILE / RSS_THREADS;
 constexpr int RSS_WAVES = RSS_THREADS / WAVE;

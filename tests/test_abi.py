@@ -29,7 +29,8 @@ def test_header_declares_the_calls():
     names = declared_functions()
     for want in ("pb_graph_create", "pb_graph_destroy", "pb_rank", "pb_count", "pb_count_global",
                  "pb_count_vertex", "pb_count_edge", "pb_count_batched", "pb_autotune", "pb_status_str",
-                 "pb_opts_default", "pb_sparsify", "pb_count_approx", "pb_wedges", "pb_rank_choose"):
+                 "pb_opts_default", "pb_sparsify", "pb_count_approx", "pb_wedges", "pb_rank_choose",
+                 "pb_tip_decompose"):
         assert want in names
 
 
@@ -115,3 +116,8 @@ def test_wedges_and_chooser_argument_checks(lib):
     chosen = ctypes.c_int()
     assert lib.pb_wedges(None, None, ctypes.byref(w), None) == -1
     assert lib.pb_rank_choose(None, 4, None, ctypes.byref(chosen), None, None, None) == -1
+
+
+def test_tip_decompose_argument_checks(lib):
+    side = ctypes.c_int()
+    assert lib.pb_tip_decompose(None, 0, None, None, ctypes.byref(side), None, None) == -1
