@@ -389,8 +389,6 @@ def run_batch(args):
                    "same_results_as_one_graph_per_launch": same},
         "cpu_baseline": None,
     }
-    if traffic_note:
-        record["roofline"]["traffic_note"] = traffic_note
     if not args.no_cpu_baseline:
         # the oracle on the batch's graphs in order, for about the target time
         import oracle
