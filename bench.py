@@ -494,8 +494,8 @@ def run_serve(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the counting path "
+              "runs on a single device, with no collectives", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
