@@ -74,9 +74,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="powerlaw_50m",
-                    choices=["powerlaw_50m", "hub_100m", "er_1k", "batch", "serve", "copy", "approx", "choose", "tip"])
+                    choices=["powerlaw_50m", "hub_100m", "er_1k", "batch", "serve", "copy", "approx", "choose", "tip",
+                             "wing"])
     ap.add_argument("--p", type=float, default=0.1, help="approx: sampling rate")
     ap.add_argument("--tip-scale", type=float, default=0.05, help="tip: size of the power-law graph")
+    ap.add_argument("--wing-scale", type=float, default=0.003, help="wing: size of the power-law graph")
     ap.add_argument("--graphs", type=int, default=4096, help="batch: graphs in the batch")
     ap.add_argument("--pool-small", type=int, default=10_000, help="serve: resident small graphs")
     ap.add_argument("--pool-big", type=int, default=50, help="serve: resident 5M-edge graphs")
@@ -333,6 +335,49 @@ def run_tip(args):
     print(json.dumps(line), flush=True)
 
 
+def run_wing(args):
+    """Wing decomposition (edge peeling, Section 3.2 and Algorithm 6) of the
+    power-law generator at --wing-scale of the powerlaw_50m size.  One step =
+    the whole decomposition (initial per-edge count + every peeling round).
+    `value` is input edges per second of one decomposition."""
+    import argparse as _ap
+    import numpy as np
+    import torch
+
+    import paper_1907_08607_amd as pb
+    g, desc, _ = make_graph(_ap.Namespace(**{**vars(args), "workload": "powerlaw_50m", "scale": args.wing_scale,
+                                               "rank": "degree"}))
+    desc["outputs"] = "wing numbers"
+    print(f"[bench] graph {desc}", file=sys.stderr, flush=True)
+    G = pb.Graph.from_csr(g)
+    for _ in range(args.warmup):
+        wing, rounds = pb.pb_wing_decompose(G)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        wing, rounds = pb.pb_wing_decompose(G)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    w = wing.cpu().numpy()
+    G.close()
+    line = {"metric": "edges/s", "value": g.m / (ms * 1e-3), "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+            "config": {"workload": "wing_decomposition", "graph": desc, "rounds": rounds,
+                       "ms_per_round": ms / rounds if rounds else None, "max_wing": int(w.max()) if w.size else 0,
+                       "note": "one step = initial per-edge count + all peeling rounds (queued in batches of 64, "
+                               "one host synchronisation per batch)"}}
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        want, want_rounds = oracle.wing(g)
+        dt = time.perf_counter() - t0
+        line["config"]["same_as_oracle"] = bool(np.array_equal(want, w)) and want_rounds == rounds
+        line["cpu_baseline"] = {"value": g.m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                                "sample": f"the whole decomposition of the same graph: {dt:.1f} s"}
+    print(json.dumps(line), flush=True)
+
+
 def upload(graphs, pb):
     return [pb.Graph.from_csr(g) for g in graphs]
 
@@ -516,6 +561,8 @@ def main():
         return run_choose(args)
     if args.workload == "tip":
         return run_tip(args)
+    if args.workload == "wing":
+        return run_wing(args)
     t0 = time.time()
     g, desc, rank_kind = make_graph(args)
     print(f"[bench] graph {desc} built in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)

@@ -307,7 +307,7 @@ pb_status pb_count_approx(pb_graph *g, pb_sparsify_kind kind, double p, uint64_t
  *   side_out   host, optional: the side peeled (PB_PEEL_SIDE_U or _V)
  *   rounds_out host, optional: peeling rounds
  * `opts` (NULL = defaults) applies to the initial count.  Synchronises
- * `stream` once per round.  Uses device scratch of up to 4 GiB of counters
+ * `stream` every 64 rounds.  Uses device scratch of up to 4 GiB of counters
  * beside the counting call's own.
  * Errors: INVALID_ARG, NO_MEMORY, HIP, and those of pb_count_vertex. */
 typedef enum {
@@ -318,6 +318,21 @@ typedef enum {
 
 pb_status pb_tip_decompose(pb_graph *g, pb_peel_side side, const pb_opts *opts, int64_t *tip_out,
                            pb_peel_side *side_out, uint64_t *rounds_out, hipStream_t stream);
+
+/* Wing decomposition by edge peeling (Section 3.2 "Peeling Framework",
+ * Algorithm 6 PEEL-E / UPDATE-E).  Starting from the per-edge butterfly
+ * counts B, each round sets k = max(k, smallest B of the remaining edges) and
+ * peels every remaining edge with B <= k (its wing number is k).  A
+ * butterfly that loses an edge in a round and had lost none before is
+ * destroyed once (by the peeled edge of smallest id among its edges peeled in
+ * that round), and each of its remaining edges loses 1.
+ *   wing_out   device int64[m], by u_adj position
+ *   rounds_out host, optional: peeling rounds
+ * `opts` (NULL = defaults) applies to the initial count.  Synchronises
+ * `stream` every 64 rounds.  Errors: INVALID_ARG, NO_MEMORY, HIP, and those of
+ * pb_count_edge. */
+pb_status pb_wing_decompose(pb_graph *g, const pb_opts *opts, int64_t *wing_out, uint64_t *rounds_out,
+                            hipStream_t stream);
 
 /* Batched counting: `count` independent graphs in one pass of the pipeline.
  * The batch is counted as the disjoint union of the graphs (no wedge spans two

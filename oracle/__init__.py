@@ -43,6 +43,7 @@ def _load():
         lib.orc_splitmix.restype = ctypes.c_uint64
         lib.orc_sparsify.argtypes = [_I, _I, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, _P, _P, _P]
         lib.orc_tip.argtypes = [_I, _I, _P, _P, ctypes.c_int, _P, _P]
+        lib.orc_wing.argtypes = [_I, _I, _P, _P, _P, _P]
         _lib = lib
     return _lib
 
@@ -206,3 +207,13 @@ def tip(g, side: str = "auto"):
     rounds = np.zeros(1, dtype=np.int64)
     _check(_load().orc_tip(g.n_u, g.n_v, _ptr(off), _ptr(adj), PEEL_SIDES[side], _ptr(out), _ptr(rounds)), "orc_tip")
     return out, int(rounds[0])
+
+
+def wing(g):
+    """Wing numbers by edge peeling (Section 3.2, Algorithm 6): (wing int64[m]
+    by u_adj position, rounds)."""
+    off, adj = _csr(g)
+    out = np.zeros(max(g.m, 1), dtype=np.int64)
+    rounds = np.zeros(1, dtype=np.int64)
+    _check(_load().orc_wing(g.n_u, g.n_v, _ptr(off), _ptr(adj), _ptr(out), _ptr(rounds)), "orc_wing")
+    return out[:g.m], int(rounds[0])

@@ -30,6 +30,7 @@
  *   orc_sparsify  the kept graph of edge or colorful sparsification (Section
  *              4.6 "Approximate counting")
  *   orc_tip    tip numbers by vertex peeling (Section 3.2, Algorithm 5)
+ *   orc_wing   wing numbers by edge peeling (Section 3.2, Algorithm 6)
  * Every function returns 0 on success and a negative value on bad input or
  * allocation failure.
  */
@@ -655,5 +656,89 @@ int orc_tip(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_ad
     }
     *rounds_out = rounds;
     free(b); free(c); free(gone); free(front); free(glob); free(vert); free(edge); free_vside(&vs);
+    return 0;
+}
+
+/*
+ * Wing decomposition by edge peeling (Section 3.2 "Peeling Framework" and
+ * Algorithm 6, PEEL-E / UPDATE-E).  B starts as the per-edge butterfly
+ * counts.  Each round sets k = max(k, smallest B among the remaining edges)
+ * and peels every remaining edge with B <= k (its wing number is k).  Every
+ * butterfly that loses an edge this round and had lost none before is
+ * destroyed once: the peeled edge of smallest id among its edges peeled this
+ * round enumerates it, and each of its edges that remains loses 1.  The
+ * butterflies of edge (u1, v1) are (u1, v1, u2, v2) for u2 in N(v1), u2 !=
+ * u1, and v2 in N(u1) & N(u2), v2 != v1.  wing[e] is indexed by u_adj
+ * position; *rounds_out counts the rounds.
+ */
+static int64_t find_edge(const int64_t *u_off, const uint32_t *u_adj, int64_t u, uint32_t v) {
+    int64_t lo = u_off[u], hi = u_off[u + 1];
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (u_adj[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    return (lo < u_off[u + 1] && u_adj[lo] == v) ? lo : -1;
+}
+
+int orc_wing(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_adj, int64_t *wing,
+             int64_t *rounds_out) {
+    if (check_csr(n_u, n_v, u_off, u_adj) != 0) return -1;
+    const int64_t n = n_u + n_v, m = n_u ? u_off[n_u] : 0;
+    vside vs;
+    if (build_vside(n_u, n_v, u_off, u_adj, &vs) != 0) return -2;
+    int64_t *glob = malloc(sizeof(int64_t)), *vert = calloc((size_t)(n ? n : 1), sizeof(int64_t));
+    int64_t *b = calloc((size_t)(m ? m : 1), sizeof(int64_t));
+    int64_t *eu = malloc(sizeof(int64_t) * (size_t)(m ? m : 1));
+    int64_t *state = calloc((size_t)(m ? m : 1), sizeof(int64_t));  /* round peeled in, 0 = remaining */
+    int64_t *front = malloc(sizeof(int64_t) * (size_t)(m ? m : 1));
+    if (!glob || !vert || !b || !eu || !state || !front || orc_count(n_u, n_v, u_off, u_adj, glob, vert, b) != 0) {
+        free(glob); free(vert); free(b); free(eu); free(state); free(front); free_vside(&vs);
+        return -2;
+    }
+    for (int64_t u = 0; u < n_u; ++u)
+        for (int64_t e = u_off[u]; e < u_off[u + 1]; ++e) eu[e] = u;
+    int64_t left = m, k = 0, rounds = 0;
+    while (left > 0) {
+        const int64_t r = rounds + 1;
+        int64_t mn = -1;
+        for (int64_t e = 0; e < m; ++e)
+            if (!state[e] && (mn < 0 || b[e] < mn)) mn = b[e];
+        if (mn > k) k = mn;
+        int64_t nf = 0;
+        for (int64_t e = 0; e < m; ++e)
+            if (!state[e] && b[e] <= k) front[nf++] = e;
+        for (int64_t i = 0; i < nf; ++i) {
+            state[front[i]] = r;
+            wing[front[i]] = k;
+        }
+        for (int64_t i = 0; i < nf; ++i) {
+            const int64_t e = front[i], u1 = eu[e];
+            const uint32_t v1 = u_adj[e];
+            for (int64_t p = vs.off[v1]; p < vs.off[v1 + 1]; ++p) {
+                const int64_t u2 = vs.adj[p], e2 = vs.eid[p];  /* edge (u2, v1) */
+                if (u2 == u1) continue;
+                for (int64_t a = u_off[u1]; a < u_off[u1 + 1]; ++a) {
+                    const uint32_t v2 = u_adj[a];
+                    if (v2 == v1) continue;
+                    const int64_t e3 = find_edge(u_off, u_adj, u2, v2);  /* edge (u2, v2) */
+                    if (e3 < 0) continue;
+                    const int64_t e1 = a;                                /* edge (u1, v2) */
+                    const int64_t other[3] = {e1, e2, e3};
+                    int skip = 0;
+                    for (int j = 0; j < 3; ++j) {
+                        const int64_t s2 = state[other[j]];
+                        if ((s2 && s2 < r) || (s2 == r && other[j] < e)) skip = 1;
+                    }
+                    if (skip) continue;
+                    for (int j = 0; j < 3; ++j)
+                        if (!state[other[j]]) b[other[j]] -= 1;
+                }
+            }
+        }
+        left -= nf;
+        rounds = r;
+    }
+    *rounds_out = rounds;
+    free(glob); free(vert); free(b); free(eu); free(state); free(front); free_vside(&vs);
     return 0;
 }

@@ -36,4 +36,6 @@ int orc_sparsify(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t 
                  uint64_t seed, int64_t *out_off, uint32_t *out_adj, int64_t *kept);
 int orc_tip(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_adj, int side, int64_t *tip,
             int64_t *rounds_out);
+int orc_wing(int64_t n_u, int64_t n_v, const int64_t *u_off, const uint32_t *u_adj, int64_t *wing,
+             int64_t *rounds_out);
 #endif

@@ -117,6 +117,8 @@ def load_library():
     lib.pb_tip_decompose.argtypes = [P, ctypes.c_int, ctypes.POINTER(pb_opts), P, ctypes.POINTER(ctypes.c_int),
                                      ctypes.POINTER(ctypes.c_uint64), P]
     lib.pb_tip_decompose.restype = ctypes.c_int
+    lib.pb_wing_decompose.argtypes = [P, ctypes.POINTER(pb_opts), P, ctypes.POINTER(ctypes.c_uint64), P]
+    lib.pb_wing_decompose.restype = ctypes.c_int
     lib.pb_sparsify.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_uint64, P, P,
                                 ctypes.POINTER(ctypes.c_uint64), P]
     lib.pb_sparsify.restype = ctypes.c_int
@@ -309,6 +311,18 @@ def pb_tip_decompose(g: Graph, side="auto", agg="auto", hub="auto", out=None, st
                                            _dev_ptr(out, torch.int64, "tip_out"), ctypes.byref(s_out),
                                            ctypes.byref(rounds), _stream(stream)), "pb_tip_decompose")
     return out, {1: "u", 2: "v"}.get(s_out.value, "u"), rounds.value
+
+
+def pb_wing_decompose(g: Graph, agg="auto", hub="auto", out=None, stream=None):
+    """Wing numbers by edge peeling: (int64 CUDA tensor [m] by u_adj position, rounds)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(max(g.m, 1), dtype=torch.int64, device="cuda")
+    opts = make_opts(agg, hub)
+    rounds = ctypes.c_uint64()
+    _check(load_library().pb_wing_decompose(g.handle, ctypes.byref(opts), _dev_ptr(out, torch.int64, "wing_out"),
+                                            ctypes.byref(rounds), _stream(stream)), "pb_wing_decompose")
+    return out[:g.m], rounds.value
 
 
 SPARSIFY_KINDS = {"edge": 0, "color": 1}

@@ -33,8 +33,9 @@ constexpr uint32_t PEEL_BATCH = 64;                    // rounds queued per host
 struct PeelState {
     int64_t k;                 // the level reached by the previous rounds
     unsigned long long mn;     // this round's smallest B (~0: none left)
-    unsigned long long left;   // X vertices not yet peeled
+    unsigned long long left;   // vertices (or edges) not yet peeled
     unsigned long long rounds; // rounds that peeled something
+    unsigned long long rid;    // edge peeling: id of the current round (1, 2, ...)
 };
 
 struct Side {
@@ -259,7 +260,7 @@ pb_status peel_impl(pb_graph *g, pb_peel_side side, const pb_opts *opts, int64_t
         if (ws.failed) return PB_ERR_NO_MEMORY;
         PB_TRY(fill<uint32_t>(cnt, 0u, (uint64_t)ugrid * nx, s));
         PB_TRY(fill<uint32_t>(gone, 0u, nx, s));
-        const PeelState st0{0, ~0ull, nx, 0};
+        const PeelState st0{0, ~0ull, nx, 0, 1};
         PB_TRY_HIP(hipMemcpyAsync(st, &st0, sizeof(st0), hipMemcpyHostToDevice, s));
         PeelState *hst = static_cast<PeelState *>(hb.p);
         for (;;) {
@@ -290,9 +291,164 @@ pb_status peel_impl(pb_graph *g, pb_peel_side side, const pb_opts *opts, int64_t
     return PB_OK;
 }
 
+// ---------------------------------------------------------------- edge peeling
+
+// Wing decomposition (Section 3.2, Algorithm 6 PEEL-E / UPDATE-E), rounds as
+// for vertices.  state[e] is the round that peeled edge e (0: remaining).
+// A butterfly that loses edges in round r and had lost none before is
+// destroyed once: by the peeled edge of smallest id among its edges peeled in
+// r, which lowers each of its remaining edges by 1.
+
+__global__ __launch_bounds__(256) void k_wing_min(const int64_t *b, const uint32_t *state, uint64_t m,
+                                                  unsigned long long *best) {
+    __shared__ unsigned long long tmp[256 / WAVE];
+    unsigned long long mn = ~0ull;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
+        if (!state[e]) {
+            const unsigned long long v = (unsigned long long)b[e];
+            mn = v < mn ? v : mn;
+        }
+    for (int d = WAVE / 2; d >= 1; d >>= 1) {
+        const unsigned long long o = __shfl_xor(mn, d, WAVE);
+        mn = o < mn ? o : mn;
+    }
+    if ((threadIdx.x & (WAVE - 1)) == 0) tmp[threadIdx.x / WAVE] = mn;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 256 / WAVE; ++i) mn = tmp[i] < mn ? tmp[i] : mn;
+        if (mn != ~0ull) atomicMin(best, mn);
+    }
+}
+
+__global__ void k_wing_flags(const int64_t *b, const uint32_t *state, uint64_t m, const PeelState *st,
+                             uint32_t *flag) {
+    const int64_t k = round_k(st);
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
+        flag[e] = !state[e] && b[e] <= k;
+}
+
+__global__ void k_wing_take(const uint32_t *flag, const uint32_t *pos, uint64_t m, const PeelState *st,
+                            uint32_t *state, uint32_t *front, int64_t *wing) {
+    const int64_t k = round_k(st);
+    const uint32_t rid = (uint32_t)st->rid;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
+        if (flag[e]) {
+            front[pos[e]] = (uint32_t)e;
+            state[e] = rid;
+            wing[e] = k;
+        }
+}
+
+struct WingGraph {
+    const int64_t *u_off;
+    const uint32_t *u_adj, *eu, *v_off, *v_adj, *v_eid;
+};
+
+// UPDATE-E: one workgroup per peeled edge (u1, v1); each thread takes one u2
+// in N(v1) and merges the sorted rows N(u1) and N(u2) for the v2 they share.
+__global__ __launch_bounds__(256) void k_wing_update(WingGraph W, const uint32_t *front, const uint32_t *nfront,
+                                                     const PeelState *st, const uint32_t *state, int64_t *b) {
+    const uint32_t nf = *nfront;
+    const uint32_t rid = (uint32_t)st->rid;
+    for (uint32_t i = blockIdx.x; i < nf; i += gridDim.x) {
+        const uint32_t e = front[i];
+        const uint32_t u1 = W.eu[e], v1 = W.u_adj[e];
+        const int64_t a0 = W.u_off[u1], a1 = W.u_off[u1 + 1];
+        for (uint32_t p = W.v_off[v1] + threadIdx.x; p < W.v_off[v1 + 1]; p += blockDim.x) {
+            const uint32_t u2 = W.v_adj[p], e2 = W.v_eid[p];  // edge (u2, v1)
+            if (u2 == u1) continue;
+            const uint32_t s2 = state[e2];
+            if ((s2 && s2 < rid) || (s2 == rid && e2 < e)) continue;
+            int64_t a = a0, c = W.u_off[u2];
+            const int64_t c1 = W.u_off[u2 + 1];
+            while (a < a1 && c < c1) {
+                const uint32_t va = W.u_adj[a], vc = W.u_adj[c];
+                if (va < vc) { ++a; continue; }
+                if (vc < va) { ++c; continue; }
+                if (va != v1) {
+                    const uint32_t e1 = (uint32_t)a, e3 = (uint32_t)c;  // edges (u1, v2), (u2, v2)
+                    const uint32_t s1 = state[e1], s3 = state[e3];
+                    const bool skip = (s1 && s1 < rid) || (s3 && s3 < rid) || (s1 == rid && e1 < e) ||
+                                      (s3 == rid && e3 < e);
+                    if (!skip) {
+                        if (!s1) atomicAdd(reinterpret_cast<unsigned long long *>(&b[e1]), ~0ull);
+                        if (!s2) atomicAdd(reinterpret_cast<unsigned long long *>(&b[e2]), ~0ull);
+                        if (!s3) atomicAdd(reinterpret_cast<unsigned long long *>(&b[e3]), ~0ull);
+                    }
+                }
+                ++a;
+                ++c;
+            }
+        }
+    }
+}
+
+__global__ void k_wing_close(const uint32_t *nfront, PeelState *st) {
+    const uint32_t nf = *nfront;
+    st->k = round_k(st);
+    st->left -= nf;
+    st->rounds += nf ? 1 : 0;
+    st->rid += 1;
+    st->mn = ~0ull;
+}
+
+pb_status wing_impl(pb_graph *g, const pb_opts *opts, int64_t *wing, uint64_t *rounds_out, hipStream_t s) {
+    if (!g || (g->m && !wing)) return PB_ERR_INVALID_ARG;
+    const uint64_t n = (uint64_t)g->n_u + g->n_v, m = g->m;
+    if (m == 0) {
+        if (rounds_out) *rounds_out = 0;
+        return PB_OK;
+    }
+    Workspace ws(s, 0);
+    HostBuf hb;
+    PB_TRY_HIP(hipHostMalloc(&hb.p, 64, hipHostMallocDefault));
+    uint32_t *rank = ws.alloc<uint32_t>(n);
+    int64_t *b = ws.alloc<int64_t>(m);
+    if (ws.failed) return PB_ERR_NO_MEMORY;
+    PB_TRY(pb_rank(g, PB_RANK_DEGREE, rank, s));
+    PB_TRY(pb_count_edge(g, rank, opts, b, s));
+    ws.release(rank);
+    uint32_t *state = ws.alloc<uint32_t>(m), *flag = ws.alloc<uint32_t>(m), *pos = ws.alloc<uint32_t>(m + 1);
+    uint32_t *front = ws.alloc<uint32_t>(m);
+    PeelState *st = ws.alloc<PeelState>(1);
+    if (ws.failed) return PB_ERR_NO_MEMORY;
+    PB_TRY(fill<uint32_t>(state, 0u, m, s));
+    const PeelState st0{0, ~0ull, m, 0, 1};
+    PB_TRY_HIP(hipMemcpyAsync(st, &st0, sizeof(st0), hipMemcpyHostToDevice, s));
+    const WingGraph W{g->u_off, g->u_adj, g->eu, g->v_off, g->v_adj, g->v_eid};
+    PeelState *hst = static_cast<PeelState *>(hb.p);
+    for (;;) {
+        for (uint32_t r = 0; r < PEEL_BATCH; ++r) {
+            hipLaunchKernelGGL(k_wing_min, dim3(grid_of(m, 1024)), dim3(256), 0, s, (const int64_t *)b,
+                               (const uint32_t *)state, m, &st->mn);
+            hipLaunchKernelGGL(k_wing_flags, dim3(grid_of(m, 65536)), dim3(256), 0, s, (const int64_t *)b,
+                               (const uint32_t *)state, m, (const PeelState *)st, flag);
+            PB_TRY_HIP(hipGetLastError());
+            PB_TRY((scan_exclusive<uint32_t, uint32_t>(flag, pos, m, pos + m, ws)));
+            hipLaunchKernelGGL(k_wing_take, dim3(grid_of(m, 65536)), dim3(256), 0, s, (const uint32_t *)flag,
+                               (const uint32_t *)pos, m, (const PeelState *)st, state, front, wing);
+            hipLaunchKernelGGL(k_wing_update, dim3(1024), dim3(256), 0, s, W, (const uint32_t *)front,
+                               (const uint32_t *)(pos + m), (const PeelState *)st, (const uint32_t *)state, b);
+            hipLaunchKernelGGL(k_wing_close, dim3(1), dim3(1), 0, s, (const uint32_t *)(pos + m), st);
+            PB_TRY_HIP(hipGetLastError());
+        }
+        PB_TRY_HIP(hipMemcpyAsync(hst, st, sizeof(PeelState), hipMemcpyDeviceToHost, s));
+        PB_TRY_HIP(hipStreamSynchronize(s));
+        if (hst->left == 0) break;
+        if (hst->left > m) return PB_ERR_HIP;  // cannot happen: each round takes at most what is left
+    }
+    if (rounds_out) *rounds_out = hst->rounds;
+    return PB_OK;
+}
+
 }  // namespace
 
 extern "C" pb_status pb_tip_decompose(pb_graph *g, pb_peel_side side, const pb_opts *opts, int64_t *tip_out,
                                       pb_peel_side *side_out, uint64_t *rounds_out, hipStream_t stream) {
     return peel_impl(g, side, opts, tip_out, side_out, rounds_out, stream);
+}
+
+extern "C" pb_status pb_wing_decompose(pb_graph *g, const pb_opts *opts, int64_t *wing_out, uint64_t *rounds_out,
+                                       hipStream_t stream) {
+    return wing_impl(g, opts, wing_out, rounds_out, stream);
 }

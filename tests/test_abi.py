@@ -30,7 +30,7 @@ def test_header_declares_the_calls():
     for want in ("pb_graph_create", "pb_graph_destroy", "pb_rank", "pb_count", "pb_count_global",
                  "pb_count_vertex", "pb_count_edge", "pb_count_batched", "pb_autotune", "pb_status_str",
                  "pb_opts_default", "pb_sparsify", "pb_count_approx", "pb_wedges", "pb_rank_choose",
-                 "pb_tip_decompose"):
+                 "pb_tip_decompose", "pb_wing_decompose"):
         assert want in names
 
 
@@ -121,3 +121,7 @@ def test_wedges_and_chooser_argument_checks(lib):
 def test_tip_decompose_argument_checks(lib):
     side = ctypes.c_int()
     assert lib.pb_tip_decompose(None, 0, None, None, ctypes.byref(side), None, None) == -1
+
+
+def test_wing_decompose_argument_checks(lib):
+    assert lib.pb_wing_decompose(None, None, None, None, None) == -1
