@@ -94,6 +94,8 @@ def parse():
     ap.add_argument("--agg", default="auto", choices=["auto", "hash", "dense", "sort"])
     ap.add_argument("--hub", default="auto", choices=["auto", "off", "force"], help="hub tile mode")
     ap.add_argument("--outputs", default="all", choices=["all", "global", "vertex", "edge"])
+    ap.add_argument("--cache-opt", action="store_true",
+                    help="retrieve wedges from their lower-ranked endpoint (same counts)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-target-s", type=float, default=15.0, help="CPU-baseline sample budget")
     return ap.parse_args()
@@ -579,7 +581,8 @@ def main():
     def step(stats):
         G = pb.Graph(g.n_u, g.n_v, off, adj, stream)
         r = pb.pb_rank(G, rank_kind, stream=stream)
-        pb.pb_count(G, r, agg=args.agg, hub=args.hub, stats=stats, outs=step_outs, stream=stream, timing=True)
+        pb.pb_count(G, r, agg=args.agg, hub=args.hub, stats=stats, outs=step_outs, stream=stream, timing=True,
+                    cache_opt=args.cache_opt)
         G.close()
 
     for i in range(args.warmup):

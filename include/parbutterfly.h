@@ -162,6 +162,13 @@ typedef struct {
 
 /* opts.flags bits */
 #define PB_FLAG_TIMING 1u
+/* Retrieve each wedge from its lower-ranked endpoint: for every vertex u,
+ * the wedges (x1, y, u) with x1 ranked above both y and u, aggregated by x1
+ * (the cache optimisation of Section 3.1 that the paper takes from Wang et
+ * al.).  The same wedges and the same counts; only the order of work changes.
+ * Single-graph calls only (ignored by batched calls); the hub tile is not
+ * used with it. */
+#define PB_FLAG_CACHE_OPT 2u
 
 /* Per-bucket choices of the AUTO aggregation policy.  Sources are bucketed by
  * the bound min(W(x1), candidate range) on their distinct endpoints (W = the

@@ -42,6 +42,7 @@ class pb_csr(ctypes.Structure):
 
 
 PB_FLAG_TIMING = 1
+PB_FLAG_CACHE_OPT = 2
 
 
 class pb_stats(ctypes.Structure):
@@ -211,11 +212,14 @@ class Graph:
         return cls(csr.n_u, csr.n_v, off, adj, stream)
 
 
-def make_opts(agg="auto", hub="auto", workspace_cap=0, stats=None, timing=False, tuning=None) -> pb_opts:
+def make_opts(agg="auto", hub="auto", workspace_cap=0, stats=None, timing=False, tuning=None,
+              cache_opt=False) -> pb_opts:
     o = pb_opts()
     load_library().pb_opts_default(ctypes.byref(o))
     if timing:
         o.flags |= PB_FLAG_TIMING
+    if cache_opt:
+        o.flags |= PB_FLAG_CACHE_OPT
     if tuning is not None:
         o.tuning = ctypes.pointer(tuning)
     o.agg = AGGS[agg] if isinstance(agg, str) else int(agg)
@@ -237,7 +241,8 @@ def pb_rank(g: Graph, kind="degree", out=None, stream=None):
 
 
 def pb_count(g: Graph, rank, want_global=True, want_vertex=True, want_edge=True, agg="auto", hub="auto",
-             workspace_cap=0, stats: pb_stats | None = None, outs=None, stream=None, timing=False, tuning=None):
+             workspace_cap=0, stats: pb_stats | None = None, outs=None, stream=None, timing=False, tuning=None,
+             cache_opt=False):
     """(global int64 tensor[1] or None, per-vertex int64[n] or None, per-edge int64[m] or None)."""
     torch = _torch()
     if outs is None:
@@ -245,7 +250,7 @@ def pb_count(g: Graph, rank, want_global=True, want_vertex=True, want_edge=True,
                 torch.empty(g.n, dtype=torch.int64, device="cuda") if want_vertex else None,
                 torch.empty(g.m, dtype=torch.int64, device="cuda") if want_edge else None)
     gout, vout, eout = outs
-    opts = make_opts(agg, hub, workspace_cap, stats, timing, tuning)
+    opts = make_opts(agg, hub, workspace_cap, stats, timing, tuning, cache_opt)
     ptr = lambda t, name: None if t is None else _dev_ptr(t, torch.int64, name)
     _check(load_library().pb_count(g.handle, _dev_ptr(rank, torch.int32, "rank"), ctypes.byref(opts),
                                    ptr(gout, "global_out"), ptr(vout, "vertex_out"), ptr(eout, "edge_out"),

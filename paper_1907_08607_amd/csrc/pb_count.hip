@@ -193,6 +193,31 @@ __global__ void k_upslots(const uint64_t *keys, const uint32_t *vals, uint64_t n
     }
 }
 
+// Up-slots of the cache-optimised order: every slot (u -> y) is an up-slot
+// (so up-slot k is slot k), and its run is the suffix of N(y) holding the
+// neighbours ranked before both y and u (N(y) is by decreasing rank, so
+// those come last): q = min(deg y - hideg y, deg y - pos - 1) entries, pos =
+// the position of u in N(y).
+__global__ void k_upslots_copt(const uint64_t *keys, const uint32_t *vals, uint64_t ns, int b, const uint32_t *roff,
+                               const uint32_t *hideg, const uint32_t *eslot, uint32_t *uprun, uint32_t *uplen) {
+    const uint64_t mask = (uint64_t(1) << b) - 1;
+    GRID_STRIDE(p, ns) {
+        const uint64_t key = keys[p];
+        const uint32_t d = (uint32_t)(mask - (key & mask));
+        const uint32_t pos = eslot[vals[p] ^ 1u] - roff[d];  // slot (d -> u) within N(d)
+        const uint32_t degy = roff[d + 1] - roff[d];
+        const uint32_t before_y = degy - hideg[d], before_u = degy - pos - 1;
+        const uint32_t q = before_y < before_u ? before_y : before_u;
+        uprun[p] = roff[d] + degy - q;
+        uplen[p] = q;
+    }
+}
+
+// cache-optimised order: the candidates of source r are the smids before its own
+__global__ void k_cend_copt(const uint32_t *smid, uint64_t n, uint32_t *cend) {
+    GRID_STRIDE(r, n) cend[r] = smid[r];
+}
+
 // ---------------------------------------------------------------- plan
 
 // Work lists: every source with wedges goes to exactly one.
@@ -276,7 +301,7 @@ constexpr uint32_t PLAN_GRID = 2048;
 __global__ __launch_bounds__(256) void k_plan(const uint32_t *upoff, const uint64_t *wscan, const uint32_t *smid,
                                               const uint32_t *cend, uint64_t n, Policy pol, uint32_t hub_base,
                                               uint32_t hub_end, const unsigned long long *roww, uint32_t *lists,
-                                              uint32_t *nwin, uint64_t *wl, PlanCounts *pc) {
+                                              uint32_t *nwin, uint64_t *wl, PlanCounts *pc, uint32_t copt_nu) {
     __shared__ uint32_t cnt[NLISTS], base[NLISTS], s_items;
     __shared__ unsigned long long wsum[NLISTS], s_sources;
     if (!pc->hub.on) hub_end = hub_base;
@@ -299,7 +324,7 @@ __global__ __launch_bounds__(256) void k_plan(const uint32_t *upoff, const uint6
             const uint32_t sm = smid[r];
             w = wscan[upoff[r + 1]] - wscan[upoff[r]];
             if (sm >= hub_base && sm < hub_end) w -= roww[sm - hub_base];
-            const uint32_t lo = cand_lo(sm, hub_base, hub_end);
+            const uint32_t lo = copt_nu ? (sm < copt_nu - 1 ? 0u : copt_nu - 1) : cand_lo(sm, hub_base, hub_end);
             if (w != 0 && lo < cend[r]) {
                 range = cend[r] - lo;
                 const uint64_t dist = w < range ? w : range;
@@ -420,8 +445,12 @@ struct Ranked {
     const uint32_t *gid;   // per rank: its graph in a batch (null: one graph)
     uint32_t n_u, n;
     uint32_t hub_base, hub_end;  // side-major ids of the hub tile's vertices (empty: no tile)
+    bool copt;                   // cache-optimised order: candidates are the smids before the source's
     // first candidate endpoint id of source r
-    __device__ uint32_t lo(uint32_t r) const { return cand_lo(smid[r], hub_base, hub_end); }
+    __device__ uint32_t lo(uint32_t r) const {
+        if (copt) return smid[r] < n_u ? 0u : n_u;
+        return cand_lo(smid[r], hub_base, hub_end);
+    }
 };
 
 struct Acc {
@@ -1739,6 +1768,8 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
     if (opts.stats) *opts.stats = pb_stats{};
 
     const bool timing = ((opts.flags & PB_FLAG_TIMING) && opts.stats) || list_ms;
+    const bool copt = (opts.flags & PB_FLAG_CACHE_OPT) && in.bl.ng <= 1;
+    const uint64_t nups = copt ? 2 * in.m : in.m;  // up-slots: every slot, or one per edge
     // events: [0] start, [1] plan done, [2 + i] after list i, [2 + NLISTS] end,
     // then the hub tile's matrix-core kernel and the hub credit pass
     constexpr int NEV = NLISTS + 3;
@@ -1801,7 +1832,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
     // Hub tile candidates (one graph only): the first HUB_T vertices in rank
     // order of the rank-0 vertex's side.
     uint32_t hub_base = 0, hub_end = 0;
-    if (m > 0 && ng == 1 && opts.hub != PB_HUB_OFF && (opts.hub == PB_HUB_FORCE || m >= HUB_AUTO_MIN_M)) {
+    if (m > 0 && ng == 1 && !copt && opts.hub != PB_HUB_OFF && (opts.hub == PB_HUB_FORCE || m >= HUB_AUTO_MIN_M)) {
         const bool hub_v = hpc->top >= in.n_u;
         const uint64_t side = hub_v ? n - in.n_u : in.n_u;
         const uint32_t H = (uint32_t)std::min<uint64_t>(HUB_T, side);
@@ -1836,6 +1867,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         PB_TRY((scan_exclusive<uint32_t, uint32_t>(rdeg, roff, n, roff + n, ws)));
         hipLaunchKernelGGL(k_cend, dim3(grid_for(n)), dim3(256), 0, s, isv, n, in.n_u, ng, in.bl.rbase, in.bl.ubase,
                            in.bl.vbase, cend, gid);
+        if (copt) hipLaunchKernelGGL(k_cend_copt, dim3(grid_for(n)), dim3(256), 0, s, (const uint32_t *)smid, n, cend);
         ws.release(vbefore);
         ws.release(rdeg);
 
@@ -1872,11 +1904,18 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         PB_TRY(fill<uint32_t>(nbr + ns, 0u, NBR_PAD, s));
         hipLaunchKernelGGL(k_slots, dim3(grid_for(ns)), dim3(256), 0, s, ks, vs, ns, b, smid, roff, nbr, eslot,
                            hideg);
-        PB_TRY((scan_exclusive<uint32_t, uint32_t>(hideg, upoff, n, upoff + n, ws)));
-        uint32_t *uprun = ws.alloc<uint32_t>(m), *uplen = ws.alloc<uint32_t>(m);
+        uint32_t *uprun = ws.alloc<uint32_t>(nups), *uplen = ws.alloc<uint32_t>(nups);
         if (ws.failed) return PB_ERR_NO_MEMORY;
-        hipLaunchKernelGGL(k_upslots, dim3(grid_for(ns)), dim3(256), 0, s, ks, vs, ns, b, roff, upoff, eslot,
-                           uprun, uplen);
+        if (copt) {
+            // every slot is an up-slot: upoff is roff
+            PB_TRY_HIP(hipMemcpyAsync(upoff, roff, (n + 1) * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+            hipLaunchKernelGGL(k_upslots_copt, dim3(grid_for(ns)), dim3(256), 0, s, ks, vs, ns, b, roff,
+                               (const uint32_t *)hideg, eslot, uprun, uplen);
+        } else {
+            PB_TRY((scan_exclusive<uint32_t, uint32_t>(hideg, upoff, n, upoff + n, ws)));
+            hipLaunchKernelGGL(k_upslots, dim3(grid_for(ns)), dim3(256), 0, s, ks, vs, ns, b, roff, upoff, eslot,
+                               uprun, uplen);
+        }
         PB_TRY_HIP(hipGetLastError());
         ws.release(k0);
         ws.release(k1);
@@ -1903,17 +1942,18 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         }
 
         // 3. plan: wedges per source, bucket by distinct-endpoint bound -------
-        uint64_t *wscan = ws.alloc<uint64_t>(m + 1);
+        uint64_t *wscan = ws.alloc<uint64_t>(nups + 1);
         uint32_t *lists = ws.alloc<uint32_t>((uint64_t)NLISTS * n);
         uint32_t *nwin = ws.alloc<uint32_t>((uint64_t)NSORTED * n);
         uint64_t *wl = ws.alloc<uint64_t>((uint64_t)NSORTED * n);
         if (ws.failed) return PB_ERR_NO_MEMORY;
-        PB_TRY((scan_exclusive<uint32_t, uint64_t>(uplen, wscan, m, wscan + m, ws)));
+        PB_TRY((scan_exclusive<uint32_t, uint64_t>(uplen, wscan, nups, wscan + nups, ws)));
         hipLaunchKernelGGL(k_plan, dim3(grid_for(n, 256, PLAN_GRID)), dim3(256), 0, s, upoff, wscan, smid, cend, n,
-                           pol, hub_base, hub_end, (const unsigned long long *)hub_roww, lists, nwin, wl, pc);
+                           pol, hub_base, hub_end, (const unsigned long long *)hub_roww, lists, nwin, wl, pc,
+                           copt ? in.n_u + 1 : 0u);
         PB_TRY_HIP(hipGetLastError());
         PB_TRY_HIP(hipMemcpyAsync(hpc, pc, sizeof(PlanCounts), hipMemcpyDeviceToHost, s));
-        PB_TRY_HIP(hipMemcpyAsync(&wtotal, wscan + m, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        PB_TRY_HIP(hipMemcpyAsync(&wtotal, wscan + nups, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
         PB_TRY_HIP(hipStreamSynchronize(s));
         plan = *hpc;
         ws.release(wscan);
@@ -1948,10 +1988,10 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
                 PB_TRY((scan_exclusive<uint32_t, uint32_t>(hnw, hoff, nh, hoff + nh, ws)));
                 hipLaunchKernelGGL(k_heavy_expand, dim3(grid_for(nh)), dim3(256), 0, s, hsrc, hnw, hoff, nh, items);
             } else if (!cur && (l == L_DENSE_HEAVY || l == L_SORT_HEAVY || l == L_HASH_PACKED)) {
-                cur = ws.alloc<uint32_t>(m);
-                nxt = ws.alloc<uint32_t>(m);
-                cval = ws.alloc<uint32_t>(m);
-                nval = ws.alloc<uint32_t>(m);
+                cur = ws.alloc<uint32_t>(nups);
+                nxt = ws.alloc<uint32_t>(nups);
+                cval = ws.alloc<uint32_t>(nups);
+                nval = ws.alloc<uint32_t>(nups);
                 if (ws.failed) return PB_ERR_NO_MEMORY;
             }
             PB_TRY_HIP(hipGetLastError());
@@ -1962,7 +2002,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         // 4. count ---------------------------------------------------------------
         const bool hub_on = plan.hub.on && hub_end > hub_base;
         Ranked G{roff, nbr, upoff, uprun, uplen, smid, cend, gid, in.n_u, (uint32_t)n,
-                 hub_on ? hub_base : 0u, hub_on ? hub_end : 0u};
+                 hub_on ? hub_base : 0u, hub_on ? hub_end : 0u, copt};
         Acc A{gacc, vacc, sacc, sacc32, &pc->flags, mode};
 
         // giant sources: per-die item lists, built on the host (one extra
