@@ -218,6 +218,19 @@ __global__ void k_cend_copt(const uint32_t *smid, uint64_t n, uint32_t *cend) {
     GRID_STRIDE(r, n) cend[r] = smid[r];
 }
 
+// Byte windows: R(x1, x2) <= deg(x2), so above the largest id of a side with
+// degree >= 256 every count fits 8 bits.  from[0] / from[1] (U / V side,
+// holding the side's first id on entry) become one past that id.
+__global__ void k_byte_from(const uint32_t *rank, const uint32_t *smid, const uint32_t *deg, uint64_t n,
+                            uint32_t n_u, uint32_t *from) {
+    GRID_STRIDE(x, n) {
+        if (deg[x] >= 256) {
+            const uint32_t sm = smid[rank[x]];
+            atomicMax(&from[sm < n_u ? 0 : 1], sm + 1);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- plan
 
 // Work lists: every source with wedges goes to exactly one.
@@ -566,32 +579,46 @@ __device__ inline uint32_t probe_below(const uint32_t *nbr, uint32_t start, uint
 }
 
 // Dense counters for the candidate window [lo, lo + size); 16-bit counters
-// packed two to a word when `half`.
+// packed two to a word when `half`, 8-bit counters four to a word when `byte`
+// (used only where every count is below 256).
 template <int T>
 struct DenseAgg {
     uint32_t *w;
     uint32_t lo, size;
     bool half;
     uint32_t *err;
+    bool byte = false;
     __device__ void init() const {
-        const uint32_t words = half ? (size + 1) >> 1 : size;
+        const uint32_t words = byte ? (size + 3) >> 2 : half ? (size + 1) >> 1 : size;
         for (uint32_t i = threadIdx.x; i < words; i += T) w[i] = 0;
     }
     __device__ void insert(uint32_t x) const {
         const uint32_t d = x - lo;
         if (d >= size) { atomicOr(err, FLAG_INTERNAL); return; }
-        if (half) atomicAdd(&w[d >> 1], 1u << ((d & 1) << 4));
+        if (byte) atomicAdd(&w[d >> 2], 1u << ((d & 3) << 3));
+        else if (half) atomicAdd(&w[d >> 1], 1u << ((d & 1) << 4));
         else atomicAdd(&w[d], 1u);
     }
     __device__ bool finalize() const { return true; }
     __device__ uint32_t count(uint32_t x) const {
         const uint32_t d = x - lo;
         if (d >= size) return 1u;
+        if (byte) return (w[d >> 2] >> ((d & 3) << 3)) & 0xFFu;
         return half ? (w[d >> 1] >> ((d & 1) << 4)) & 0xFFFFu : w[d];
     }
     template <class F>
     __device__ void for_each(F f) const {
-        if (half) {
+        if (byte) {
+            for (uint32_t i = threadIdx.x; 4 * i < size; i += T) {
+                const uint32_t v = w[i];
+                if (!v) continue;
+#pragma unroll
+                for (uint32_t j = 0; j < 4; ++j) {
+                    const uint32_t c = (v >> (8 * j)) & 0xFFu;
+                    if (c) f(lo + 4 * i + j, c);
+                }
+            }
+        } else if (half) {
             for (uint32_t i = threadIdx.x; 2 * i < size; i += T) {
                 const uint32_t v = w[i];
                 if (v & 0xFFFFu) f(lo + 2 * i, v & 0xFFFFu);
@@ -1302,7 +1329,7 @@ constexpr uint64_t SHORT_RUN = 64;
 template <int T, int U>
 __global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32_t *list, const uint64_t *wsrc,
                                                    uint32_t *cur, uint32_t *nxt, uint32_t *cval, uint32_t *nval,
-                                                   uint32_t count) {
+                                                   const uint32_t *byte_from, uint32_t count) {
     constexpr uint32_t NW = T / WAVE;
     static_assert(sizeof(WaveRuns) * NW <= sizeof(RunShared<T>), "wave scratch shares the run table's LDS");
     __shared__ uint32_t words[WIN_WORDS];
@@ -1323,18 +1350,23 @@ __global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32
         const uint32_t s_start = have ? G.uprun[ks] : 0u, s_pos = have ? G.uplen[ks] : 0u;
         uint32_t s_cur = 0, s_val = s_pos ? G.nbr[s_start] : 0u;
         const uint32_t lo_min = G.lo(r);
+        // ids from here up take 8-bit counters: 4 * WIN_WORDS of them in a window
+        const uint32_t bfrom = byte_from[G.smid[r] < G.n_u ? 0 : 1];
         uint32_t hi = G.cend[r];
         bool first = true;
         __syncthreads();  // the previous source is done with the shared tables
         while (hi > lo_min) {
-            const uint32_t lo = hi - lo_min > wsz ? hi - wsz : lo_min;
-            const DenseAgg<T> agg{words, lo, hi - lo, half, A.err};
+            const bool byte = hi > bfrom;
+            const uint32_t width = byte ? 4 * WIN_WORDS : wsz;
+            uint32_t lo = hi - lo_min > width ? hi - width : lo_min;
+            if (byte && lo < bfrom) lo = bfrom;
+            const DenseAgg<T> agg{words, lo, hi - lo, half, A.err, byte};
             const CursorRange rng{cur, nxt, cval, nval, lo, first, two_pass};
             if (!waves) {
                 count_item<T, U>(G, A, r, agg, rng, sh, A.passes());
             } else {
                 {
-                    const uint32_t nwords = half ? (hi - lo + 1) >> 1 : hi - lo;
+                    const uint32_t nwords = byte ? (hi - lo + 3) >> 2 : half ? (hi - lo + 1) >> 1 : hi - lo;
                     for (uint32_t w = tid; w < nwords; w += T) words[w] = 0;
                 }
                 __syncthreads();
@@ -1841,6 +1873,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
             hub_end = hub_base + H;
         }
     }
+    uint32_t *byte_from = nullptr;
     uint32_t *hub_rank = nullptr, *hub_d = nullptr, *hub_off = nullptr;
     unsigned long long *hub_roww = nullptr;
     uint32_t hub_grid = 0;
@@ -1868,6 +1901,17 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         hipLaunchKernelGGL(k_cend, dim3(grid_for(n)), dim3(256), 0, s, isv, n, in.n_u, ng, in.bl.rbase, in.bl.ubase,
                            in.bl.vbase, cend, gid);
         if (copt) hipLaunchKernelGGL(k_cend_copt, dim3(grid_for(n)), dim3(256), 0, s, (const uint32_t *)smid, n, cend);
+        // byte windows (one graph): each side from one past its last id of degree >= 256
+        byte_from = ws.alloc<uint32_t>(2);
+        if (ws.failed) return PB_ERR_NO_MEMORY;
+        {
+            PB_TRY(fill<uint32_t>(byte_from, ng <= 1 ? 0u : (uint32_t)n, 1, s));
+            PB_TRY(fill<uint32_t>(byte_from + 1, ng <= 1 ? in.n_u : (uint32_t)n, 1, s));
+            if (ng <= 1)
+                hipLaunchKernelGGL(k_byte_from, dim3(grid_for(n)), dim3(256), 0, s, in.rank, (const uint32_t *)smid,
+                                   in.deg, n, in.n_u, byte_from);
+            PB_TRY_HIP(hipGetLastError());
+        }
         ws.release(vbefore);
         ws.release(rdeg);
 
@@ -2060,7 +2104,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
                 switch (l) {
                     case L_DENSE_HEAVY:
                         launch_items(k_count_heavy<1024, 4>, c, 1024, s, G, A, sorted_src[2], sorted_w[2], cur, nxt,
-                                     cval, nval);
+                                     cval, nval, (const uint32_t *)byte_from);
                         break;
                     case L_SORT_HEAVY:
                         launch_items(k_count_sort_heavy<256, 4, SORT_W>, c, 256, s, G, A, sorted_src[1], sorted_w[1],
