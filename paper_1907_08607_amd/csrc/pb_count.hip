@@ -218,16 +218,40 @@ __global__ void k_cend_copt(const uint32_t *smid, uint64_t n, uint32_t *cend) {
     GRID_STRIDE(r, n) cend[r] = smid[r];
 }
 
-// Byte windows: R(x1, x2) <= deg(x2), so above the largest id of a side with
-// degree >= 256 every count fits 8 bits.  from[0] / from[1] (U / V side,
-// holding the side's first id on entry) become one past that id.
-__global__ void k_byte_from(const uint32_t *rank, const uint32_t *smid, const uint32_t *deg, uint64_t n,
-                            uint32_t n_u, uint32_t *from) {
+// Narrow windows: R(x1, x2) <= deg(x2), so above the largest id of a side
+// with degree >= 256 every count fits 8 bits, and above the largest with
+// degree >= 16, 4 bits.  from[0] / from[1] (U / V side, 8-bit) and from[2] /
+// from[3] (4-bit), holding the side's first id on entry, become one past those
+// ids.
+// One atomic per workgroup and threshold: the maxima are reduced in the
+// workgroup first.
+__global__ __launch_bounds__(256) void k_byte_from(const uint32_t *rank, const uint32_t *smid, const uint32_t *deg,
+                                                   uint64_t n, uint32_t n_u, uint32_t *from) {
+    __shared__ uint32_t tmp[4][256 / WAVE];
+    uint32_t mx[4] = {0u, 0u, 0u, 0u};  // 8-bit U, 8-bit V, 4-bit U, 4-bit V
     GRID_STRIDE(x, n) {
-        if (deg[x] >= 256) {
+        const uint32_t d = deg[x];
+        if (d >= 16) {
             const uint32_t sm = smid[rank[x]];
-            atomicMax(&from[sm < n_u ? 0 : 1], sm + 1);
+            const uint32_t side = sm < n_u ? 0 : 1;
+            if (sm + 1 > mx[2 + side]) mx[2 + side] = sm + 1;
+            if (d >= 256 && sm + 1 > mx[side]) mx[side] = sm + 1;
         }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t v = mx[q];
+        for (int dd = WAVE / 2; dd >= 1; dd >>= 1) {
+            const uint32_t o = __shfl_xor(v, dd, WAVE);
+            v = o > v ? o : v;
+        }
+        if ((threadIdx.x & (WAVE - 1)) == 0) tmp[q][threadIdx.x / WAVE] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        uint32_t v = 0;
+        for (int i = 0; i < 256 / WAVE; ++i) v = tmp[threadIdx.x][i] > v ? tmp[threadIdx.x][i] : v;
+        if (v) atomicMax(&from[threadIdx.x], v);
     }
 }
 
@@ -578,56 +602,45 @@ __device__ inline uint32_t probe_below(const uint32_t *nbr, uint32_t start, uint
     return y;
 }
 
-// Dense counters for the candidate window [lo, lo + size); 16-bit counters
-// packed two to a word when `half`, 8-bit counters four to a word when `byte`
-// (used only where every count is below 256).
+// Dense counters for the candidate window [lo, lo + size), 2^cs of them to a
+// 32-bit word: 32-bit (cs 0), 16-bit (`half`, cs 1), 8-bit (`byte`, cs 2) or
+// 4-bit (`nib`, cs 3).  A narrow width is used only where every count fits it.
 template <int T>
 struct DenseAgg {
     uint32_t *w;
     uint32_t lo, size;
     bool half;
     uint32_t *err;
-    bool byte = false;
+    bool byte = false, nib = false;
+    __device__ uint32_t cs() const { return nib ? 3u : byte ? 2u : half ? 1u : 0u; }
     __device__ void init() const {
-        const uint32_t words = byte ? (size + 3) >> 2 : half ? (size + 1) >> 1 : size;
+        const uint32_t c = cs(), words = (size + (1u << c) - 1) >> c;
         for (uint32_t i = threadIdx.x; i < words; i += T) w[i] = 0;
     }
     __device__ void insert(uint32_t x) const {
         const uint32_t d = x - lo;
         if (d >= size) { atomicOr(err, FLAG_INTERNAL); return; }
-        if (byte) atomicAdd(&w[d >> 2], 1u << ((d & 3) << 3));
-        else if (half) atomicAdd(&w[d >> 1], 1u << ((d & 1) << 4));
-        else atomicAdd(&w[d], 1u);
+        const uint32_t c = cs();
+        atomicAdd(&w[d >> c], 1u << ((d & ((1u << c) - 1)) << (5 - c)));
     }
     __device__ bool finalize() const { return true; }
     __device__ uint32_t count(uint32_t x) const {
         const uint32_t d = x - lo;
         if (d >= size) return 1u;
-        if (byte) return (w[d >> 2] >> ((d & 3) << 3)) & 0xFFu;
-        return half ? (w[d >> 1] >> ((d & 1) << 4)) & 0xFFFFu : w[d];
+        const uint32_t c = cs();
+        const uint32_t v = w[d >> c] >> ((d & ((1u << c) - 1)) << (5 - c));
+        return c ? v & ((1u << (32 >> c)) - 1) : v;
     }
     template <class F>
     __device__ void for_each(F f) const {
-        if (byte) {
-            for (uint32_t i = threadIdx.x; 4 * i < size; i += T) {
-                const uint32_t v = w[i];
-                if (!v) continue;
-#pragma unroll
-                for (uint32_t j = 0; j < 4; ++j) {
-                    const uint32_t c = (v >> (8 * j)) & 0xFFu;
-                    if (c) f(lo + 4 * i + j, c);
-                }
-            }
-        } else if (half) {
-            for (uint32_t i = threadIdx.x; 2 * i < size; i += T) {
-                const uint32_t v = w[i];
-                if (v & 0xFFFFu) f(lo + 2 * i, v & 0xFFFFu);
-                if (v >> 16) f(lo + 2 * i + 1, v >> 16);
-            }
-        } else {
-            for (uint32_t i = threadIdx.x; i < size; i += T) {
-                const uint32_t c = w[i];
-                if (c) f(lo + i, c);
+        const uint32_t c = cs(), per = 1u << c, bits = 32 >> c;
+        const uint32_t mask = c ? (1u << bits) - 1 : 0xFFFFFFFFu;
+        for (uint32_t i = threadIdx.x; i * per < size; i += T) {
+            const uint32_t v = w[i];
+            if (!v) continue;
+            for (uint32_t j = 0; j < per; ++j) {
+                const uint32_t cc = (v >> (j * bits)) & mask;
+                if (cc) f(lo + i * per + j, cc);
             }
         }
     }
@@ -1350,23 +1363,26 @@ __global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32
         const uint32_t s_start = have ? G.uprun[ks] : 0u, s_pos = have ? G.uplen[ks] : 0u;
         uint32_t s_cur = 0, s_val = s_pos ? G.nbr[s_start] : 0u;
         const uint32_t lo_min = G.lo(r);
-        // ids from here up take 8-bit counters: 4 * WIN_WORDS of them in a window
-        const uint32_t bfrom = byte_from[G.smid[r] < G.n_u ? 0 : 1];
+        // ids from bfrom up take 8-bit counters (4 * WIN_WORDS in a window),
+        // from nfrom up 4-bit ones (8 * WIN_WORDS)
+        const uint32_t side = G.smid[r] < G.n_u ? 0 : 1;
+        const uint32_t bfrom = byte_from[side], nfrom = byte_from[2 + side];
         uint32_t hi = G.cend[r];
         bool first = true;
         __syncthreads();  // the previous source is done with the shared tables
         while (hi > lo_min) {
-            const bool byte = hi > bfrom;
-            const uint32_t width = byte ? 4 * WIN_WORDS : wsz;
+            const bool nib = hi > nfrom, byte = !nib && hi > bfrom;
+            const uint32_t floor_id = nib ? nfrom : bfrom;
+            const uint32_t width = nib ? 8 * WIN_WORDS : byte ? 4 * WIN_WORDS : wsz;
             uint32_t lo = hi - lo_min > width ? hi - width : lo_min;
-            if (byte && lo < bfrom) lo = bfrom;
-            const DenseAgg<T> agg{words, lo, hi - lo, half, A.err, byte};
+            if ((nib || byte) && lo < floor_id) lo = floor_id;
+            const DenseAgg<T> agg{words, lo, hi - lo, half, A.err, byte, nib};
             const CursorRange rng{cur, nxt, cval, nval, lo, first, two_pass};
             if (!waves) {
                 count_item<T, U>(G, A, r, agg, rng, sh, A.passes());
             } else {
                 {
-                    const uint32_t nwords = byte ? (hi - lo + 3) >> 2 : half ? (hi - lo + 1) >> 1 : hi - lo;
+                    const uint32_t c = agg.cs(), nwords = (hi - lo + (1u << c) - 1) >> c;
                     for (uint32_t w = tid; w < nwords; w += T) words[w] = 0;
                 }
                 __syncthreads();
@@ -1902,14 +1918,16 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
                            in.bl.vbase, cend, gid);
         if (copt) hipLaunchKernelGGL(k_cend_copt, dim3(grid_for(n)), dim3(256), 0, s, (const uint32_t *)smid, n, cend);
         // byte windows (one graph): each side from one past its last id of degree >= 256
-        byte_from = ws.alloc<uint32_t>(2);
+        byte_from = ws.alloc<uint32_t>(4);
         if (ws.failed) return PB_ERR_NO_MEMORY;
         {
-            PB_TRY(fill<uint32_t>(byte_from, ng <= 1 ? 0u : (uint32_t)n, 1, s));
-            PB_TRY(fill<uint32_t>(byte_from + 1, ng <= 1 ? in.n_u : (uint32_t)n, 1, s));
+            for (int t = 0; t < 2; ++t) {
+                PB_TRY(fill<uint32_t>(byte_from + 2 * t, ng <= 1 ? 0u : (uint32_t)n, 1, s));
+                PB_TRY(fill<uint32_t>(byte_from + 2 * t + 1, ng <= 1 ? in.n_u : (uint32_t)n, 1, s));
+            }
             if (ng <= 1)
-                hipLaunchKernelGGL(k_byte_from, dim3(grid_for(n)), dim3(256), 0, s, in.rank, (const uint32_t *)smid,
-                                   in.deg, n, in.n_u, byte_from);
+                hipLaunchKernelGGL(k_byte_from, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, in.rank,
+                                   (const uint32_t *)smid, in.deg, n, in.n_u, byte_from);
             PB_TRY_HIP(hipGetLastError());
         }
         ws.release(vbefore);
