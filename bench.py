@@ -250,7 +250,8 @@ def run_approx(args):
 def run_choose(args):
     """The ranking chooser of Section 6.2 on both single-graph workloads: W
     under side order and under each degree-like order, the metric f, the
-    choice, and the time of one choice (ranking both ways + two wedge counts).
+    choice, and the time of one choice (ranking both ways + two wedge counts);
+    also the time of the exact and approximate complement-coreness orders.
     `value` is input edges per second of the wedge count (pb_wedges) on the
     powerlaw_50m graph under degree order."""
     import argparse as _ap
@@ -262,7 +263,7 @@ def run_choose(args):
         g, desc, _ = make_graph(_ap.Namespace(**{**vars(args), "workload": w, "rank": None}))
         G = pb.Graph.from_csr(g)
         res = {}
-        for other in ("approx_degree", "degree", "approx_codeg"):
+        for other in ("approx_degree", "degree", "approx_codeg", "codeg"):
             pb.pb_rank_choose(G, other)
             t0 = time.perf_counter()
             for _ in range(args.steps):
@@ -270,6 +271,14 @@ def run_choose(args):
             ms = 1e3 * (time.perf_counter() - t0) / args.steps
             res[other] = {"chosen": chosen, "w_side": ws, "w_other": wr, "f": (ws - wr) / ws if ws else 0.0,
                           "ms_choose": ms}
+        for kind in ("codeg", "approx_codeg"):  # the two complement-coreness orders alone
+            pb.pb_rank(G, kind)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                pb.pb_rank(G, kind)
+            torch.cuda.synchronize()
+            res[f"ms_rank_{kind}"] = 1e3 * (time.perf_counter() - t0) / args.steps
         rk = pb.pb_rank(G, "degree")
         torch.cuda.synchronize()
         pb.pb_wedges(G, rk)

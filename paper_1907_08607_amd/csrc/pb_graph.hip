@@ -5,6 +5,7 @@
 // Section 3.1.1 defines the orderings built by pb_rank.
 #include "pb_internal.h"
 
+#include <cstring>
 #include <new>
 
 using namespace pb;
@@ -287,6 +288,310 @@ __global__ void k_codeg_decrement(const uint32_t *front, const uint32_t *coff, u
     }
 }
 
+// Exact complement coreness over key windows.  A window holds every live
+// vertex whose key lies in [L, H], H the largest live key, with L chosen so
+// that at most CW_CAP vertices qualify (or exactly the vertices of key H when
+// they alone are more).  Keys only fall, so until every window vertex is
+// removed or drops below L, each round's largest key and its vertices are
+// found inside the window: one workgroup runs those rounds back to back,
+// reading only the window's vertices, and hands a round back to the host
+// only when its removed vertices have more than CW_DMAX neighbours to visit.
+constexpr uint32_t CW_CAP = 4096;    // window vertices run by one workgroup
+constexpr uint32_t CW_BINS = 4096;   // keys H, H-1, ... histogrammed to choose L
+constexpr uint32_t CW_DMAX = 32768;  // neighbour visits one in-kernel round may make
+constexpr uint32_t CW_T = 1024;
+
+enum : uint32_t { CW_EXHAUSTED = 0, CW_BIG = 1 };
+
+struct CodegState {
+    uint32_t status;  // CW_EXHAUSTED or CW_BIG
+    uint32_t next;    // next rank to hand out
+    uint32_t key;     // CW_BIG: the round's key
+    uint32_t nf;      // CW_BIG: vertices the round removes
+};
+
+// hist[d] = live vertices of key H - d (d < CW_BINS), H = *best - 1.  Counts
+// are taken in LDS and added once per block.
+__global__ __launch_bounds__(256) void k_codeg_hist(const uint32_t *cur, const uint32_t *alive, uint64_t n,
+                                                    const uint32_t *best, uint32_t *hist) {
+    __shared__ uint32_t h[CW_BINS];
+    for (uint32_t i = threadIdx.x; i < CW_BINS; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    const uint32_t top = *best - 1;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+         x += (uint64_t)gridDim.x * blockDim.x)
+        if (alive[x]) {
+            const uint32_t d = top - cur[x];
+            if (d < CW_BINS) atomicAdd(&h[d], 1u);
+        }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < CW_BINS; i += blockDim.x)
+        if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// lim[0] = L: the keys H, H-1, ..., L are the longest run from the top whose
+// vertices number at most CW_CAP, or key H alone when it has more.
+__global__ __launch_bounds__(CW_T) void k_codeg_cut(const uint32_t *hist, const uint32_t *best, uint32_t *lim) {
+    constexpr uint32_t PER = CW_BINS / CW_T;
+    __shared__ uint32_t tmp[CW_T / WAVE + 1];
+    __shared__ uint32_t first_over;
+    const uint32_t top = *best - 1;
+    if (threadIdx.x == 0) first_over = CW_BINS;
+    uint32_t v[PER], sum = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) {
+        v[j] = hist[threadIdx.x * PER + j];
+        sum += v[j];
+    }
+    uint32_t total;
+    uint32_t pre = block_exclusive_sum<CW_T, uint32_t>(sum, tmp, &total);
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) {
+        pre += v[j];
+        if (pre > CW_CAP) atomicMin(&first_over, threadIdx.x * PER + j);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t bins = first_over ? first_over : 1u;  // bins 0 .. bins-1 are taken
+        if (bins > top + 1) bins = top + 1;
+        lim[0] = top + 1 - bins;
+    }
+}
+
+__global__ void k_codeg_inwin(const uint32_t *cur, const uint32_t *alive, uint64_t n, const uint32_t *lim,
+                              uint32_t *flag) {
+    const uint32_t lo = lim[0];
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+         x += (uint64_t)gridDim.x * blockDim.x)
+        flag[x] = alive[x] && cur[x] >= lo;
+}
+
+__global__ void k_codeg_gather(const uint32_t *flag, const uint32_t *pos, uint64_t n, uint32_t *win) {
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
+         x += (uint64_t)gridDim.x * blockDim.x)
+        if (flag[x]) win[pos[x]] = (uint32_t)x;
+}
+
+// Window vertices of key `key` that are still live.
+__global__ void k_codeg_wflags(const uint32_t *win, uint32_t nw, uint32_t key, const uint32_t *cur,
+                               const uint32_t *alive, uint32_t *flag) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += gridDim.x * blockDim.x) {
+        const uint32_t x = win[i];
+        flag[i] = alive[x] && cur[x] == key;
+    }
+}
+
+// Ranks in window order (= id order); `all` takes every window vertex.
+__global__ void k_codeg_wassign(const uint32_t *win, const uint32_t *flag, const uint32_t *pos, uint32_t nw,
+                                bool all, uint32_t next, uint32_t *alive, uint32_t *rank, uint32_t *front) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += gridDim.x * blockDim.x)
+        if (all || flag[i]) {
+            const uint32_t x = win[i], p = all ? i : pos[i];
+            rank[x] = next + p;
+            front[p] = x;
+            alive[x] = 0;
+        }
+}
+
+// The rounds of one window (at most CW_CAP vertices, ids increasing).  Each
+// round: the largest live key M among the window's vertices; if M < L the
+// window is exhausted.  Its vertices take the next ranks in id order, and
+// every neighbour of theirs loses one.  A removed vertex's key is never read
+// again, so its neighbours are dropped without a liveness test.
+__global__ __launch_bounds__(CW_T) void k_codeg_window(const uint32_t *win, uint32_t nw, uint32_t lo, uint32_t next,
+                                                       const uint32_t *deg, const int64_t *u_off,
+                                                       const uint32_t *u_adj, const uint32_t *v_off,
+                                                       const uint32_t *v_adj, uint32_t n_u, uint32_t *cur,
+                                                       uint32_t *alive, uint32_t *rank, CodegState *st) {
+    constexpr uint32_t PER = CW_CAP / CW_T;
+    __shared__ uint32_t fv[CW_CAP];
+    __shared__ unsigned long long foff[CW_CAP + 1];
+    __shared__ uint32_t tmp32[CW_T / WAVE + 1];
+    __shared__ unsigned long long tmp64[CW_T / WAVE + 1];
+    __shared__ uint32_t wmax[CW_T / WAVE];
+    const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1);
+    uint32_t ids[PER], dg[PER];
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) {
+        const uint32_t i = tid * PER + j;
+        ids[j] = i < nw ? win[i] : 0u;
+        dg[j] = i < nw ? deg[ids[j]] : 0u;
+    }
+    for (;;) {
+        uint32_t key[PER], best = 0;  // key + 1, 0 = removed or not a window slot
+#pragma unroll
+        for (uint32_t j = 0; j < PER; ++j) {
+            key[j] = tid * PER + j < nw && alive[ids[j]] ? cur[ids[j]] + 1 : 0u;
+            best = key[j] > best ? key[j] : best;
+        }
+        for (int d = WAVE / 2; d >= 1; d >>= 1) {
+            const uint32_t o = __shfl_xor(best, d, WAVE);
+            best = o > best ? o : best;
+        }
+        if (lane == 0) wmax[tid / WAVE] = best;
+        __syncthreads();
+        best = 0;
+        for (uint32_t w = 0; w < CW_T / WAVE; ++w) best = wmax[w] > best ? wmax[w] : best;
+        if (best == 0 || best - 1 < lo) {
+            if (tid == 0) {
+                st->status = CW_EXHAUSTED;
+                st->next = next;
+            }
+            return;
+        }
+        uint32_t f = 0;
+        unsigned long long sd = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < PER; ++j)
+            if (key[j] == best) {
+                ++f;
+                sd += dg[j];
+            }
+        uint32_t nf;
+        unsigned long long sum;
+        uint32_t fp = block_exclusive_sum<CW_T, uint32_t>(f, tmp32, &nf);
+        unsigned long long sp = block_exclusive_sum<CW_T, unsigned long long>(sd, tmp64, &sum);
+        if (sum > CW_DMAX) {
+            if (tid == 0) {
+                st->status = CW_BIG;
+                st->next = next;
+                st->key = best - 1;
+                st->nf = nf;
+            }
+            return;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < PER; ++j)
+            if (key[j] == best) {
+                rank[ids[j]] = next + fp;
+                alive[ids[j]] = 0;
+                fv[fp] = ids[j];
+                foff[fp] = sp;
+                ++fp;
+                sp += dg[j];
+            }
+        if (tid == 0) foff[nf] = sum;
+        __syncthreads();
+        // visit q of the flat neighbour sequence: front vertex p with
+        // foff[p] <= q < foff[p + 1]
+        const uint32_t total = (uint32_t)sum;
+        for (uint32_t q = tid; q < total; q += CW_T) {
+            uint32_t a = 0, b = nf;
+            while (b - a > 1) {
+                const uint32_t mid = (a + b) >> 1;
+                if (foff[mid] <= q) a = mid; else b = mid;
+            }
+            const uint32_t x = fv[a], k = q - (uint32_t)foff[a];
+            const uint32_t y = x < n_u ? n_u + u_adj[u_off[x] + k] : v_adj[v_off[x - n_u] + k];
+            atomicSub(&cur[y], 1u);
+        }
+        // the decrements and removals are complete and visible (L1 bypassed
+        // by the fence) before the next round reads keys
+        __threadfence();
+        __syncthreads();
+        next += nf;
+    }
+}
+
+pb_status rank_codeg_exact(pb_graph *g, uint32_t *rank, hipStream_t s) {
+    const uint64_t n = (uint64_t)g->n_u + g->n_v;
+    Workspace ws(s, 0);
+    uint32_t *cur = ws.alloc<uint32_t>(n), *alive = ws.alloc<uint32_t>(n);
+    uint32_t *flag = ws.alloc<uint32_t>(n), *pos = ws.alloc<uint32_t>(n + 1);
+    uint32_t *win = ws.alloc<uint32_t>(n), *front = ws.alloc<uint32_t>(n);
+    uint32_t *ccnt = ws.alloc<uint32_t>(n + 1), *coff = ws.alloc<uint32_t>(n + 1);
+    uint32_t *best = ws.alloc<uint32_t>(2), *hist = ws.alloc<uint32_t>(CW_BINS);
+    CodegState *st = ws.alloc<CodegState>(1);
+    uint32_t *lim = best + 1;
+    if (ws.failed) return PB_ERR_NO_MEMORY;
+    uint32_t *host = nullptr;  // [0] = window size, [1..4] = state
+    PB_TRY_HIP(hipHostMalloc((void **)&host, 8 * sizeof(uint32_t), hipHostMallocDefault));
+    pb_status rc = PB_OK;
+    const auto sync_read = [&](void *dst, const void *src, size_t bytes) {
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s) == hipSuccess &&
+               hipStreamSynchronize(s) == hipSuccess;
+    };
+    // removes the `nf` vertices in front[0, nf): their live neighbours lose one
+    const auto drop_front = [&](uint32_t nf) -> pb_status {
+        hipLaunchKernelGGL(k_codeg_small, dim3(grid_for(nf)), dim3(256), 0, s, (const uint32_t *)front, nf,
+                           (const uint32_t *)g->deg, g->u_off, g->u_adj, g->v_off, g->v_adj, g->n_u,
+                           (const uint32_t *)alive, cur, ccnt);
+        PB_TRY((scan_exclusive<uint32_t, uint32_t>(ccnt, coff, nf, coff + nf, ws)));
+        hipLaunchKernelGGL(k_codeg_decrement, dim3(DEC_GRID), dim3(256), 0, s, (const uint32_t *)front,
+                           (const uint32_t *)coff, nf, g->u_off, g->u_adj, g->v_off, g->v_adj, g->n_u,
+                           (const uint32_t *)alive, cur);
+        PB_TRY_HIP(hipGetLastError());
+        return PB_OK;
+    };
+    do {
+        if (hipMemcpyAsync(cur, g->deg, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s) != hipSuccess) {
+            rc = PB_ERR_HIP;
+            break;
+        }
+        if ((rc = fill<uint32_t>(alive, 1u, n, s)) != PB_OK) break;
+        uint32_t next = 0;
+        while (next < n && rc == PB_OK) {
+            // the window: largest live key H, cut L, live vertices of key >= L
+            if ((rc = fill<uint32_t>(best, 0u, 1, s)) != PB_OK) break;
+            if ((rc = fill<uint32_t>(hist, 0u, CW_BINS, s)) != PB_OK) break;
+            hipLaunchKernelGGL(k_codeg_max, dim3(grid_for(n, 256, CODEG_MAX_GRID)), dim3(256), 0, s, cur, alive, n,
+                               0, best);
+            hipLaunchKernelGGL(k_codeg_hist, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, cur, alive, n,
+                               (const uint32_t *)best, hist);
+            hipLaunchKernelGGL(k_codeg_cut, dim3(1), dim3(CW_T), 0, s, (const uint32_t *)hist,
+                               (const uint32_t *)best, lim);
+            hipLaunchKernelGGL(k_codeg_inwin, dim3(grid_for(n)), dim3(256), 0, s, cur, alive, n,
+                               (const uint32_t *)lim, flag);
+            if ((rc = scan_exclusive<uint32_t, uint32_t>(flag, pos, n, pos + n, ws)) != PB_OK) break;
+            hipLaunchKernelGGL(k_codeg_gather, dim3(grid_for(n)), dim3(256), 0, s, (const uint32_t *)flag,
+                               (const uint32_t *)pos, n, win);
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(host + 1, lim, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                !sync_read(host, pos + n, sizeof(uint32_t))) {
+                rc = PB_ERR_HIP;
+                break;
+            }
+            const uint32_t nw = host[0], lo = host[1];
+            if (nw == 0) { rc = PB_ERR_HIP; break; }  // cannot happen while vertices remain
+            if (nw > CW_CAP) {
+                // only key H's vertices: one round removes them all
+                hipLaunchKernelGGL(k_codeg_wassign, dim3(grid_for(nw)), dim3(256), 0, s, (const uint32_t *)win,
+                                   (const uint32_t *)flag, (const uint32_t *)pos, nw, true, next, alive, rank,
+                                   front);
+                if ((rc = drop_front(nw)) != PB_OK) break;
+                next += nw;
+                continue;
+            }
+            for (;;) {
+                hipLaunchKernelGGL(k_codeg_window, dim3(1), dim3(CW_T), 0, s, (const uint32_t *)win, nw, lo, next,
+                                   (const uint32_t *)g->deg, g->u_off, g->u_adj, g->v_off, g->v_adj, g->n_u, cur,
+                                   alive, rank, st);
+                if (hipGetLastError() != hipSuccess || !sync_read(host + 4, st, sizeof(CodegState))) {
+                    rc = PB_ERR_HIP;
+                    break;
+                }
+                CodegState h;
+                memcpy(&h, host + 4, sizeof(h));
+                next = h.next;
+                if (h.status == CW_EXHAUSTED) break;
+                if (h.status != CW_BIG || h.nf == 0) { rc = PB_ERR_HIP; break; }  // a round removes someone
+                // a round with many neighbours to visit: all workgroups
+                hipLaunchKernelGGL(k_codeg_wflags, dim3(grid_for(nw)), dim3(256), 0, s, (const uint32_t *)win, nw,
+                                   h.key, (const uint32_t *)cur, (const uint32_t *)alive, flag);
+                if ((rc = scan_exclusive<uint32_t, uint32_t>(flag, pos, nw, pos + nw, ws)) != PB_OK) break;
+                hipLaunchKernelGGL(k_codeg_wassign, dim3(grid_for(nw)), dim3(256), 0, s, (const uint32_t *)win,
+                                   (const uint32_t *)flag, (const uint32_t *)pos, nw, false, next, alive, rank,
+                                   front);
+                if ((rc = drop_front(h.nf)) != PB_OK) break;
+                next += h.nf;
+            }
+        }
+    } while (0);
+    (void)hipStreamSynchronize(s);
+    (void)hipHostFree(host);
+    return rc;
+}
+
 pb_status rank_codeg(pb_graph *g, bool approx, uint32_t *rank, hipStream_t s) {
     const uint64_t n = (uint64_t)g->n_u + g->n_v;
     Workspace ws(s, 0);
@@ -502,7 +807,7 @@ pb_status pb_rank(pb_graph *g, pb_rank_kind kind, uint32_t *rank, hipStream_t s)
             return PB_OK;
         }
         case PB_RANK_COMPLEMENT_CORENESS:
-            return rank_codeg(g, false, rank, s);
+            return rank_codeg_exact(g, rank, s);
         case PB_RANK_APPROX_COMPLEMENT_CORENESS:
             return rank_codeg(g, true, rank, s);
     }

@@ -5,8 +5,11 @@ here comes from the GPU library.  For each workload it records the CSR hash
 (so a test can confirm it regenerated the same graph), the butterfly total,
 SHA-256 digests of the per-vertex and per-edge int64 arrays (little endian),
 the wedge count of the workload's ordering, and a sample of single values.
+With --codeg it records instead the digest of the exact complement-coreness
+ordering of each workload's graph (codeg_<name>.json).
 
     python tests/golden/make_golden.py powerlaw_50m hub_100m
+    python tests/golden/make_golden.py --codeg powerlaw_50m hub_100m
 """
 import hashlib
 import json
@@ -61,7 +64,27 @@ def make(name: str) -> dict:
     }
 
 
+def make_codeg(name: str) -> dict:
+    make_graph, _, desc = WORKLOADS[name]
+    g = make_graph()
+    t = time.time()
+    rank = oracle.rank(g, "codeg")
+    print(f"{name}: complement coreness in {time.time() - t:.1f}s", flush=True)
+    return {
+        "workload": name, "description": desc, "csr_sha256": g.sha256(), "rank": "codeg",
+        "rank_sha256": digest(rank.astype(np.int64)),
+        "made_by": "tests/golden/make_golden.py --codeg (oracle/orc_rank)",
+    }
+
+
 if __name__ == "__main__":
+    if sys.argv[1:2] == ["--codeg"]:
+        for name in sys.argv[2:] or list(WORKLOADS):
+            d = make_codeg(name)
+            with open(os.path.join(HERE, f"codeg_{name}.json"), "w") as f:
+                json.dump(d, f, indent=1)
+            print(json.dumps({k: d[k] for k in ("workload", "rank_sha256")}), flush=True)
+        sys.exit(0)
     for name in sys.argv[1:] or list(WORKLOADS):
         d = make(name)
         with open(os.path.join(HERE, f"{name}.json"), "w") as f:

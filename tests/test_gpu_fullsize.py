@@ -62,3 +62,22 @@ def test_full_size_workload(name):
     assert digest(v) == want["vertex_sha256"]
     assert digest(e) == want["edge_sha256"]
     G.close()
+
+
+@pytest.mark.parametrize("name", sorted(MAKERS))
+def test_full_size_codeg_rank(name):
+    """The exact complement-coreness ordering of the full graph (thousands of
+    rounds) against the oracle's digest of it."""
+    path = os.path.join(GOLDEN, f"codeg_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"codeg_{name}.json not generated")
+    with open(path) as f:
+        want = json.load(f)
+    g = MAKERS[name]()
+    assert g.sha256() == want["csr_sha256"], "generator produced a different graph"
+    G = pb.Graph.from_csr(g)
+    rank = pb.pb_rank(G, "codeg")
+    torch.cuda.synchronize()
+    r = rank.cpu().numpy().view(np.uint32)
+    assert digest(r.astype(np.int64)) == want["rank_sha256"], "ordering differs from the reference"
+    G.close()
