@@ -298,8 +298,9 @@ __global__ void k_codeg_decrement(const uint32_t *front, const uint32_t *coff, u
 // only when its removed vertices have more than CW_DMAX neighbours to visit.
 constexpr uint32_t CW_CAP = 4096;    // window vertices run by one workgroup
 constexpr uint32_t CW_BINS = 4096;   // keys H, H-1, ... histogrammed to choose L
-constexpr uint32_t CW_DMAX = 32768;  // neighbour visits one in-kernel round may make
+constexpr uint32_t CW_DMAX = 16384;  // neighbour visits one in-kernel round may make
 constexpr uint32_t CW_T = 1024;
+constexpr uint32_t CW_U = 4;        // neighbour loads in flight per thread
 
 enum : uint32_t { CW_EXHAUSTED = 0, CW_BIG = 1 };
 
@@ -307,7 +308,7 @@ struct CodegState {
     uint32_t status;  // CW_EXHAUSTED or CW_BIG
     uint32_t next;    // next rank to hand out
     uint32_t key;     // CW_BIG: the round's key
-    uint32_t nf;      // CW_BIG: vertices the round removes
+    uint32_t nf;      // CW_BIG: vertices the round removed (ranked, in front[0, nf))
 };
 
 // hist[d] = live vertices of key H - d (d < CW_BINS), H = *best - 1.  Counts
@@ -372,25 +373,16 @@ __global__ void k_codeg_gather(const uint32_t *flag, const uint32_t *pos, uint64
         if (flag[x]) win[pos[x]] = (uint32_t)x;
 }
 
-// Window vertices of key `key` that are still live.
-__global__ void k_codeg_wflags(const uint32_t *win, uint32_t nw, uint32_t key, const uint32_t *cur,
-                               const uint32_t *alive, uint32_t *flag) {
+// A window of one key (more vertices than one workgroup takes): every
+// window vertex is removed, ranked in window order (= id order).
+__global__ void k_codeg_wtake(const uint32_t *win, uint32_t nw, uint32_t next, uint32_t *alive, uint32_t *rank,
+                              uint32_t *front) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += gridDim.x * blockDim.x) {
         const uint32_t x = win[i];
-        flag[i] = alive[x] && cur[x] == key;
+        rank[x] = next + i;
+        front[i] = x;
+        alive[x] = 0;
     }
-}
-
-// Ranks in window order (= id order); `all` takes every window vertex.
-__global__ void k_codeg_wassign(const uint32_t *win, const uint32_t *flag, const uint32_t *pos, uint32_t nw,
-                                bool all, uint32_t next, uint32_t *alive, uint32_t *rank, uint32_t *front) {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += gridDim.x * blockDim.x)
-        if (all || flag[i]) {
-            const uint32_t x = win[i], p = all ? i : pos[i];
-            rank[x] = next + p;
-            front[p] = x;
-            alive[x] = 0;
-        }
 }
 
 // The rounds of one window (at most CW_CAP vertices, ids increasing).  Each
@@ -398,30 +390,50 @@ __global__ void k_codeg_wassign(const uint32_t *win, const uint32_t *flag, const
 // window is exhausted.  Its vertices take the next ranks in id order, and
 // every neighbour of theirs loses one.  A removed vertex's key is never read
 // again, so its neighbours are dropped without a liveness test.
+//
+// The whole window lives on one CU, so the waves only need each other's
+// writes to have reached L2 (a full wait before the barrier) and read keys
+// and liveness from L2 (relaxed atomic loads, which miss L1); no device-wide
+// fence is needed between rounds.
+__device__ inline uint32_t l2_load(const uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ __launch_bounds__(CW_T) void k_codeg_window(const uint32_t *win, uint32_t nw, uint32_t lo, uint32_t next,
                                                        const uint32_t *deg, const int64_t *u_off,
                                                        const uint32_t *u_adj, const uint32_t *v_off,
                                                        const uint32_t *v_adj, uint32_t n_u, uint32_t *cur,
-                                                       uint32_t *alive, uint32_t *rank, CodegState *st) {
+                                                       uint32_t *alive, uint32_t *rank, uint32_t *front,
+                                                       CodegState *st) {
     constexpr uint32_t PER = CW_CAP / CW_T;
-    __shared__ uint32_t fv[CW_CAP];
-    __shared__ unsigned long long foff[CW_CAP + 1];
+    __shared__ uint32_t fv[CW_CAP];                   // the round's vertices
+    __shared__ uint32_t foff[CW_CAP + 1];             // their offsets in the flat neighbour sequence
+    __shared__ unsigned long long fadj[CW_CAP];       // where their neighbour lists start
     __shared__ uint32_t tmp32[CW_T / WAVE + 1];
     __shared__ unsigned long long tmp64[CW_T / WAVE + 1];
     __shared__ uint32_t wmax[CW_T / WAVE];
     const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1);
     uint32_t ids[PER], dg[PER];
+    unsigned long long at0[PER];
+    bool slot[PER];
 #pragma unroll
     for (uint32_t j = 0; j < PER; ++j) {
         const uint32_t i = tid * PER + j;
-        ids[j] = i < nw ? win[i] : 0u;
-        dg[j] = i < nw ? deg[ids[j]] : 0u;
+        slot[j] = i < nw;
+        ids[j] = slot[j] ? win[i] : win[0];  // a valid id, never used as a window vertex
+        dg[j] = slot[j] ? deg[ids[j]] : 0u;
+        at0[j] = ids[j] < n_u ? (unsigned long long)u_off[ids[j]] : (unsigned long long)v_off[ids[j] - n_u];
     }
     for (;;) {
-        uint32_t key[PER], best = 0;  // key + 1, 0 = removed or not a window slot
+        uint32_t av[PER], cv[PER], key[PER], best = 0;  // key + 1, 0 = removed or not a window slot
 #pragma unroll
         for (uint32_t j = 0; j < PER; ++j) {
-            key[j] = tid * PER + j < nw && alive[ids[j]] ? cur[ids[j]] + 1 : 0u;
+            av[j] = l2_load(&alive[ids[j]]);
+            cv[j] = l2_load(&cur[ids[j]]);
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < PER; ++j) {
+            key[j] = slot[j] && av[j] ? cv[j] + 1 : 0u;
             best = key[j] > best ? key[j] : best;
         }
         for (int d = WAVE / 2; d >= 1; d >>= 1) {
@@ -452,9 +464,18 @@ __global__ __launch_bounds__(CW_T) void k_codeg_window(const uint32_t *win, uint
         uint32_t fp = block_exclusive_sum<CW_T, uint32_t>(f, tmp32, &nf);
         unsigned long long sp = block_exclusive_sum<CW_T, unsigned long long>(sd, tmp64, &sum);
         if (sum > CW_DMAX) {
+            // ranked here; the neighbours are dropped by all workgroups
+#pragma unroll
+            for (uint32_t j = 0; j < PER; ++j)
+                if (key[j] == best) {
+                    rank[ids[j]] = next + fp;
+                    alive[ids[j]] = 0;
+                    front[fp] = ids[j];
+                    ++fp;
+                }
             if (tid == 0) {
                 st->status = CW_BIG;
-                st->next = next;
+                st->next = next + nf;
                 st->key = best - 1;
                 st->nf = nf;
             }
@@ -466,28 +487,46 @@ __global__ __launch_bounds__(CW_T) void k_codeg_window(const uint32_t *win, uint
                 rank[ids[j]] = next + fp;
                 alive[ids[j]] = 0;
                 fv[fp] = ids[j];
-                foff[fp] = sp;
+                foff[fp] = (uint32_t)sp;
+                fadj[fp] = at0[j];
                 ++fp;
                 sp += dg[j];
             }
-        if (tid == 0) foff[nf] = sum;
+        if (tid == 0) foff[nf] = (uint32_t)sum;
         __syncthreads();
-        // visit q of the flat neighbour sequence: front vertex p with
-        // foff[p] <= q < foff[p + 1]
+        // visit q of the flat neighbour sequence: front vertex p, the largest
+        // with foff[p] <= q, found by a fixed number of halving steps so that
+        // a thread's CW_U searches and loads proceed side by side
         const uint32_t total = (uint32_t)sum;
-        for (uint32_t q = tid; q < total; q += CW_T) {
-            uint32_t a = 0, b = nf;
-            while (b - a > 1) {
-                const uint32_t mid = (a + b) >> 1;
-                if (foff[mid] <= q) a = mid; else b = mid;
+        uint32_t lg = 0;
+        while ((1u << lg) < nf) ++lg;
+        for (uint32_t q0 = tid; q0 < total; q0 += CW_U * CW_T) {
+            uint32_t q[CW_U], pa[CW_U], y[CW_U];
+#pragma unroll
+            for (uint32_t u = 0; u < CW_U; ++u) {
+                const uint32_t qq = q0 + u * CW_T;
+                q[u] = qq < total ? qq : total - 1;
+                pa[u] = 0;
             }
-            const uint32_t x = fv[a], k = q - (uint32_t)foff[a];
-            const uint32_t y = x < n_u ? n_u + u_adj[u_off[x] + k] : v_adj[v_off[x - n_u] + k];
-            atomicSub(&cur[y], 1u);
+            for (uint32_t sh = lg; sh-- > 0;) {
+#pragma unroll
+                for (uint32_t u = 0; u < CW_U; ++u) {
+                    const uint32_t c = pa[u] + (1u << sh);
+                    if (c < nf && foff[c] <= q[u]) pa[u] = c;
+                }
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < CW_U; ++u) {
+                const bool us = fv[pa[u]] < n_u;
+                const unsigned long long at = fadj[pa[u]] + (q[u] - foff[pa[u]]);
+                const uint32_t *src = us ? u_adj + at : v_adj + at;
+                y[u] = *src + (us ? n_u : 0u);
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < CW_U; ++u)
+                if (q0 + u * CW_T < total) atomicSub(&cur[y[u]], 1u);
         }
-        // the decrements and removals are complete and visible (L1 bypassed
-        // by the fence) before the next round reads keys
-        __threadfence();
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's removals and decrements have reached L2
         __syncthreads();
         next += nf;
     }
@@ -555,9 +594,8 @@ pb_status rank_codeg_exact(pb_graph *g, uint32_t *rank, hipStream_t s) {
             if (nw == 0) { rc = PB_ERR_HIP; break; }  // cannot happen while vertices remain
             if (nw > CW_CAP) {
                 // only key H's vertices: one round removes them all
-                hipLaunchKernelGGL(k_codeg_wassign, dim3(grid_for(nw)), dim3(256), 0, s, (const uint32_t *)win,
-                                   (const uint32_t *)flag, (const uint32_t *)pos, nw, true, next, alive, rank,
-                                   front);
+                hipLaunchKernelGGL(k_codeg_wtake, dim3(grid_for(nw)), dim3(256), 0, s, (const uint32_t *)win, nw,
+                                   next, alive, rank, front);
                 if ((rc = drop_front(nw)) != PB_OK) break;
                 next += nw;
                 continue;
@@ -565,7 +603,7 @@ pb_status rank_codeg_exact(pb_graph *g, uint32_t *rank, hipStream_t s) {
             for (;;) {
                 hipLaunchKernelGGL(k_codeg_window, dim3(1), dim3(CW_T), 0, s, (const uint32_t *)win, nw, lo, next,
                                    (const uint32_t *)g->deg, g->u_off, g->u_adj, g->v_off, g->v_adj, g->n_u, cur,
-                                   alive, rank, st);
+                                   alive, rank, front, st);
                 if (hipGetLastError() != hipSuccess || !sync_read(host + 4, st, sizeof(CodegState))) {
                     rc = PB_ERR_HIP;
                     break;
@@ -575,15 +613,9 @@ pb_status rank_codeg_exact(pb_graph *g, uint32_t *rank, hipStream_t s) {
                 next = h.next;
                 if (h.status == CW_EXHAUSTED) break;
                 if (h.status != CW_BIG || h.nf == 0) { rc = PB_ERR_HIP; break; }  // a round removes someone
-                // a round with many neighbours to visit: all workgroups
-                hipLaunchKernelGGL(k_codeg_wflags, dim3(grid_for(nw)), dim3(256), 0, s, (const uint32_t *)win, nw,
-                                   h.key, (const uint32_t *)cur, (const uint32_t *)alive, flag);
-                if ((rc = scan_exclusive<uint32_t, uint32_t>(flag, pos, nw, pos + nw, ws)) != PB_OK) break;
-                hipLaunchKernelGGL(k_codeg_wassign, dim3(grid_for(nw)), dim3(256), 0, s, (const uint32_t *)win,
-                                   (const uint32_t *)flag, (const uint32_t *)pos, nw, false, next, alive, rank,
-                                   front);
+                // a round with many neighbours to visit: ranked by the window
+                // kernel, its neighbours dropped by all workgroups
                 if ((rc = drop_front(h.nf)) != PB_OK) break;
-                next += h.nf;
             }
         }
     } while (0);

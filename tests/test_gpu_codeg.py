@@ -5,7 +5,7 @@ take the next ranks in id order.
 
 The GPU path works in key windows: the live vertices whose keys lie in the top
 run of keys holding at most 4096 vertices.  One workgroup runs the rounds
-inside a window; a round whose removed vertices have more than 32768
+inside a window; a round whose removed vertices have more than 16384
 neighbours to visit, and a window that is one key of more than 4096 vertices,
 run on all workgroups.  The graphs below reach each of these cases:
   * the power law at 1/50 size: several windows, the last one key 1 of more
