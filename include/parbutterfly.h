@@ -217,8 +217,12 @@ void pb_graph_destroy(pb_graph *g);
 
 /* Writes a vertex ordering of kind `kind` (Section 3.1.1, see pb_rank_kind):
  * rank_out[x] for every unified id x (device, n_u + n_v entries).
- * Synchronises `stream` (once for the side and degree orders, once per
- * removal round for the complement-coreness orders).
+ * Synchronises `stream`: once for the side and degree orders; once per
+ * removal round for the approximate complement-coreness order; for the exact
+ * one, once per key window (the live vertices of the top keys, at most 4096
+ * unless one key alone has more) and once per round whose removed vertices
+ * have more than 16384 neighbours, the other rounds running back to back on
+ * the device.
  * Errors: INVALID_ARG, NO_MEMORY, HIP. */
 pb_status pb_rank(pb_graph *g, pb_rank_kind kind, uint32_t *rank_out, hipStream_t stream);
 
