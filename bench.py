@@ -123,6 +123,21 @@ def make_graph(args):
     return g, desc, rank
 
 
+def host_info():
+    """The host the oracle was timed on: the cores this process may use (what
+    `nproc` prints) and the CPU model."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"host_nproc": len(os.sched_getaffinity(0)), "host_cpu": model}
+
+
 def cpu_baseline(g, wedges, target_s):
     """The oracle (single thread) on every k-th endpoint, scaled by k."""
     import numpy as np
@@ -142,7 +157,7 @@ def cpu_baseline(g, wedges, target_s):
         stride = max(1, int(round(t * stride / target_s)))
         t = oracle.count_sample(g, stride)
     est = t * stride
-    return {"value": wedges / est, "unit": "wedges/s", "cores": 1, "kind": "oracle",
+    return {"value": wedges / est, "unit": "wedges/s", "cores": 1, "kind": "oracle", **host_info(),
             "sample": f"oracle dense 2-hop counter (global+vertex+edge) on every {stride}-th endpoint "
                       f"of its endpoint side: {t:.1f} s measured, x{stride} = {est:.1f} s estimated full run; "
                       f"wedges = the GPU ordering's wedge count",
@@ -241,7 +256,7 @@ def run_approx(args):
         t0 = time.perf_counter()
         oracle.count_approx(g, "edge", args.p, 2000)
         dt = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+        line["cpu_baseline"] = {"value": m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle", **host_info(),
                                 "sample": f"one edge-sparsification estimate at p={args.p} "
                                           f"(sparsify + dense 2-hop count of the kept graph): {dt:.1f} s"}
     print(json.dumps(line), flush=True)
@@ -341,7 +356,7 @@ def run_tip(args):
         want, want_rounds = oracle.tip(g, side)
         dt = time.perf_counter() - t0
         line["config"]["same_as_oracle"] = bool(np.array_equal(want, t)) and want_rounds == rounds
-        line["cpu_baseline"] = {"value": g.m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+        line["cpu_baseline"] = {"value": g.m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle", **host_info(),
                                 "sample": f"the whole decomposition of the same graph: {dt:.1f} s"}
     print(json.dumps(line), flush=True)
 
@@ -384,7 +399,7 @@ def run_wing(args):
         want, want_rounds = oracle.wing(g)
         dt = time.perf_counter() - t0
         line["config"]["same_as_oracle"] = bool(np.array_equal(want, w)) and want_rounds == rounds
-        line["cpu_baseline"] = {"value": g.m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+        line["cpu_baseline"] = {"value": g.m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle", **host_info(),
                                 "sample": f"the whole decomposition of the same graph: {dt:.1f} s"}
     print(json.dumps(line), flush=True)
 
@@ -457,7 +472,7 @@ def run_batch(args):
             done += 1
             if t_cpu >= args.cpu_target_s:
                 break
-        record["cpu_baseline"] = {"value": done / t_cpu, "unit": "graphs/s", "cores": 1, "kind": "oracle",
+        record["cpu_baseline"] = {"value": done / t_cpu, "unit": "graphs/s", "cores": 1, "kind": "oracle", **host_info(),
                                   "sample": f"oracle dense 2-hop counter (per-edge) on the first {done} of the "
                                             f"{len(graphs)} graphs, one after another: {t_cpu:.1f} s"}
     print(json.dumps(record), flush=True)
@@ -658,7 +673,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle sample on the host", file=sys.stderr, flush=True)
         cb = cpu_baseline(g, wedges, args.cpu_target_s)
-        record["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        record["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample", "host_nproc", "host_cpu")}
     print(json.dumps(record), flush=True)
 
 
