@@ -14,7 +14,10 @@
 // binary search), so a vertex with long lists spreads over all the threads.
 // The first walk counts c(u1, u2) with atomic adds, the second takes each
 // count with an atomic exchange (which also clears the slice for the next
-// vertex) and subtracts C(c, 2) from B(u2) once per u2.
+// vertex) and subtracts C(c, 2) from B(u2) once per u2.  Most rounds peel one
+// or a few vertices, which would leave all but a few workgroups idle; a round
+// of at most PEEL_FEW vertices is instead spread over the whole GPU, one
+// neighbour list of the 2-hop walk per wave, its two walks in two launches.
 //
 // The round state (k, the round's minimum, vertices left, rounds) stays on
 // the device, so rounds are queued in batches with one host synchronisation
@@ -29,6 +32,8 @@ constexpr uint32_t PEEL_T = 1024;                      // threads per workgroup 
 constexpr uint32_t PEEL_MAX_GRID = 256;                // update workgroups (counter slices) at most
 constexpr uint64_t PEEL_SCRATCH = uint64_t(1) << 32;  // bytes of counter slices at most
 constexpr uint32_t PEEL_BATCH = 64;                    // rounds queued per host synchronisation
+constexpr uint32_t PEEL_FEW = 8;                       // rounds of at most this many vertices spread over the GPU
+constexpr uint32_t SPREAD_GRID = 2048;                 // workgroups of the spread update (256 threads each)
 
 struct PeelState {
     int64_t k;                 // the level reached by the previous rounds
@@ -113,13 +118,14 @@ __global__ void k_peel_close(const uint32_t *nfront, PeelState *st) {
 // UPDATE-V: one workgroup per peeled vertex (see the file comment).  `cnt`
 // holds gridDim.x slices of nx words, all zero on entry and on exit.
 __global__ __launch_bounds__(PEEL_T) void k_peel_update(Side S, const uint32_t *front, const uint32_t *nfront,
-                                                        const uint32_t *gone, uint32_t *cnt, int64_t *b) {
+                                                        const uint32_t *gone, uint32_t few, uint32_t *cnt, int64_t *b) {
     __shared__ uint32_t s_off[PEEL_T];  // flat start of each list of the chunk
     __shared__ uint32_t s_y0[PEEL_T];   // first entry of each list
     __shared__ uint32_t s_tmp[PEEL_T / WAVE + 1];
     const uint32_t t = threadIdx.x;
     uint32_t *c = cnt + (uint64_t)blockIdx.x * S.nx;
     const uint32_t nf = *nfront;
+    if (nf <= few) return;  // k_peel_spread takes the round
     for (uint32_t i = blockIdx.x; i < nf; i += gridDim.x) {
         const uint32_t u1 = front[i];
         const uint64_t p0 = S.xb(u1), p1 = S.xb(u1 + 1);
@@ -157,6 +163,52 @@ __global__ __launch_bounds__(PEEL_T) void k_peel_update(Side S, const uint32_t *
                     }
                 }
                 __syncthreads();  // s_off / s_y0 are refilled by the next chunk; pass 2 follows pass 1
+            }
+        }
+    }
+}
+
+// UPDATE-V for a round of at most `few` peeled vertices, spread over the
+// whole GPU: peeled vertex i keeps its own counter slice, and every wave takes
+// one neighbour y of a peeled vertex at a time and walks N(y) with its lanes.
+// PASS 1 counts c(u1, u2); PASS 2 (a launch of its own, after all of PASS 1)
+// takes each count with an atomic exchange and subtracts C(c, 2) from B(u2).
+template <int PASS>
+__global__ __launch_bounds__(256) void k_peel_spread(Side S, const uint32_t *front, const uint32_t *nfront,
+                                                     const uint32_t *gone, uint32_t few, uint32_t *cnt, int64_t *b) {
+    const uint32_t nf = *nfront;
+    if (nf == 0 || nf > few) return;
+    // first-level entries of the peeled vertices, laid end to end
+    uint64_t start[PEEL_FEW], end[PEEL_FEW], first[PEEL_FEW + 1];
+    first[0] = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < PEEL_FEW; ++i) {
+        start[i] = i < nf ? S.xb(front[i]) : 0;
+        end[i] = i < nf ? S.xb(front[i] + 1) : 0;
+        first[i + 1] = first[i] + (end[i] - start[i]);
+    }
+    const uint64_t items = first[PEEL_FEW];
+    const uint32_t lane = threadIdx.x & (WAVE - 1);
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / WAVE);
+    for (uint64_t t = (uint64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; t < items; t += waves) {
+        uint32_t i = 0;
+#pragma unroll
+        for (uint32_t j = 1; j < PEEL_FEW; ++j)
+            if (first[j] <= t) i = j;
+        uint32_t *c = cnt + (uint64_t)i * S.nx;
+        const uint32_t y = S.xadj[start[i] + (t - first[i])];
+        const uint64_t y0 = S.yb(y), y1 = S.yb(y + 1);
+        for (uint64_t q = y0 + lane; q < y1; q += WAVE) {
+            const uint32_t u2 = S.yadj[q];
+            if (gone[u2]) continue;
+            if (PASS == 1) {
+                atomicAdd(&c[u2], 1u);
+            } else {
+                const uint32_t cc = atomicExch(&c[u2], 0u);
+                if (cc >= 2) {
+                    const unsigned long long tt = (unsigned long long)cc * (cc - 1) / 2;
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&b[u2]), 0ull - tt);
+                }
             }
         }
     }
@@ -255,6 +307,7 @@ pb_status peel_impl(pb_graph *g, pb_peel_side side, const pb_opts *opts, int64_t
         uint64_t grid = PEEL_SCRATCH / slice;
         grid = grid > PEEL_MAX_GRID ? PEEL_MAX_GRID : grid < 1 ? 1 : grid;
         const uint32_t ugrid = (uint32_t)grid;
+        const uint32_t few = ugrid < PEEL_FEW ? ugrid : PEEL_FEW;  // spread rounds need one slice per vertex
         uint32_t *cnt = ws.alloc<uint32_t>((uint64_t)ugrid * nx);
         PeelState *st = ws.alloc<PeelState>(1);
         if (ws.failed) return PB_ERR_NO_MEMORY;
@@ -274,7 +327,11 @@ pb_status peel_impl(pb_graph *g, pb_peel_side side, const pb_opts *opts, int64_t
                 hipLaunchKernelGGL(k_peel_take, dim3(grid_of(nx, 65536)), dim3(256), 0, s, (const uint32_t *)flag,
                                    (const uint32_t *)pos, nx, S.base, (const PeelState *)st, gone, front, tip);
                 hipLaunchKernelGGL(k_peel_update, dim3(ugrid), dim3(PEEL_T), 0, s, S, (const uint32_t *)front,
-                                   (const uint32_t *)(pos + nx), (const uint32_t *)gone, cnt, b);
+                                   (const uint32_t *)(pos + nx), (const uint32_t *)gone, few, cnt, b);
+                hipLaunchKernelGGL(k_peel_spread<1>, dim3(SPREAD_GRID), dim3(256), 0, s, S, (const uint32_t *)front,
+                                   (const uint32_t *)(pos + nx), (const uint32_t *)gone, few, cnt, b);
+                hipLaunchKernelGGL(k_peel_spread<2>, dim3(SPREAD_GRID), dim3(256), 0, s, S, (const uint32_t *)front,
+                                   (const uint32_t *)(pos + nx), (const uint32_t *)gone, few, cnt, b);
                 hipLaunchKernelGGL(k_peel_close, dim3(1), dim3(1), 0, s, (const uint32_t *)(pos + nx), st);
                 PB_TRY_HIP(hipGetLastError());
             }
