@@ -85,34 +85,39 @@ __device__ inline int64_t round_k(const PeelState *st) {
     return mn != ~0ull && (int64_t)mn > st->k ? (int64_t)mn : st->k;
 }
 
-// flag[x] = remaining and B <= k
-__global__ void k_peel_flags(const int64_t *b, const uint32_t *gone, uint32_t nx, const PeelState *st,
-                             uint32_t *flag) {
+// the round's peeled vertices (B <= k among the remaining ones): tip number
+// k, and appended to front[] (in no particular order; the update does not
+// depend on it) with one counter atomic per wave
+__global__ void k_peel_take(const int64_t *b, uint32_t nx, uint32_t base, const PeelState *st, uint32_t *gone,
+                            uint32_t *front, uint32_t *nfront, int64_t *tip) {
     const int64_t k = round_k(st);
-    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nx; x += gridDim.x * blockDim.x)
-        flag[x] = !gone[x] && b[x] <= k;
-}
-
-// the round's peeled vertices, in id order; their tip number is k
-__global__ void k_peel_take(const uint32_t *flag, const uint32_t *pos, uint32_t nx, uint32_t base,
-                            const PeelState *st, uint32_t *gone, uint32_t *front, int64_t *tip) {
-    const int64_t k = round_k(st);
-    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nx; x += gridDim.x * blockDim.x)
-        if (flag[x]) {
-            front[pos[x]] = x;
+    const uint32_t lane = threadIdx.x & (WAVE - 1);
+    for (uint32_t x0 = blockIdx.x * blockDim.x; x0 < nx; x0 += gridDim.x * blockDim.x) {
+        const uint32_t x = x0 + threadIdx.x;
+        const bool take = x < nx && !gone[x] && b[x] <= k;
+        const uint64_t mask = __ballot(take);
+        if (mask == 0) continue;
+        const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1;
+        uint32_t at = 0;
+        if (lane == leader) at = atomicAdd(nfront, (uint32_t)__popcll(mask));
+        at = __shfl(at, (int)leader, WAVE);
+        if (take) {
+            front[at + (uint32_t)__popcll(mask & lanemask_lt())] = x;
             gone[x] = 1;
             tip[base + x] = k;
         }
+    }
 }
 
 // closes a round (one thread): k advances, the peeled vertices leave `left`,
 // and the next round's minimum starts empty
-__global__ void k_peel_close(const uint32_t *nfront, PeelState *st) {
+__global__ void k_peel_close(uint32_t *nfront, PeelState *st) {
     const uint32_t nf = *nfront;
     st->k = round_k(st);
     st->left -= nf;
     st->rounds += nf ? 1 : 0;
     st->mn = ~0ull;
+    *nfront = 0;
 }
 
 // UPDATE-V: one workgroup per peeled vertex (see the file comment).  `cnt`
@@ -293,7 +298,7 @@ pb_status peel_impl(pb_graph *g, pb_peel_side side, const pb_opts *opts, int64_t
     ws.release(rank);
     const uint32_t nx = S.nx;
     int64_t *b = ws.alloc<int64_t>(nx);
-    uint32_t *gone = ws.alloc<uint32_t>(nx), *flag = ws.alloc<uint32_t>(nx), *pos = ws.alloc<uint32_t>((uint64_t)nx + 1);
+    uint32_t *gone = ws.alloc<uint32_t>(nx), *nfront = ws.alloc<uint32_t>(1);
     uint32_t *front = ws.alloc<uint32_t>(nx);
     if (ws.failed) return PB_ERR_NO_MEMORY;
     hipLaunchKernelGGL(k_peel_init, dim3(grid_of(n, 65536)), dim3(256), 0, s, (const int64_t *)vcount, S.base, nx, n,
@@ -313,6 +318,7 @@ pb_status peel_impl(pb_graph *g, pb_peel_side side, const pb_opts *opts, int64_t
         if (ws.failed) return PB_ERR_NO_MEMORY;
         PB_TRY(fill<uint32_t>(cnt, 0u, (uint64_t)ugrid * nx, s));
         PB_TRY(fill<uint32_t>(gone, 0u, nx, s));
+        PB_TRY(fill<uint32_t>(nfront, 0u, 1, s));
         const PeelState st0{0, ~0ull, nx, 0, 1};
         PB_TRY_HIP(hipMemcpyAsync(st, &st0, sizeof(st0), hipMemcpyHostToDevice, s));
         PeelState *hst = static_cast<PeelState *>(hb.p);
@@ -320,19 +326,15 @@ pb_status peel_impl(pb_graph *g, pb_peel_side side, const pb_opts *opts, int64_t
             for (uint32_t r = 0; r < PEEL_BATCH; ++r) {
                 hipLaunchKernelGGL(k_peel_min, dim3(grid_of(nx, 1024)), dim3(256), 0, s, (const int64_t *)b,
                                    (const uint32_t *)gone, nx, &st->mn);
-                hipLaunchKernelGGL(k_peel_flags, dim3(grid_of(nx, 65536)), dim3(256), 0, s, (const int64_t *)b,
-                                   (const uint32_t *)gone, nx, (const PeelState *)st, flag);
-                PB_TRY_HIP(hipGetLastError());
-                PB_TRY((scan_exclusive<uint32_t, uint32_t>(flag, pos, nx, pos + nx, ws)));
-                hipLaunchKernelGGL(k_peel_take, dim3(grid_of(nx, 65536)), dim3(256), 0, s, (const uint32_t *)flag,
-                                   (const uint32_t *)pos, nx, S.base, (const PeelState *)st, gone, front, tip);
+                hipLaunchKernelGGL(k_peel_take, dim3(grid_of(nx, 65536)), dim3(256), 0, s, (const int64_t *)b, nx,
+                                   S.base, (const PeelState *)st, gone, front, nfront, tip);
                 hipLaunchKernelGGL(k_peel_update, dim3(ugrid), dim3(PEEL_T), 0, s, S, (const uint32_t *)front,
-                                   (const uint32_t *)(pos + nx), (const uint32_t *)gone, few, cnt, b);
+                                   (const uint32_t *)nfront, (const uint32_t *)gone, few, cnt, b);
                 hipLaunchKernelGGL(k_peel_spread<1>, dim3(SPREAD_GRID), dim3(256), 0, s, S, (const uint32_t *)front,
-                                   (const uint32_t *)(pos + nx), (const uint32_t *)gone, few, cnt, b);
+                                   (const uint32_t *)nfront, (const uint32_t *)gone, few, cnt, b);
                 hipLaunchKernelGGL(k_peel_spread<2>, dim3(SPREAD_GRID), dim3(256), 0, s, S, (const uint32_t *)front,
-                                   (const uint32_t *)(pos + nx), (const uint32_t *)gone, few, cnt, b);
-                hipLaunchKernelGGL(k_peel_close, dim3(1), dim3(1), 0, s, (const uint32_t *)(pos + nx), st);
+                                   (const uint32_t *)nfront, (const uint32_t *)gone, few, cnt, b);
+                hipLaunchKernelGGL(k_peel_close, dim3(1), dim3(1), 0, s, nfront, st);
                 PB_TRY_HIP(hipGetLastError());
             }
             PB_TRY_HIP(hipMemcpyAsync(hst, st, sizeof(PeelState), hipMemcpyDeviceToHost, s));
