@@ -379,23 +379,29 @@ __global__ __launch_bounds__(256) void k_wing_min(const int64_t *b, const uint32
     }
 }
 
-__global__ void k_wing_flags(const int64_t *b, const uint32_t *state, uint64_t m, const PeelState *st,
-                             uint32_t *flag) {
-    const int64_t k = round_k(st);
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
-        flag[e] = !state[e] && b[e] <= k;
-}
-
-__global__ void k_wing_take(const uint32_t *flag, const uint32_t *pos, uint64_t m, const PeelState *st,
-                            uint32_t *state, uint32_t *front, int64_t *wing) {
+// the round's peeled edges (B <= k among the remaining ones): wing number k,
+// state = this round, appended to front[] in no particular order (the update
+// decides by edge id, not by position) with one counter atomic per wave
+__global__ void k_wing_take(const int64_t *b, uint64_t m, const PeelState *st, uint32_t *state, uint32_t *front,
+                            uint32_t *nfront, int64_t *wing) {
     const int64_t k = round_k(st);
     const uint32_t rid = (uint32_t)st->rid;
-    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (uint64_t)gridDim.x * blockDim.x)
-        if (flag[e]) {
-            front[pos[e]] = (uint32_t)e;
+    const uint32_t lane = threadIdx.x & (WAVE - 1);
+    for (uint64_t e0 = (uint64_t)blockIdx.x * blockDim.x; e0 < m; e0 += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t e = e0 + threadIdx.x;
+        const bool take = e < m && !state[e] && b[e] <= k;
+        const uint64_t mask = __ballot(take);
+        if (mask == 0) continue;
+        const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1;
+        uint32_t at = 0;
+        if (lane == leader) at = atomicAdd(nfront, (uint32_t)__popcll(mask));
+        at = __shfl(at, (int)leader, WAVE);
+        if (take) {
+            front[at + (uint32_t)__popcll(mask & lanemask_lt())] = (uint32_t)e;
             state[e] = rid;
             wing[e] = k;
         }
+    }
 }
 
 struct WingGraph {
@@ -442,13 +448,14 @@ __global__ __launch_bounds__(256) void k_wing_update(WingGraph W, const uint32_t
     }
 }
 
-__global__ void k_wing_close(const uint32_t *nfront, PeelState *st) {
+__global__ void k_wing_close(uint32_t *nfront, PeelState *st) {
     const uint32_t nf = *nfront;
     st->k = round_k(st);
     st->left -= nf;
     st->rounds += nf ? 1 : 0;
     st->rid += 1;
     st->mn = ~0ull;
+    *nfront = 0;
 }
 
 pb_status wing_impl(pb_graph *g, const pb_opts *opts, int64_t *wing, uint64_t *rounds_out, hipStream_t s) {
@@ -467,11 +474,12 @@ pb_status wing_impl(pb_graph *g, const pb_opts *opts, int64_t *wing, uint64_t *r
     PB_TRY(pb_rank(g, PB_RANK_DEGREE, rank, s));
     PB_TRY(pb_count_edge(g, rank, opts, b, s));
     ws.release(rank);
-    uint32_t *state = ws.alloc<uint32_t>(m), *flag = ws.alloc<uint32_t>(m), *pos = ws.alloc<uint32_t>(m + 1);
+    uint32_t *state = ws.alloc<uint32_t>(m), *nfront = ws.alloc<uint32_t>(1);
     uint32_t *front = ws.alloc<uint32_t>(m);
     PeelState *st = ws.alloc<PeelState>(1);
     if (ws.failed) return PB_ERR_NO_MEMORY;
     PB_TRY(fill<uint32_t>(state, 0u, m, s));
+    PB_TRY(fill<uint32_t>(nfront, 0u, 1, s));
     const PeelState st0{0, ~0ull, m, 0, 1};
     PB_TRY_HIP(hipMemcpyAsync(st, &st0, sizeof(st0), hipMemcpyHostToDevice, s));
     const WingGraph W{g->u_off, g->u_adj, g->eu, g->v_off, g->v_adj, g->v_eid};
@@ -480,15 +488,11 @@ pb_status wing_impl(pb_graph *g, const pb_opts *opts, int64_t *wing, uint64_t *r
         for (uint32_t r = 0; r < PEEL_BATCH; ++r) {
             hipLaunchKernelGGL(k_wing_min, dim3(grid_of(m, 1024)), dim3(256), 0, s, (const int64_t *)b,
                                (const uint32_t *)state, m, &st->mn);
-            hipLaunchKernelGGL(k_wing_flags, dim3(grid_of(m, 65536)), dim3(256), 0, s, (const int64_t *)b,
-                               (const uint32_t *)state, m, (const PeelState *)st, flag);
-            PB_TRY_HIP(hipGetLastError());
-            PB_TRY((scan_exclusive<uint32_t, uint32_t>(flag, pos, m, pos + m, ws)));
-            hipLaunchKernelGGL(k_wing_take, dim3(grid_of(m, 65536)), dim3(256), 0, s, (const uint32_t *)flag,
-                               (const uint32_t *)pos, m, (const PeelState *)st, state, front, wing);
+            hipLaunchKernelGGL(k_wing_take, dim3(grid_of(m, 65536)), dim3(256), 0, s, (const int64_t *)b, m,
+                               (const PeelState *)st, state, front, nfront, wing);
             hipLaunchKernelGGL(k_wing_update, dim3(1024), dim3(256), 0, s, W, (const uint32_t *)front,
-                               (const uint32_t *)(pos + m), (const PeelState *)st, (const uint32_t *)state, b);
-            hipLaunchKernelGGL(k_wing_close, dim3(1), dim3(1), 0, s, (const uint32_t *)(pos + m), st);
+                               (const uint32_t *)nfront, (const PeelState *)st, (const uint32_t *)state, b);
+            hipLaunchKernelGGL(k_wing_close, dim3(1), dim3(1), 0, s, nfront, st);
             PB_TRY_HIP(hipGetLastError());
         }
         PB_TRY_HIP(hipMemcpyAsync(hst, st, sizeof(PeelState), hipMemcpyDeviceToHost, s));
