@@ -490,6 +490,47 @@ def run_batch(args):
     print(json.dumps(record), flush=True)
 
 
+def check_serve_outputs(args, Gs, outs, which, kinds, pb):
+    """Compares what the served requests wrote with the oracle's values for
+    the pool (tests/golden/serve_pool.json, made by the oracle alone): the
+    total of every graph queried for it and the per-vertex / per-edge array
+    digests of every graph queried for those.  Every output starts at -1, so
+    a graph's output that no request wrote cannot pass."""
+    import hashlib
+
+    import numpy as np
+    import torch
+    path = os.path.join(ROOT, "tests", "golden", "serve_pool.json")
+    if args.pool_small != 10_000 or args.pool_big > 50 or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        want = json.load(f)
+    print("[bench] checking the served outputs against the oracle's values", file=sys.stderr, flush=True)
+    asked = {}
+    for gi, k in zip(which.tolist(), kinds.tolist()):
+        asked[gi] = asked.get(gi, 0) | int(k)
+    torch.cuda.synchronize()
+    bad, outputs = [], 0
+    for gi, mask in sorted(asked.items()):
+        G, (go, vo, eo) = Gs[gi], outs[gi]
+        j = gi if gi < args.pool_small else 10_000 + (gi - args.pool_small)
+        d16 = lambda t, k: hashlib.sha256(np.ascontiguousarray(t.cpu().numpy()[:k], dtype="<i8").tobytes()
+                                          ).hexdigest()[:16]
+        if mask & pb.WANT["global"]:
+            outputs += 1
+            if int(go.cpu()[0]) != want["global"][j]:
+                bad.append((gi, "global"))
+        if mask & pb.WANT["vertex"]:
+            outputs += 1
+            if d16(vo, G.n) != want["vertex_sha256_16"][j]:
+                bad.append((gi, "vertex"))
+        if mask & pb.WANT["edge"]:
+            outputs += 1
+            if d16(eo, G.m) != want["edge_sha256_16"][j]:
+                bad.append((gi, "edge"))
+    return {"graphs": len(asked), "outputs": outputs, "all_equal": not bad, "differing": bad[:10]}
+
+
 def run_serve(args):
     """Serving workload: Poisson arrivals of count queries over a resident pool."""
     import numpy as np
@@ -499,16 +540,15 @@ def run_serve(args):
     from paper_1907_08607_amd import graphgen as gg
 
     t0 = time.time()
-    small = gg.workload_batch(args.pool_small, seed=5)
-    big = [gg.chung_lu(200_000, 50_000, 5_000_000, 2.1, 50_000.0, 200_000.0, 5_000 + i) for i in range(args.pool_big)]
-    graphs = small + big
+    graphs = gg.workload_serve_pool(args.pool_small, args.pool_big)
     print(f"[bench] pool of {len(graphs)} graphs generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     Gs = upload(graphs, pb)
     ranks = [pb.pb_rank(G, "degree") for G in Gs]
     print(f"[bench] pool resident and ranked ({sum(G.m for G in Gs)} edges)", file=sys.stderr, flush=True)
     # one output set per graph (every request on a graph writes the same values)
-    outs = [(torch.empty(1, dtype=torch.int64, device="cuda"), torch.empty(G.n, dtype=torch.int64, device="cuda"),
-             torch.empty(max(G.m, 1), dtype=torch.int64, device="cuda")) for G in Gs]
+    outs = [(torch.full((1,), -1, dtype=torch.int64, device="cuda"),
+             torch.full((G.n,), -1, dtype=torch.int64, device="cuda"),
+             torch.full((max(G.m, 1),), -1, dtype=torch.int64, device="cuda")) for G in Gs]
     rng = np.random.default_rng(55)
     n_req = int(args.rate * args.duration)
     arrivals = np.cumsum(rng.exponential(1.0 / args.rate, n_req))
@@ -536,6 +576,7 @@ def run_serve(args):
     comps = srv.poll(n_req + 16)
     srv.close()
     assert len(comps) == n_req and all(c.status == 0 for c in comps)
+    checked = check_serve_outputs(args, Gs, outs, which, kinds, pb)
     lat = [c.done_s - c.submit_s for c in comps]
     span = max(c.done_s for c in comps) - min(c.submit_s for c in comps)
     p50, p99 = lat_stats(lat)
@@ -569,7 +610,7 @@ def run_serve(args):
                    "max_batch": args.max_batch, "p50_ms": p50, "p99_ms": p99,
                    "mean_batch": float(np.mean(batch_sizes)),
                    "sequential_requests": n_seq, "sequential_requests_per_s": n_seq / seq_span, "sequential_p50_ms": s50,
-                   "sequential_p99_ms": s99},
+                   "sequential_p99_ms": s99, "oracle_check": checked},
     }
     print(json.dumps(record), flush=True)
 

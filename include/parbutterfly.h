@@ -25,7 +25,8 @@
  *     (the two sides' arrays are stored consecutively, Section 2).
  *   - Per-vertex outputs are indexed by unified id; per-edge outputs by the
  *     edge's position in u_adj.
- *   - Limits: m < 2^31 and n_u + n_v < 2^32 - 1.
+ *   - Limits: m < 2^31 and n_u + n_v < 2^32 - 1; degrees are otherwise
+ *     unrestricted.
  *   - Every buffer argument named "device" is device memory on the current
  *     HIP device; the caller owns all input and output buffers and the library
  *     never frees them.
@@ -54,8 +55,16 @@ typedef enum {
     PB_ERR_ID_RANGE = -3,    /* a column id >= n_v, or u_off is not a valid offset array */
     PB_ERR_BAD_RANK = -4,    /* rank is not a permutation of [0, n) */
     PB_ERR_NO_MEMORY = -5,   /* device allocation failed or the workspace cap is too small */
-    PB_ERR_OVERFLOW = -6,    /* a count would not fit int64 */
-    PB_ERR_HIP = -7          /* a HIP runtime call failed */
+    /* Reserved; no call returns it.  Under m < 2^31 no count can overflow
+     * int64: a butterfly {u1, u2, v1, v2} holds the two disjoint edges
+     * (u1, v1), (u2, v2), and two disjoint edges lie in at most one
+     * butterfly, so the total is at most C(m, 2) < 2^61; every per-vertex and
+     * per-edge count is at most the total, the per-vertex ones sum to 4 times
+     * it (< 2^63), and every partial sum the library keeps is a sum of
+     * non-negative terms of one of these counts. */
+    PB_ERR_OVERFLOW = -6,
+    PB_ERR_HIP = -7,         /* a HIP runtime call failed */
+    PB_ERR_INTERNAL = -8     /* an internal consistency check tripped (a library defect); outputs are invalid */
 } pb_status;
 
 /* The bipartite input graph (U-side CSR, device pointers). */
@@ -251,8 +260,7 @@ pb_status pb_rank_choose(pb_graph *g, pb_rank_kind other, uint32_t *rank_out, pb
  * Synchronises `stream` three times: after the rank check, after the work
  * plan (to size the launches) and at the end (to confirm that no internal
  * capacity check tripped), so the outputs are ready when it returns.
- * Errors: INVALID_ARG (also when max degree * 1024 >= 2^32), BAD_RANK,
- * NO_MEMORY, HIP. */
+ * Errors: INVALID_ARG, BAD_RANK, NO_MEMORY, HIP, INTERNAL. */
 pb_status pb_count(pb_graph *g, const uint32_t *rank, const pb_opts *opts, int64_t *global_out,
                    int64_t *vertex_out, int64_t *edge_out, hipStream_t stream);
 
@@ -417,8 +425,10 @@ pb_status pb_server_add_graph(pb_server *srv, pb_graph *g, const uint32_t *rank,
 
 /* Queues a request for graph `graph_id`; `want` is a PB_WANT_* mask and the
  * matching outputs (device, caller-owned, sized as for pb_count) must stay
- * valid until the request completes.  Returns at once; *request_id receives
- * its id.  NO_MEMORY when the request alone could never fit the budget. */
+ * valid until the request completes.  The slots' streams do not wait for the
+ * caller's streams: work the caller has queued on the output buffers must be
+ * complete before the call.  Returns at once; *request_id receives its id.
+ * NO_MEMORY when the request alone could never fit the budget. */
 pb_status pb_server_submit(pb_server *srv, uint32_t graph_id, uint32_t want, int64_t *global_out,
                            int64_t *vertex_out, int64_t *edge_out, uint64_t *request_id);
 

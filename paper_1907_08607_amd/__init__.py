@@ -21,6 +21,7 @@ PB_OK = 0
 STATUS = {
     0: "PB_OK", -1: "PB_ERR_INVALID_ARG", -2: "PB_ERR_NOT_SIMPLE", -3: "PB_ERR_ID_RANGE",
     -4: "PB_ERR_BAD_RANK", -5: "PB_ERR_NO_MEMORY", -6: "PB_ERR_OVERFLOW", -7: "PB_ERR_HIP",
+    -8: "PB_ERR_INTERNAL",
 }
 RANK_KINDS = {
     "side_auto": 0, "side_u": 1, "side_v": 2, "degree": 3, "approx_degree": 4,

@@ -1364,18 +1364,22 @@ __global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32
         uint32_t s_cur = 0, s_val = s_pos ? G.nbr[s_start] : 0u;
         const uint32_t lo_min = G.lo(r);
         // ids from bfrom up take 8-bit counters (4 * WIN_WORDS in a window),
-        // from nfrom up 4-bit ones (8 * WIN_WORDS)
+        // from nfrom up 4-bit ones (8 * WIN_WORDS).  R(x1, x2) <= deg_x1(x1)
+        // = ups as well, so a source with fewer than 256 (16) up-slots takes
+        // 8-bit (4-bit) counters over its whole range.
         const uint32_t side = G.smid[r] < G.n_u ? 0 : 1;
         const uint32_t bfrom = byte_from[side], nfrom = byte_from[2 + side];
+        const bool nib_all = ups < 16, byte_all = ups < 256;
         uint32_t hi = G.cend[r];
         bool first = true;
         __syncthreads();  // the previous source is done with the shared tables
         while (hi > lo_min) {
-            const bool nib = hi > nfrom, byte = !nib && hi > bfrom;
-            const uint32_t floor_id = nib ? nfrom : bfrom;
+            const bool nib = nib_all || hi > nfrom, byte = !nib && (byte_all || hi > bfrom);
             const uint32_t width = nib ? 8 * WIN_WORDS : byte ? 4 * WIN_WORDS : wsz;
             uint32_t lo = hi - lo_min > width ? hi - width : lo_min;
-            if ((nib || byte) && lo < floor_id) lo = floor_id;
+            // a window narrowed by the id thresholds alone stops at its threshold
+            if (nib && !nib_all && lo < nfrom) lo = nfrom;
+            if (byte && !byte_all && lo < bfrom) lo = bfrom;
             const DenseAgg<T> agg{words, lo, hi - lo, half, A.err, byte, nib};
             const CursorRange rng{cur, nxt, cval, nval, lo, first, two_pass};
             if (!waves) {
@@ -1811,8 +1815,11 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
                      hipStream_t s, float *list_ms) {
     const uint64_t n = in.n, m = in.m, ns = 2 * m;
     const uint32_t ng = in.bl.ng;
-    // per-chunk wedge offsets are 32-bit: 1024 runs of at most max_deg each
-    if ((uint64_t)in.max_deg * 1024 >= (uint64_t(1) << 32)) return PB_ERR_INVALID_ARG;
+    // Chunk and segment sums are 32-bit.  Every chunk holds up-slots of one
+    // source x1, whose centres y are distinct vertices of one side, so its
+    // wedges number at most the sum of their degrees <= m < 2^31; a run
+    // segment's credits sum R(x1, x2) - 1 over distinct x2 of one side, each
+    // R <= deg(x2), so they too stay below m.  No degree limit is needed.
     if (opts.stats) *opts.stats = pb_stats{};
 
     const bool timing = ((opts.flags & PB_FLAG_TIMING) && opts.stats) || list_ms;
@@ -2189,7 +2196,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
     mark(2 + NLISTS);
     PB_TRY_HIP(hipMemcpyAsync(hpc, pc, sizeof(PlanCounts), hipMemcpyDeviceToHost, s));
     PB_TRY_HIP(hipStreamSynchronize(s));
-    if (hpc->flags & FLAG_INTERNAL) return PB_ERR_HIP;
+    if (hpc->flags & FLAG_INTERNAL) return PB_ERR_INTERNAL;
 
     // t[0] prepare, t[1 + l] list l, t[1 + NLISTS] output; hub kernels apart
     float t[NEV - 1] = {}, t_gemm = 0, t_hub_pass = 0;

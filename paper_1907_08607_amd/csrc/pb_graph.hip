@@ -591,7 +591,7 @@ pb_status rank_codeg_exact(pb_graph *g, uint32_t *rank, hipStream_t s) {
                 break;
             }
             const uint32_t nw = host[0], lo = host[1];
-            if (nw == 0) { rc = PB_ERR_HIP; break; }  // cannot happen while vertices remain
+            if (nw == 0) { rc = PB_ERR_INTERNAL; break; }  // cannot happen while vertices remain
             if (nw > CW_CAP) {
                 // only key H's vertices: one round removes them all
                 hipLaunchKernelGGL(k_codeg_wtake, dim3(grid_for(nw)), dim3(256), 0, s, (const uint32_t *)win, nw,
@@ -612,7 +612,7 @@ pb_status rank_codeg_exact(pb_graph *g, uint32_t *rank, hipStream_t s) {
                 memcpy(&h, host + 4, sizeof(h));
                 next = h.next;
                 if (h.status == CW_EXHAUSTED) break;
-                if (h.status != CW_BIG || h.nf == 0) { rc = PB_ERR_HIP; break; }  // a round removes someone
+                if (h.status != CW_BIG || h.nf == 0) { rc = PB_ERR_INTERNAL; break; }  // a round removes someone
                 // a round with many neighbours to visit: ranked by the window
                 // kernel, its neighbours dropped by all workgroups
                 if ((rc = drop_front(h.nf)) != PB_OK) break;
@@ -657,7 +657,7 @@ pb_status rank_codeg(pb_graph *g, bool approx, uint32_t *rank, hipStream_t s) {
                 break;
             }
             const uint32_t nf = *host;
-            if (nf == 0) { st = PB_ERR_HIP; break; }  // cannot happen while vertices remain
+            if (nf == 0) { st = PB_ERR_INTERNAL; break; }  // cannot happen while vertices remain
             hipLaunchKernelGGL(k_codeg_small, dim3(grid_for(nf)), dim3(256), 0, s, (const uint32_t *)front, nf,
                                (const uint32_t *)g->deg, g->u_off, g->u_adj, g->v_off, g->v_adj, g->n_u,
                                (const uint32_t *)alive, cur, ccnt);
@@ -697,8 +697,9 @@ const char *pb_status_str(pb_status s) {
         case PB_ERR_ID_RANGE: return "vertex id or offset out of range";
         case PB_ERR_BAD_RANK: return "rank is not a permutation of [0, n)";
         case PB_ERR_NO_MEMORY: return "out of device memory or workspace cap";
-        case PB_ERR_OVERFLOW: return "count overflows int64";
+        case PB_ERR_OVERFLOW: return "count overflows int64 (reserved, never returned)";
         case PB_ERR_HIP: return "HIP runtime error";
+        case PB_ERR_INTERNAL: return "internal consistency check failed";
     }
     return "unknown status";
 }

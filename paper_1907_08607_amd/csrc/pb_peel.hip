@@ -340,7 +340,7 @@ pb_status peel_impl(pb_graph *g, pb_peel_side side, const pb_opts *opts, int64_t
             PB_TRY_HIP(hipMemcpyAsync(hst, st, sizeof(PeelState), hipMemcpyDeviceToHost, s));
             PB_TRY_HIP(hipStreamSynchronize(s));
             if (hst->left == 0) break;
-            if (hst->left > nx) return PB_ERR_HIP;  // cannot happen: each round takes at most what is left
+            if (hst->left > nx) return PB_ERR_INTERNAL;  // cannot happen: each round takes at most what is left
         }
         rounds = hst->rounds;
     }
@@ -498,7 +498,7 @@ pb_status wing_impl(pb_graph *g, const pb_opts *opts, int64_t *wing, uint64_t *r
         PB_TRY_HIP(hipMemcpyAsync(hst, st, sizeof(PeelState), hipMemcpyDeviceToHost, s));
         PB_TRY_HIP(hipStreamSynchronize(s));
         if (hst->left == 0) break;
-        if (hst->left > m) return PB_ERR_HIP;  // cannot happen: each round takes at most what is left
+        if (hst->left > m) return PB_ERR_INTERNAL;  // cannot happen: each round takes at most what is left
     }
     if (rounds_out) *rounds_out = hst->rounds;
     return PB_OK;

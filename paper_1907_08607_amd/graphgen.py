@@ -305,3 +305,15 @@ def batch_graph(n_u: int, n_v: int, m: int, seed: int) -> BipartiteCSR:
 def workload_batch(count: int = 4096, seed: int = 4) -> list[BipartiteCSR]:
     return [batch_graph(nu, nv, m, seed * 1_000_003 + i)
             for i, (nu, nv, m) in enumerate(batch_shapes(count, seed))]
+
+
+def serve_big_graph(i: int) -> BipartiteCSR:
+    """One of the serving pool's large graphs: Chung-Lu, |U|=200k, |V|=50k,
+    m=5M, exponent 2.1."""
+    return chung_lu(200_000, 50_000, 5_000_000, 2.1, 50_000.0, 200_000.0, 5_000 + i)
+
+
+def workload_serve_pool(pool_small: int = 10_000, pool_big: int = 50) -> list[BipartiteCSR]:
+    """The serving pool: graphs shaped as the batched workload (seed 5), then
+    the large graphs."""
+    return workload_batch(pool_small, seed=5) + [serve_big_graph(i) for i in range(pool_big)]

@@ -39,11 +39,26 @@ def test_every_declared_symbol_is_exported(lib):
         assert hasattr(lib, name), name
 
 
+def declared_statuses():
+    """(name, value) of every pb_status constant the header declares."""
+    with open(os.path.join(ROOT, "include", "parbutterfly.h")) as f:
+        text = f.read()
+    body = re.search(r"typedef enum \{(.*?)\} pb_status;", text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    return [(k, int(v)) for k, v in re.findall(r"(PB_\w+)\s*=\s*(-?\d+)", body)]
+
+
 def test_status_strings(lib):
     import paper_1907_08607_amd as pb
+    decl = declared_statuses()
+    assert {v: k for k, v in decl} == pb.STATUS
+    strs = set()
     for code in pb.STATUS:
         assert pb.status_str(code)
+        strs.add(pb.status_str(code))
+    assert len(strs) == len(pb.STATUS)  # every code has its own text
     assert pb.status_str(-4).startswith("rank")
+    assert "never returned" in pb.status_str(-6)
 
 
 def test_opts_default(lib):

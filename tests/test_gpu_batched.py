@@ -104,3 +104,56 @@ def test_autotune_table_is_valid_and_exact():
     want = oracle.count(g)
     assert int(gl1.cpu()[0]) == want[0]
     assert (ve1.cpu().numpy() == want[1]).all() and (ed1.cpu().numpy() == want[2]).all()
+
+
+def mid_batch(seed=21, count=8):
+    """Members of the batched workload's upper sizes (5k-20k vertices a side,
+    100k-500k edges): candidate ranges beyond one 4096-id window, so the
+    batched dense windows, packed-hash windows and window hashing run with
+    per-graph candidate ends.  Plus one graph with giant sources (up-slot
+    counts above the global-histogram threshold) between two others."""
+    rng = np.random.default_rng(seed)
+    gs = []
+    for i in range(count):
+        n_u = int(np.exp(rng.uniform(np.log(5_000), np.log(20_000))))
+        n_v = int(np.exp(rng.uniform(np.log(5_000), np.log(20_000))))
+        m = int(np.exp(rng.uniform(np.log(100_000), np.log(500_000))))
+        gs.append(gg.batch_graph(n_u, n_v, m, seed * 1000 + i))
+    gs.insert(count // 2, gg.giant_hubs(150_000, 6_000, 4, 70_000, 2, 7))
+    return gs
+
+
+_mid = {}
+
+
+def mid_want():
+    if not _mid:
+        gs = mid_batch()
+        _mid["gs"] = gs
+        _mid["want"] = [oracle.count(g) for g in gs]
+    return _mid["gs"], _mid["want"]
+
+
+@pytest.mark.parametrize("agg", ["auto", "hash", "dense", "sort"])
+def test_mid_size_batch_matches_oracle(agg):
+    gs, want = mid_want()
+    Gs, ranks = to_gpu(gs)
+    st = pb.pb_stats()
+    gl, ve, ed = pb.pb_count_batched(Gs, ranks, True, True, True, agg=agg, stats=st)
+    torch.cuda.synchronize()
+    for i, (g, (wg, wv, we)) in enumerate(zip(gs, want)):
+        assert int(gl[i].cpu()[0]) == wg, i
+        assert np.array_equal(ve[i].cpu().numpy(), wv), i
+        assert np.array_equal(ed[i].cpu().numpy()[:g.m], we), i
+    assert st.wedges == sum(oracle.wedges(g, oracle.rank(g, "degree")) for g in gs)
+    # the paths this batch is meant to reach
+    if agg in ("auto", "dense"):
+        assert st.wedges_heavy > 0 and st.wedges_global > 0
+    if agg == "auto":
+        assert st.wedges_hash > 0
+    if agg == "hash":
+        assert st.wedges_hash == st.wedges and st.window_items > 0
+    if agg == "sort":
+        assert st.wedges_sort == st.wedges
+    for G in Gs:
+        G.close()

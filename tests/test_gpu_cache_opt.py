@@ -55,8 +55,6 @@ def run(g, rank, **kw):
 @pytest.mark.parametrize("kind", ["degree", "side_auto", "approx_codeg"])
 @pytest.mark.parametrize("agg", ["auto", "hash", "dense", "sort"])
 def test_cache_opt_matches_oracle(name, kind, agg):
-    if name == "giant" and agg != "auto":
-        pytest.skip("forced aggregators on the giant graph are covered by the default order")
     g, (gw, vw, ew) = want(name)
     rank = oracle.rank(g, kind)
     (gl, ve, ed), st = run(g, rank, agg=agg)

@@ -108,3 +108,18 @@ def test_giant_transposed(giant):
     tw = oracle.count(t)
     assert got[0] == want[0] == tw[0]
     assert_same(got, tw, "transposed")
+
+
+@pytest.mark.parametrize("kind", ["degree", "side_v"])
+def test_vertex_of_degree_above_2_22(kind):
+    """One V vertex adjacent to all 4.5M U vertices (degree above 2^22), each
+    U vertex also taking one random neighbour among 1000 others: a source (or,
+    V first, a centre) far longer than any 1024-up-slot chunk's run total
+    could be if degrees alone bounded it.  Counts must equal the oracle's."""
+    g = gg.giant_hubs(4_500_000, 1_000, 1, 4_500_000, 1, 17)
+    assert int(np.bincount(g.u_adj).max()) > (1 << 22)
+    want = oracle.count(g)
+    rank = oracle.rank(g, kind)
+    got, st = run(g, rank)
+    assert_same(got, want, kind)
+    assert st.wedges == oracle.wedges(g, rank)

@@ -35,11 +35,14 @@ def run_trace(srv, Gs, gids, trace):
     outs = []
     for gi, want in trace:
         G = Gs[gi]
-        o = (torch.full((1,), -1, dtype=torch.int64, device="cuda") if want & 1 else None,
-             torch.full((G.n,), -1, dtype=torch.int64, device="cuda") if want & 2 else None,
-             torch.full((max(G.m, 1),), -1, dtype=torch.int64, device="cuda") if want & 4 else None)
+        outs.append((torch.full((1,), -1, dtype=torch.int64, device="cuda") if want & 1 else None,
+                     torch.full((G.n,), -1, dtype=torch.int64, device="cuda") if want & 2 else None,
+                     torch.full((max(G.m, 1),), -1, dtype=torch.int64, device="cuda") if want & 4 else None))
+    # the server's streams do not wait for torch's: the -1 fills must be done
+    # before a request may write its outputs
+    torch.cuda.synchronize()
+    for (gi, want), o in zip(trace, outs):
         srv.submit(gids[gi], want, *o)
-        outs.append(o)
     srv.drain()
     return outs
 
@@ -107,3 +110,48 @@ def test_admission_by_footprint():
     for i, (go, _, _) in enumerate(outs):
         assert int(go.cpu()[0]) == oracle.count(gs[i % len(gs)], False, False)[0]
     srv.close()
+
+
+def test_serving_pool_members_match_the_oracle():
+    """Members of the full serving pool (the first 200 graphs of its
+    batch-shaped part and the first 10 of its 5M-edge graphs), each queried
+    for all three outputs in one request and again in single-output requests
+    mixed with the others, compared with the oracle's values for the pool
+    (tests/golden/serve_pool.json, written by make_golden.py from the oracle
+    alone)."""
+    import hashlib
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "serve_pool.json")) as f:
+        want = json.load(f)
+    small, big = 200, 10
+    n_small = want["count"] - 50
+    gs = gg.workload_batch(small, seed=5) + [gg.serve_big_graph(i) for i in range(big)]
+    idx = list(range(small)) + [n_small + i for i in range(big)]
+    Gs = [pb.Graph.from_csr(g) for g in gs]
+    ranks = [pb.pb_rank(G, "degree") for G in Gs]
+    srv = pb.Server(slots=4, max_batch=16)
+    gids = [srv.add_graph(G, r) for G, r in zip(Gs, ranks)]
+    rng = np.random.default_rng(13)
+    trace = [(i, 7) for i in range(len(gs))] + [(int(rng.integers(0, len(gs))), int(rng.choice([1, 2, 4])))
+                                                for _ in range(400)]
+    order = rng.permutation(len(trace))
+    trace = [trace[i] for i in order]
+    outs = run_trace(srv, Gs, gids, trace)
+    comps = srv.poll(len(trace) + 16)
+    assert len(comps) == len(trace) and all(c.status == 0 for c in comps)
+    srv.close()
+
+    def d16(t, k):
+        return hashlib.sha256(np.ascontiguousarray(t.cpu().numpy()[:k], dtype="<i8").tobytes()).hexdigest()[:16]
+
+    for (gi, w), (go, vo, eo) in zip(trace, outs):
+        j, G = idx[gi], Gs[gi]
+        if go is not None:
+            assert int(go.cpu()[0]) == want["global"][j], (gi, w)
+        if vo is not None:
+            assert d16(vo, G.n) == want["vertex_sha256_16"][j], (gi, w)
+        if eo is not None:
+            assert d16(eo, G.m) == want["edge_sha256_16"][j], (gi, w)
+    for G in Gs:
+        G.close()
