@@ -276,6 +276,35 @@ pb_status pb_count_vertex(pb_graph *g, const uint32_t *rank, const pb_opts *opts
 pb_status pb_count_edge(pb_graph *g, const uint32_t *rank, const pb_opts *opts, int64_t *out,
                         hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Counting without allocation.
+ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, serving loops that must not allocate, harnesses that forbid it.
+ * pb_count_noalloc computes exactly what pb_count computes (same arguments,
+ * same outputs), but every scratch block comes from one array of
+ * PB_NOALLOC_SCRATCH_BYTES inside the library, a device global that each
+ * device holds from the library's load to the end of the process.  The call
+ * allocates no device memory and no pinned host memory.  Differences from
+ * pb_count: the hub tile is never used (opts->hub is ignored), phase times are
+ * not measured (PB_FLAG_TIMING is ignored; the other stats are filled) and
+ * opts->workspace_cap_bytes is ignored.
+ * Limits: NO_MEMORY, before any work is queued, when
+ * 200 (n_u + n_v) + 84 m + 32 u + 65536 bytes exceed the array (u = m up-slots,
+ * 2m with PB_FLAG_CACHE_OPT), that is graphs of up to about 1M edges; NO_MEMORY
+ * also when data-dependent tables (the window items of forced hashing, the
+ * histograms of sources with 65536 or more up-slots) do not fit beside them.
+ * Sharing: calls on one device are serialised by a lock in the library, and
+ * each returns only once its work on `stream` has finished, so two calls
+ * never use the array at the same time.  The array keeps the last call's
+ * contents; every call clears what it needs.
+ * Synchronises `stream` as pb_count does, and once more before returning.
+ * Errors: those of pb_count. */
+#define PB_NOALLOC_SCRATCH_BYTES (128ull << 20)
+
+pb_status pb_count_noalloc(pb_graph *g, const uint32_t *rank, const pb_opts *opts, int64_t *global_out,
+                           int64_t *vertex_out, int64_t *edge_out, hipStream_t stream);
+
 /* Approximate total counts by graph sparsification (Section 4.6
  * "Approximate counting"): a kept graph is drawn, counted exactly, and the
  * count scaled to an unbiased estimate.  Only the total can be estimated.

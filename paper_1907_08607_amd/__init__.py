@@ -101,6 +101,8 @@ def load_library():
     lib.pb_rank.restype = ctypes.c_int
     lib.pb_count.argtypes = [P, P, ctypes.POINTER(pb_opts), P, P, P, P]
     lib.pb_count.restype = ctypes.c_int
+    lib.pb_count_noalloc.argtypes = [P, P, ctypes.POINTER(pb_opts), P, P, P, P]
+    lib.pb_count_noalloc.restype = ctypes.c_int
     for name in ("pb_count_global", "pb_count_vertex", "pb_count_edge"):
         fn = getattr(lib, name)
         fn.argtypes = [P, P, ctypes.POINTER(pb_opts), P, P]
@@ -257,6 +259,21 @@ def pb_count(g: Graph, rank, want_global=True, want_vertex=True, want_edge=True,
                                    ptr(gout, "global_out"), ptr(vout, "vertex_out"), ptr(eout, "edge_out"),
                                    _stream(stream)), "pb_count")
     return gout, vout, eout
+
+
+def pb_count_noalloc(g: Graph, rank, outs, agg="auto", stats: pb_stats | None = None, stream=None,
+                     cache_opt=False):
+    """pb_count with every scratch block taken from the library's fixed
+    per-device array: `outs` = (global int64[1] or None, per-vertex int64[n] or
+    None, per-edge int64[m] or None), caller-allocated."""
+    torch = _torch()
+    gout, vout, eout = outs
+    opts = make_opts(agg, "off", 0, stats, False, None, cache_opt)
+    ptr = lambda t, name: None if t is None else _dev_ptr(t, torch.int64, name)
+    _check(load_library().pb_count_noalloc(g.handle, _dev_ptr(rank, torch.int32, "rank"), ctypes.byref(opts),
+                                           ptr(gout, "global_out"), ptr(vout, "vertex_out"),
+                                           ptr(eout, "edge_out"), _stream(stream)), "pb_count_noalloc")
+    return outs
 
 
 def _single(name, g, rank, n_out, agg, hub, workspace_cap, stats, stream):

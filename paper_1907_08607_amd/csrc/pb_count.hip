@@ -22,6 +22,7 @@
 #include "pb_internal.h"
 
 #include <algorithm>
+#include <mutex>
 
 using namespace pb;
 
@@ -1810,9 +1811,12 @@ bool policy_from(const pb_opts &o, Policy *p) {
 }
 
 // Runs framework steps 2-4 (Section 3.1) on `in`.  `list_ms`, if given,
-// receives the time of each work list's kernel (NLISTS entries).
+// receives the time of each work list's kernel (NLISTS entries).  With
+// `region` (device memory of `region_bytes`) every scratch block comes from
+// that region and the call allocates nothing, device or pinned host memory:
+// no phase timing (events) and no hub tile then.
 pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_opts &opts, const Policy &pol,
-                     hipStream_t s, float *list_ms) {
+                     hipStream_t s, float *list_ms, void *region = nullptr, uint64_t region_bytes = 0) {
     const uint64_t n = in.n, m = in.m, ns = 2 * m;
     const uint32_t ng = in.bl.ng;
     // Chunk and segment sums are 32-bit.  Every chunk holds up-slots of one
@@ -1822,7 +1826,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
     // R <= deg(x2), so they too stay below m.  No degree limit is needed.
     if (opts.stats) *opts.stats = pb_stats{};
 
-    const bool timing = ((opts.flags & PB_FLAG_TIMING) && opts.stats) || list_ms;
+    const bool timing = !region && (((opts.flags & PB_FLAG_TIMING) && opts.stats) || list_ms);
     const bool copt = (opts.flags & PB_FLAG_CACHE_OPT) && in.bl.ng <= 1;
     const uint64_t nups = copt ? 2 * in.m : in.m;  // up-slots: every slot, or one per edge
     // events: [0] start, [1] plan done, [2 + i] after list i, [2 + NLISTS] end,
@@ -1846,13 +1850,18 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         if (ev.ok) ev.ok = hipEventRecord(ev.e[i], s) == hipSuccess;
     };
 
-    Workspace ws(s, opts.workspace_cap_bytes);
-    PlanCounts *hpc = nullptr;
-    PB_TRY_HIP(hipHostMalloc((void **)&hpc, sizeof(PlanCounts), hipHostMallocDefault));
+    Workspace ws = region ? Workspace(s, region, region_bytes) : Workspace(s, opts.workspace_cap_bytes);
+    // plan read-backs: pinned host memory, or a pageable local without a region
+    // (the stream is synchronised after each copy either way)
+    PlanCounts local_pc{}, *hpc = &local_pc;
+    if (!region) PB_TRY_HIP(hipHostMalloc((void **)&hpc, sizeof(PlanCounts), hipHostMallocDefault));
     struct HostFree {
         PlanCounts *p;
-        ~HostFree() { (void)hipHostFree(p); }
-    } host_free{hpc};
+        bool pinned;
+        ~HostFree() {
+            if (pinned) (void)hipHostFree(p);
+        }
+    } host_free{hpc, !region};
 
     // Accumulators first so an empty graph still writes zeros.
     unsigned long long *gacc = ws.alloc<unsigned long long>(ng);
@@ -1887,7 +1896,8 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
     // Hub tile candidates (one graph only): the first HUB_T vertices in rank
     // order of the rank-0 vertex's side.
     uint32_t hub_base = 0, hub_end = 0;
-    if (m > 0 && ng == 1 && !copt && opts.hub != PB_HUB_OFF && (opts.hub == PB_HUB_FORCE || m >= HUB_AUTO_MIN_M)) {
+    if (m > 0 && ng == 1 && !copt && !region && opts.hub != PB_HUB_OFF &&
+        (opts.hub == PB_HUB_FORCE || m >= HUB_AUTO_MIN_M)) {
         const bool hub_v = hpc->top >= in.n_u;
         const uint64_t side = hub_v ? n - in.n_u : in.n_u;
         const uint32_t H = (uint32_t)std::min<uint64_t>(HUB_T, side);
@@ -2388,6 +2398,34 @@ pb_status build_batch(pb_graph *const *gs, const uint32_t *const *ranks, uint32_
     return PB_OK;
 }
 
+// ---------------------------------------------------------------- allocation-free counting
+
+// Device scratch of pb_count_noalloc: one array per device, held for the life
+// of the process.  Host code reaches it only through the address
+// hipGetSymbolAddress gives on each device.
+static __device__ __align__(256) unsigned char scratch[PB_NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+struct NoallocDevice {
+    std::mutex mu;
+    void *ptr = nullptr;  // the array's address on this device, once looked up
+};
+NoallocDevice noalloc_devices[NOALLOC_MAX_DEVICES];
+
+// An upper bound on the scratch one counting call carves from the array for
+// a graph of n vertices and m edges, before the data-dependent tables (window
+// items of forced hashing, giant-source histograms), which are checked when
+// they are sized.  Per vertex: 4-byte rank, side, offset and degree tables,
+// the 8-byte vertex credits and the work lists (196 bytes in all).  Per
+// up-slot: run start and length, four cursors and the wedge scan (32 bytes;
+// m up-slots, 2m with the cache-optimised order).  Per edge: sort keys and
+// values in two buffers (48 bytes), the ranked lists and slot table (16),
+// slot credits (16) and the sort histograms; plus block rounding.
+inline uint64_t noalloc_need(uint64_t n, uint64_t m, bool copt) {
+    const uint64_t ups = copt ? 2 * m : m;
+    return 200 * n + 84 * m + 32 * ups + (uint64_t(1) << 16);
+}
+
 }  // namespace
 
 extern "C" {
@@ -2410,6 +2448,40 @@ pb_status pb_count_vertex(pb_graph *g, const uint32_t *rank, const pb_opts *opts
 pb_status pb_count_edge(pb_graph *g, const uint32_t *rank, const pb_opts *opts, int64_t *out, hipStream_t stream) {
     if (!out) return PB_ERR_INVALID_ARG;
     return count_impl(g, rank, opts, nullptr, nullptr, out, stream);
+}
+
+pb_status pb_count_noalloc(pb_graph *g, const uint32_t *rank, const pb_opts *opts_in, int64_t *global_out,
+                           int64_t *vertex_out, int64_t *edge_out, hipStream_t stream) {
+    if (!g || !rank) return PB_ERR_INVALID_ARG;
+    if (!global_out && !vertex_out && !edge_out) return PB_ERR_INVALID_ARG;
+    pb_opts opts;
+    Policy pol;
+    PB_TRY(check_opts(opts_in, &opts, &pol));
+    const int mode = (global_out ? MODE_GLOBAL : 0) | (vertex_out ? MODE_VERTEX : 0) | (edge_out ? MODE_EDGE : 0);
+    const uint64_t n = (uint64_t)g->n_u + g->n_v;
+    if (noalloc_need(n, g->m, (opts.flags & PB_FLAG_CACHE_OPT) != 0) > PB_NOALLOC_SCRATCH_BYTES)
+        return PB_ERR_NO_MEMORY;
+    int dev = 0;
+    PB_TRY_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return PB_ERR_INVALID_ARG;
+    NoallocDevice &d = noalloc_devices[dev];
+    std::lock_guard<std::mutex> lk(d.mu);  // one call at a time uses this device's array
+    if (!d.ptr) {
+        // the array's device address on this device (the symbol's name is a
+        // host-side stand-in, never a device pointer)
+        void *p = nullptr;
+        PB_TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return PB_ERR_HIP;
+        d.ptr = p;
+    }
+    CoreIn in{n, g->n_u, g->m, g->eu, g->u_adj, g->deg, rank, g->max_deg,
+              BatchLayout{1, nullptr, nullptr, nullptr, nullptr}, g->u_off, g->u_adj, g->v_off, g->v_adj, g->v_eid};
+    CoreOut out{global_out, vertex_out, edge_out, nullptr, nullptr, nullptr};
+    const pb_status st = count_core(in, out, mode, opts, pol, stream, nullptr, d.ptr, PB_NOALLOC_SCRATCH_BYTES);
+    // the array is free for the next call only once this call's work is done
+    // (an error return may leave work queued)
+    if (hipStreamSynchronize(stream) != hipSuccess && st == PB_OK) return PB_ERR_HIP;
+    return st;
 }
 
 pb_status pb_count_batched(pb_graph *const *graphs, const uint32_t *const *ranks, uint32_t count, const pb_opts *opts_in,

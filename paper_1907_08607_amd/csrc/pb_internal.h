@@ -36,6 +36,12 @@ void scratch_put(hipStream_t s, void *p);
 // Stream-ordered scratch for one library call.  Every allocation goes back to
 // the cache when the Workspace goes out of scope.  `cap` bounds the total
 // bytes (0 = unbounded).
+//
+// With a fixed region instead (`region`, `region_bytes`: device memory the
+// caller owns), blocks are carved from it as a stack and nothing is ever
+// allocated: a block is placed after the highest live one, so releasing the
+// top block (and any freed blocks below it) makes room again.  A request the
+// region cannot hold fails like an exhausted cap.
 struct Workspace {
     hipStream_t stream;
     uint64_t cap;
@@ -43,17 +49,41 @@ struct Workspace {
     uint64_t peak = 0;
     bool failed = false;
     std::vector<std::pair<void *, uint64_t>> ptrs;
+    char *region = nullptr;
+    uint64_t region_bytes = 0;
 
     Workspace(hipStream_t s, uint64_t cap_bytes) : stream(s), cap(cap_bytes) {}
+    Workspace(hipStream_t s, void *fixed, uint64_t fixed_bytes)
+        : stream(s), cap(0), region(static_cast<char *>(fixed)), region_bytes(fixed_bytes) {}
     Workspace(const Workspace &) = delete;
     Workspace &operator=(const Workspace &) = delete;
     ~Workspace() { release_all(); }
+
+    // End offset of the highest live block of the fixed region.
+    uint64_t region_top() const {
+        uint64_t top = 0;
+        for (auto &p : ptrs) {
+            const uint64_t end = (uint64_t)(static_cast<char *>(p.first) - region) + p.second;
+            if (end > top) top = end;
+        }
+        return top;
+    }
 
     void *alloc_bytes(uint64_t bytes) {
         if (bytes == 0) bytes = 256;
         bytes = (bytes + 255) & ~uint64_t(255);
         if (cap && used + bytes > cap) { failed = true; return nullptr; }
-        void *p = scratch_get(stream, bytes);
+        void *p;
+        if (region) {
+            const uint64_t top = region_top();
+            if (bytes > region_bytes - top) {
+                failed = true;
+                return nullptr;
+            }
+            p = region + top;
+        } else {
+            p = scratch_get(stream, bytes);
+        }
         if (!p) {
             failed = true;
             return nullptr;
@@ -70,14 +100,15 @@ struct Workspace {
     void release(void *p) {
         for (size_t i = 0; i < ptrs.size(); ++i)
             if (ptrs[i].first == p) {
-                scratch_put(stream, p);
+                if (!region) scratch_put(stream, p);
                 used -= ptrs[i].second;
                 ptrs.erase(ptrs.begin() + i);
                 return;
             }
     }
     void release_all() {
-        for (auto &p : ptrs) scratch_put(stream, p.first);
+        if (!region)
+            for (auto &p : ptrs) scratch_put(stream, p.first);
         ptrs.clear();
         used = 0;
     }
