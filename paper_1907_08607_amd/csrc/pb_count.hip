@@ -947,7 +947,7 @@ struct RunShared {
     uint32_t kidx[T];   // its up-slot index
     unsigned long long sum[T];
     unsigned long long tmp64[T / WAVE + 1];
-    uint32_t mark[T];   // per wave: run starts inside the current 64-wedge tile
+    uint8_t mark[4 * T];  // per wave: 4 byte strips, run starts inside each of 4 64-wedge tiles
     uint32_t keys;      // packed hash: keys inserted in the current window
 };
 
@@ -1021,12 +1021,13 @@ __device__ inline void segment_add(uint32_t d, bool ok, uint32_t first, bool las
 template <int T, int U, int PASS, class Agg>
 __device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, RunShared<T> &sh, uint32_t total,
                                  uint32_t nne) {
+    static_assert(U <= 4, "one byte strip per sub-tile");
     const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
     const bool edge = A.mode & MODE_EDGE;
-    // Lanes exchange data through this strip within one wave: relaxed
+    // Lanes exchange data through these strips within one wave: relaxed
     // wavefront-scope atomic accesses, so each store and load is issued as
     // written (LDS runs one wave's operations in order).
-    uint32_t *mark = sh.mark + wv * WAVE;
+    uint8_t *strip = sh.mark + wv * (4 * WAVE);
     const uint64_t le = lanemask_lt() | (1ull << lane);
     // each wave walks one contiguous share of whole 64-wedge tiles, so the
     // held runs move forward with a ballot instead of a search
@@ -1042,41 +1043,77 @@ __device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, 
         uint32_t pidx[U], rel[U], xs[U];
         uint64_t st[U];
         bool ok[U];
+        const uint32_t span_last = wb + U * WAVE - 1 < f1 ? wb + U * WAVE - 1 : f1 - 1;
+        if (span_last < o_end) {
+            // every sub-tile lies inside the held runs: the strips of all
+            // sub-tiles are cleared, marked and read back to back, so their
+            // LDS round trips overlap
+            uint32_t before[U], mk[U], jj[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t base = wb + u * WAVE;
-            st[u] = 0;
-            ok[u] = base + lane < f1;
-            rel[u] = 0;
-            pidx[u] = 0;
-            if (base < f1) {  // wave-uniform
-                const uint32_t last = base + WAVE - 1 < f1 ? base + WAVE - 1 : f1 - 1;
-                if (last >= o_end) {
-                    // reload: the 64 runs from the one holding `base` always
-                    // cover [base, base + 64); that run is found among the
-                    // held ones when it is there
-                    const uint32_t c = (uint32_t)__popcll(__ballot(o <= base));
-                    uint32_t ni;
-                    if (c == 0) ni = last_le(sh.off, 0, nne, base);
-                    else if (c < WAVE) ni = i0 + c - 1;
-                    else ni = last_le(sh.off, i0 + WAVE - 1, nne, base);
-                    i0 = __builtin_amdgcn_readfirstlane(ni);
-                    const uint32_t kk = i0 + lane;
-                    o = kk < nne ? sh.off[kk] : 0xFFFFFFFFu;
-                    dlt = kk < nne ? sh.begin[kk] - o : 0u;
-                    o_end = __builtin_amdgcn_readfirstlane(i0 + WAVE < nne ? sh.off[i0 + WAVE] : total);
-                }
-                const uint32_t f = base + lane;
-                const uint32_t before = (uint32_t)__popcll(__ballot(o <= base));  // held runs starting <= base
-                __hip_atomic_store(&mark[lane], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                if (o > base && o - base < WAVE)
-                    __hip_atomic_store(&mark[o - base], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                const uint64_t starts =
-                    __ballot(__hip_atomic_load(&mark[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) != 0);
-                const uint32_t j = before - 1 + (uint32_t)__popcll(starts & le);
-                pidx[u] = __shfl(dlt, j, WAVE) + f;
-                rel[u] = i0 + j;
+            for (int u = 0; u < U; ++u) {
+                const uint32_t base = wb + u * WAVE;
+                ok[u] = base + lane < f1;
+                before[u] = (uint32_t)__popcll(__ballot(o <= base));
+                __hip_atomic_store(&strip[u * WAVE + lane], (uint8_t)0, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WAVEFRONT);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t base = wb + u * WAVE;
+                if (base < f1 && o > base && o - base < WAVE)
+                    __hip_atomic_store(&strip[u * WAVE + (o - base)], (uint8_t)1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                mk[u] = __hip_atomic_load(&strip[u * WAVE + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t starts = __ballot(mk[u] != 0);
+                jj[u] = before[u] - 1 + (uint32_t)__popcll(starts & le);
                 st[u] = starts;
+                rel[u] = i0 + jj[u];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) pidx[u] = __shfl(dlt, jj[u], WAVE) + wb + u * WAVE + lane;
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t base = wb + u * WAVE;
+                st[u] = 0;
+                ok[u] = base + lane < f1;
+                rel[u] = 0;
+                pidx[u] = 0;
+                if (base < f1) {  // wave-uniform
+                    const uint32_t last = base + WAVE - 1 < f1 ? base + WAVE - 1 : f1 - 1;
+                    if (last >= o_end) {
+                        // reload: the 64 runs from the one holding `base` always
+                        // cover [base, base + 64); that run is found among the
+                        // held ones when it is there
+                        const uint32_t c = (uint32_t)__popcll(__ballot(o <= base));
+                        uint32_t ni;
+                        if (c == 0) ni = last_le(sh.off, 0, nne, base);
+                        else if (c < WAVE) ni = i0 + c - 1;
+                        else ni = last_le(sh.off, i0 + WAVE - 1, nne, base);
+                        i0 = __builtin_amdgcn_readfirstlane(ni);
+                        const uint32_t kk = i0 + lane;
+                        o = kk < nne ? sh.off[kk] : 0xFFFFFFFFu;
+                        dlt = kk < nne ? sh.begin[kk] - o : 0u;
+                        o_end = __builtin_amdgcn_readfirstlane(i0 + WAVE < nne ? sh.off[i0 + WAVE] : total);
+                    }
+                    const uint32_t f = base + lane;
+                    const uint32_t before = (uint32_t)__popcll(__ballot(o <= base));  // held runs starting <= base
+                    __hip_atomic_store(&strip[lane], (uint8_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    if (o > base && o - base < WAVE)
+                        __hip_atomic_store(&strip[o - base], (uint8_t)1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    const uint64_t starts = __ballot(
+                        __hip_atomic_load(&strip[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) != 0);
+                    const uint32_t j = before - 1 + (uint32_t)__popcll(starts & le);
+                    pidx[u] = __shfl(dlt, j, WAVE) + f;
+                    rel[u] = i0 + j;
+                    st[u] = starts;
+                }
             }
         }
 #pragma unroll
@@ -1215,7 +1252,7 @@ __global__ __launch_bounds__(T) void k_count_hash_win(Ranked G, Acc A, const uin
 
 // Per-wave scratch of the wave-independent sweep.
 struct WaveRuns {
-    uint32_t mark[WAVE];             // run starts inside the current 64-wedge tile
+    uint8_t mark[4 * WAVE];          // run starts inside each of 4 64-wedge tiles
     unsigned long long sum[WAVE];    // pass-2 credit of each run
 };
 
@@ -1245,30 +1282,39 @@ __device__ inline void wave_compact(uint32_t cnt, uint32_t first_slot, uint32_t 
 template <int U, int PASS, class Agg>
 __device__ inline void wave_walk(const Ranked &G, const Acc &A, const Agg &agg, WaveRuns &wr, uint32_t o,
                                  uint32_t dlt, uint32_t total, uint32_t lane) {
+    static_assert(U <= 4, "one byte strip per sub-tile");
     const bool edge = A.mode & MODE_EDGE;
     const uint64_t le = lanemask_lt() | (1ull << lane);
     if (PASS == 2) __hip_atomic_store(&wr.sum[lane], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     for (uint32_t wb = 0; wb < total; wb += U * WAVE) {
-        uint32_t pidx[U], rel[U], xs[U];
+        uint32_t pidx[U], rel[U], xs[U], before[U], mk[U];
         bool ok[U];
+        // the strips of all sub-tiles are cleared, marked and read back to
+        // back, so their LDS round trips overlap
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t base = wb + u * WAVE;
             ok[u] = base + lane < total;
-            rel[u] = 0;
-            pidx[u] = 0;
-            if (base < total) {  // wave-uniform
-                const uint32_t before = (uint32_t)__popcll(__ballot(o <= base));
-                __hip_atomic_store(&wr.mark[lane], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                if (o > base && o - base < WAVE)
-                    __hip_atomic_store(&wr.mark[o - base], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-                const uint64_t starts = __ballot(
-                    __hip_atomic_load(&wr.mark[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) != 0);
-                const uint32_t j = before - 1 + (uint32_t)__popcll(starts & le);
-                pidx[u] = __shfl(dlt, j, WAVE) + base + lane;
-                rel[u] = j;
-            }
+            before[u] = (uint32_t)__popcll(__ballot(o <= base));
+            __hip_atomic_store(&wr.mark[u * WAVE + lane], (uint8_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t base = wb + u * WAVE;
+            if (base < total && o > base && o - base < WAVE)
+                __hip_atomic_store(&wr.mark[u * WAVE + (o - base)], (uint8_t)1, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            mk[u] = __hip_atomic_load(&wr.mark[u * WAVE + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t starts = __ballot(mk[u] != 0);
+            rel[u] = before[u] - 1 + (uint32_t)__popcll(starts & le);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) pidx[u] = __shfl(dlt, rel[u], WAVE) + wb + u * WAVE + lane;
 #pragma unroll
         for (int u = 0; u < U; ++u)
             if (ok[u]) xs[u] = G.nbr[pidx[u]];
@@ -1329,15 +1375,18 @@ __device__ inline void wave_endpoint(const Ranked &G, const Acc &A, uint32_t r, 
 // from the top in windows that fit 128 KB of LDS counters (65536 ids with
 // 16-bit counters when the source has fewer than 65536 up-neighbours, since
 // R(x1, x2) <= deg_x1(x1); else 32768 ids).  Within a window the up-slots are
-// walked in one of two ways:
-//   * wave-independent (wave_compact / wave_walk): every wave takes its own
-//     chunks of 64 up-slots and the workgroup synchronises only between the
-//     window's passes -- for sources with at most T up-slots (each lane then
-//     keeps its run and cursor in registers for the whole sweep) and for
-//     sources whose runs are short (fewer than SHORT_RUN wedges per
-//     up-slot), where per-chunk block synchronisation would dominate;
-//   * block-wide chunks of T up-slots (count_item) for long runs, which keeps
-//     whole chunks' wedges in one balanced flat walk.
+// walked in one of three ways:
+//   * sources with at most T up-slots: each thread keeps its up-slot's run and
+//     cursor in registers for the whole sweep; per window the run parts are
+//     laid end to end over the workgroup once (compact_runs) and both passes
+//     walk that one table, every wave on an equal share;
+//   * wave-independent (wave_compact / wave_walk) for larger sources whose
+//     runs are short (fewer than SHORT_RUN wedges per up-slot): every wave
+//     takes its own chunks of 64 up-slots and the workgroup synchronises only
+//     between the window's passes, since per-chunk block synchronisation
+//     would dominate;
+//   * block-wide chunks of T up-slots (count_item) for the other sources,
+//     which keeps whole chunks' wedges in one balanced flat walk.
 constexpr uint64_t SHORT_RUN = 64;
 
 template <int T, int U>
@@ -1392,15 +1441,16 @@ __global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32
                 }
                 __syncthreads();
                 if (small) {
+                    // the window's run parts of all up-slots laid end to end
+                    // over the workgroup, so every wave takes an equal share
                     uint32_t e = s_cur, ev = s_val;
                     if (s_cur < s_pos && s_val >= lo) e = probe_below(G.nbr, s_start, s_cur, s_pos, lo, &ev);
-                    uint32_t o, dlt, kc, nne, total;
-                    wave_compact(e - s_cur, s_start + s_cur, ks, lane, o, dlt, kc, nne, total);
-                    wave_walk<U, 1>(G, A, agg, wr, o, dlt, total, lane);
-                    __syncthreads();
+                    uint32_t total, nne;
+                    compact_runs<T>(ks, s_start, s_cur, e - s_cur, sh, &total, &nne);
+                    walk_runs<T, U, 1>(G, A, agg, sh, total, nne);
                     if (two_pass) {
-                        wave_walk<U, 2>(G, A, agg, wr, o, dlt, total, lane);
-                        wave_flush(G, A, r, k0, wr, kc, nne, lane);
+                        walk_runs<T, U, 2>(G, A, agg, sh, total, nne);
+                        flush_runs<T>(G, A, r, k0, sh, nne);
                     }
                     s_cur = e;
                     s_val = ev;
