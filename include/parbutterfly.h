@@ -124,7 +124,11 @@ typedef enum {
  * the number of centres).  The sparse aggregators then skip hub partners of
  * hub sources.
  *   AUTO   single graphs with at least 2^22 edges, when a cost model (hub
- *          pair paths against compacted centre columns) predicts a gain
+ *          pair paths against compacted centre columns, and for per-vertex
+ *          or per-edge counts the tile's own credit pass) predicts a gain;
+ *          with per-vertex or per-edge counts it is evaluated only when some
+ *          vertex has at least 65536 neighbours (the tile cannot win
+ *          otherwise)
  *   OFF    never
  *   FORCE  every single graph with at least two vertices on the hub side
  * Batched calls never use the tile. */
@@ -179,27 +183,44 @@ typedef struct {
  * used with it. */
 #define PB_FLAG_CACHE_OPT 2u
 
-/* Per-bucket choices of the AUTO aggregation policy.  Sources are bucketed by
- * the bound min(W(x1), candidate range) on their distinct endpoints (W = the
- * source's wedges): light (<= light_max, at most 512), medium (<= medium_max,
- * at most 4096) and heavy (the rest).  Each bucket names its aggregator:
- * light and medium take PB_AGG_LDS_HASH, PB_AGG_RADIX_SORT or
- * PB_AGG_DENSE_HIST; heavy takes any of the three.  pb_autotune fills one
- * from timed runs; opts.tuning = NULL uses the built-in table (hash, hash,
- * dense; 512; 4096). */
+/* Per-bucket choices: aggregator, workgroup size and batch width.  Sources
+ * are bucketed by the bound min(W(x1), candidate range) on their distinct
+ * endpoints (W = the source's wedges): light (<= light_max, at most 512),
+ * medium (<= medium_max, at most 4096) and heavy (the rest).
+ *   *_agg    the bucket's aggregator under PB_AGG_AUTO: PB_AGG_LDS_HASH,
+ *            PB_AGG_RADIX_SORT or PB_AGG_DENSE_HIST
+ *   *_wg     threads per workgroup of the bucket's hash and sort kernels (for
+ *            medium also of the whole-range dense kernel, which takes every
+ *            dense source whose candidate range is at most 4096 ids):
+ *            light 64, 128 or 256 (0 = 64); medium 128, 256 or 512 (0 = 256).
+ *            The heavy bucket's kernels have fixed sizes.
+ *   *_width  batch width: the workgroups one launch of the bucket's kernels
+ *            keeps in flight, each taking work items (sources, or source
+ *            windows) until the list is done; 0 = one workgroup per item
+ * The thresholds and aggregators apply under PB_AGG_AUTO only; workgroup
+ * sizes and widths apply under every aggregation policy.  pb_autotune fills
+ * one from timed runs; opts.tuning = NULL uses the built-in table (hash,
+ * hash, dense; 512; 4096; 64, 256; widths 0). */
 typedef struct {
     uint32_t light_max;
     uint32_t medium_max;
     pb_agg light_agg;
     pb_agg medium_agg;
     pb_agg heavy_agg;
+    uint32_t light_wg;
+    uint32_t medium_wg;
+    uint32_t light_width;
+    uint32_t medium_width;
+    uint32_t heavy_width;
 } pb_tuning;
 
 typedef struct {
     pb_agg agg;                   /* AUTO: per-bucket table; others: forced for every source */
     pb_hub_mode hub;
     uint64_t workspace_cap_bytes; /* 0: no cap beyond the device's free memory */
-    uint32_t wg_size;             /* reserved, 0 */
+    uint32_t wg_size;             /* 0, or threads per workgroup for the light and medium buckets' kernels
+                                   * where they are built for it (light: 64, 128, 256; medium: 128, 256,
+                                   * 512), overriding the tuning table; INVALID_ARG when neither is */
     uint32_t flags;               /* PB_FLAG_* bits, 0 for none */
     pb_stats *stats;              /* optional host pointer, filled by the call */
     const pb_tuning *tuning;      /* optional: the AUTO table, NULL = built-in */
@@ -290,7 +311,7 @@ pb_status pb_count_edge(pb_graph *g, const uint32_t *rank, const pb_opts *opts, 
  * not measured (PB_FLAG_TIMING is ignored; the other stats are filled) and
  * opts->workspace_cap_bytes is ignored.
  * Limits: NO_MEMORY, before any work is queued, when
- * 200 (n_u + n_v) + 84 m + 32 u + 65536 bytes exceed the array (u = m up-slots,
+ * 208 (n_u + n_v) + 84 m + 32 u + 65536 bytes exceed the array (u = m up-slots,
  * 2m with PB_FLAG_CACHE_OPT), that is graphs of up to about 1M edges; NO_MEMORY
  * also when data-dependent tables (the window items of forced hashing, the
  * histograms of sources with 65536 or more up-slots) do not fit beside them.
@@ -398,13 +419,14 @@ pb_status pb_count_batched(pb_graph *const *graphs, const uint32_t *const *ranks
                            const pb_opts *opts, int64_t *const *global_outs, int64_t *const *vertex_outs,
                            int64_t *const *edge_outs, hipStream_t stream);
 
-/* Chooses the per-bucket aggregators (and bucket thresholds) of the AUTO
- * policy by timing whole batched counts of the given sample graphs under each
- * candidate, one bucket at a time (the others held at the current best),
- * `repeats` runs each, fastest median kept.  Writes the table to *out; counts
- * are exact under every candidate, so the table only affects speed.  The
- * timed counts produce the global and per-edge outputs.  Synchronises
- * `stream`.
+/* Fills a pb_tuning by timing whole batched counts of the given sample
+ * graphs (the counting kernels' time, `repeats` runs each, median kept) under
+ * candidate tables, one choice at a time with the others held at the current
+ * best: each bucket's aggregator, the light and medium thresholds, the light
+ * and medium workgroup sizes, then each bucket's batch width (0, 256, 1024,
+ * 4096 workgroups).  Counts are exact under every candidate, so the table
+ * only affects speed.  The timed counts produce the global and per-edge
+ * outputs.  Synchronises `stream`.
  * Errors: as pb_count_batched. */
 pb_status pb_autotune(pb_graph *const *graphs, const uint32_t *const *ranks, uint32_t count, const pb_opts *opts,
                       uint32_t repeats, pb_tuning *out, hipStream_t stream);

@@ -62,12 +62,17 @@ class pb_stats(ctypes.Structure):
 
 class pb_tuning(ctypes.Structure):
     _fields_ = [("light_max", ctypes.c_uint32), ("medium_max", ctypes.c_uint32), ("light_agg", ctypes.c_int),
-                ("medium_agg", ctypes.c_int), ("heavy_agg", ctypes.c_int)]
+                ("medium_agg", ctypes.c_int), ("heavy_agg", ctypes.c_int), ("light_wg", ctypes.c_uint32),
+                ("medium_wg", ctypes.c_uint32), ("light_width", ctypes.c_uint32), ("medium_width", ctypes.c_uint32),
+                ("heavy_width", ctypes.c_uint32)]
 
     def as_dict(self):
         names = {v: k for k, v in AGGS.items()}
         return {"light_max": self.light_max, "medium_max": self.medium_max, "light_agg": names[self.light_agg],
-                "medium_agg": names[self.medium_agg], "heavy_agg": names[self.heavy_agg]}
+                "medium_agg": names[self.medium_agg], "heavy_agg": names[self.heavy_agg],
+                "light_wg": self.light_wg or 64, "medium_wg": self.medium_wg or 256,
+                "light_width": self.light_width, "medium_width": self.medium_width,
+                "heavy_width": self.heavy_width}
 
 
 class pb_opts(ctypes.Structure):
@@ -216,9 +221,10 @@ class Graph:
 
 
 def make_opts(agg="auto", hub="auto", workspace_cap=0, stats=None, timing=False, tuning=None,
-              cache_opt=False) -> pb_opts:
+              cache_opt=False, wg_size=0) -> pb_opts:
     o = pb_opts()
     load_library().pb_opts_default(ctypes.byref(o))
+    o.wg_size = int(wg_size)
     if timing:
         o.flags |= PB_FLAG_TIMING
     if cache_opt:
@@ -385,7 +391,7 @@ def _ptr_array(items):
 
 
 def pb_count_batched(graphs, ranks, want_global=True, want_vertex=False, want_edge=True, agg="auto", hub="auto",
-                     stats: pb_stats | None = None, tuning=None, outs=None, stream=None, timing=False):
+                     stats: pb_stats | None = None, tuning=None, outs=None, stream=None, timing=False, wg_size=0):
     """outs, if given: (global list or None, vertex list or None, edge list or None)."""
     """Counts a batch of graphs in one pass; returns per-graph (global, vertex, edge) lists."""
     torch = _torch()
@@ -399,7 +405,7 @@ def pb_count_batched(graphs, ranks, want_global=True, want_vertex=False, want_ed
     arrs = [None if o is None else _ptr_array([t.data_ptr() for t in o]) for o in outs]
     gp = _ptr_array([g.handle.value for g in graphs])
     rp = _ptr_array([_dev_ptr(r, torch.int32, "rank").value for r in ranks])
-    opts = make_opts(agg, hub, 0, stats, timing, tuning)
+    opts = make_opts(agg, hub, 0, stats, timing, tuning, wg_size=wg_size)
     cast = lambda a: None if a is None else ctypes.cast(a, ctypes.POINTER(ctypes.c_void_p))
     _check(load_library().pb_count_batched(cast(gp), cast(rp), k, ctypes.byref(opts), cast(arrs[0]), cast(arrs[1]),
                                            cast(arrs[2]), _stream(stream)), "pb_count_batched")

@@ -294,12 +294,22 @@ constexpr uint32_t GH_SEG = 65536;      // histogram entries per endpoint-step i
 constexpr uint32_t NXCD = 8;            // accelerator complex dies; workgroup b runs on die b % NXCD
 constexpr uint32_t GH_WG_PER_XCD = 256;
 
-// Aggregator per bucket of the distinct-endpoint bound (light, medium, heavy).
+// Aggregator per bucket of the distinct-endpoint bound (light, medium, heavy),
+// the workgroup size of the light and medium buckets' kernels (hash, sort,
+// and for medium also the whole-range dense kernel) and each bucket's batch
+// width: the workgroups one launch keeps in flight, each taking items until
+// the list is done (0 = one workgroup per item).
 struct Policy {
     uint32_t light_max, medium_max;
     int agg[3];
     bool packed;  // AUTO: heavy-bucket sources with few wedges may take the packed hash
+    uint32_t wg[2] = {64, 256};
+    uint32_t width[3] = {0, 0, 0};
 };
+
+// Workgroup sizes each bucket's kernels are built for.
+__host__ __device__ inline bool light_wg_ok(uint32_t t) { return t == 64 || t == 128 || t == 256; }
+__host__ __device__ inline bool medium_wg_ok(uint32_t t) { return t == 128 || t == 256 || t == 512; }
 
 constexpr uint32_t PH_SLOTS = 32768;          // packed hash: 128 KB of LDS
 constexpr uint32_t PH_FULL = PH_SLOTS / 4 * 3;  // keys at which a window is refused and narrowed
@@ -1815,11 +1825,83 @@ __global__ void k_out_edge(const uint32_t *eslot, const unsigned long long *s, c
     }
 }
 
+// Per-vertex counts from per-edge counts of one graph: each butterfly at x
+// holds exactly two of x's edges, so b(x) = (sum of b(e) over the edges e at
+// x) / 2 (the definitions of Section 2).  U rows are contiguous in the
+// per-edge output; V rows reach it through the V-side CSR's edge ids.  A row
+// of at most VTX_SHORT entries is summed by one thread; a longer one is split
+// into items of VTX_CHUNK entries, each summed by a wave and added to the
+// row's total (cnt[x] = its items, scanned into coff), then halved.
+constexpr uint32_t VTX_SHORT = 64;
+constexpr uint32_t VTX_CHUNK = 2048;
+
+__device__ inline void vertex_row(const int64_t *u_off, const uint32_t *v_off, uint32_t n_u, uint64_t x,
+                                  uint64_t *b, uint64_t *e) {
+    if (x < n_u) {
+        *b = (uint64_t)u_off[x];
+        *e = (uint64_t)u_off[x + 1];
+    } else {
+        *b = v_off[x - n_u];
+        *e = v_off[x - n_u + 1];
+    }
+}
+
+__global__ void k_vtx_short(const int64_t *u_off, const uint32_t *v_off, const uint32_t *v_eid, uint32_t n_u,
+                            uint64_t n, const int64_t *eout, int64_t *vout, uint32_t *cnt) {
+    GRID_STRIDE(x, n) {
+        uint64_t b, e;
+        vertex_row(u_off, v_off, n_u, x, &b, &e);
+        int64_t sum = 0;
+        uint32_t items = 0;
+        if (e - b <= VTX_SHORT) {
+            for (uint64_t i = b; i < e; ++i) sum += eout[x < n_u ? i : v_eid[i]];
+            sum /= 2;
+        } else {
+            items = (uint32_t)((e - b + VTX_CHUNK - 1) / VTX_CHUNK);
+        }
+        vout[x] = sum;  // long rows: 0, the items add to it
+        cnt[x] = items;
+    }
+}
+
+// Item `it` belongs to vertex x with coff[x] <= it < coff[x + 1].
+__global__ __launch_bounds__(256) void k_vtx_long(const int64_t *u_off, const uint32_t *v_off, const uint32_t *v_eid,
+                                                  uint32_t n_u, uint64_t n, const uint32_t *coff, const int64_t *eout,
+                                                  int64_t *vout) {
+    const uint32_t lane = threadIdx.x & (WAVE - 1);
+    const uint32_t items = coff[n];
+    const uint32_t waves = gridDim.x * (blockDim.x / WAVE);
+    for (uint32_t it = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; it < items; it += waves) {
+        uint64_t lo = 0, hi = n;  // coff[lo] <= it < coff[hi]
+        while (hi - lo > 1) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (coff[mid] <= it) lo = mid; else hi = mid;
+        }
+        const uint64_t x = lo;
+        uint64_t b, e;
+        vertex_row(u_off, v_off, n_u, x, &b, &e);
+        const uint64_t cb = b + (uint64_t)(it - coff[x]) * VTX_CHUNK;
+        const uint64_t ce = cb + VTX_CHUNK < e ? cb + VTX_CHUNK : e;
+        int64_t sum = 0;
+        for (uint64_t i = cb + lane; i < ce; i += WAVE) sum += eout[x < n_u ? i : v_eid[i]];
+        sum = wave_sum(sum);
+        if (lane == 0) atomicAdd((unsigned long long *)&vout[x], (unsigned long long)sum);
+    }
+}
+
+__global__ void k_vtx_halve(const uint32_t *cnt, uint64_t n, int64_t *vout) {
+    GRID_STRIDE(x, n)
+        if (cnt[x]) vout[x] /= 2;
+}
+
 constexpr uint32_t MAX_ITEM_GRID = 1u << 20;
 
+// `width` caps the workgroups in flight (0: one per item, up to MAX_ITEM_GRID);
+// the kernels loop over their items with a grid stride.
 template <class K, class... Args>
-void launch_items(K kernel, uint32_t count, uint32_t threads, hipStream_t s, Args... args) {
-    const uint32_t grid = std::min(count, MAX_ITEM_GRID);
+void launch_items(K kernel, uint32_t count, uint32_t threads, uint32_t width, hipStream_t s, Args... args) {
+    const uint32_t cap = width ? std::min(width, MAX_ITEM_GRID) : MAX_ITEM_GRID;
+    const uint32_t grid = std::min(count, cap);
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), 0, s, args..., count);
 }
 
@@ -1844,16 +1926,35 @@ struct CoreIn {
 
 bool policy_from(const pb_opts &o, Policy *p) {
     *p = Policy{LIGHT_D, MEDIUM_D, {PB_AGG_LDS_HASH, PB_AGG_LDS_HASH, PB_AGG_DENSE_HIST}, true};
-    if (o.agg == PB_AGG_AUTO) {
-        if (!o.tuning) return true;
+    if (o.tuning) {
+        // the table's launch shapes apply under every aggregation policy, its
+        // aggregators and thresholds under AUTO only
         const pb_tuning &t = *o.tuning;
-        const pb_agg a[3] = {t.light_agg, t.medium_agg, t.heavy_agg};
-        for (int i = 0; i < 3; ++i)
-            if (a[i] != PB_AGG_LDS_HASH && a[i] != PB_AGG_DENSE_HIST && a[i] != PB_AGG_RADIX_SORT) return false;
-        if (t.light_max > LIGHT_D || t.medium_max > MEDIUM_D || t.light_max > t.medium_max) return false;
-        *p = Policy{t.light_max, t.medium_max, {a[0], a[1], a[2]}, true};
-        return true;
+        const uint32_t lw = t.light_wg ? t.light_wg : 64u, mw = t.medium_wg ? t.medium_wg : 256u;
+        if (!light_wg_ok(lw) || !medium_wg_ok(mw)) return false;
+        p->wg[0] = lw;
+        p->wg[1] = mw;
+        p->width[0] = t.light_width;
+        p->width[1] = t.medium_width;
+        p->width[2] = t.heavy_width;
+        if (o.agg == PB_AGG_AUTO) {
+            const pb_agg a[3] = {t.light_agg, t.medium_agg, t.heavy_agg};
+            for (int i = 0; i < 3; ++i)
+                if (a[i] != PB_AGG_LDS_HASH && a[i] != PB_AGG_DENSE_HIST && a[i] != PB_AGG_RADIX_SORT) return false;
+            if (t.light_max > LIGHT_D || t.medium_max > MEDIUM_D || t.light_max > t.medium_max) return false;
+            p->light_max = t.light_max;
+            p->medium_max = t.medium_max;
+            for (int i = 0; i < 3; ++i) p->agg[i] = a[i];
+        }
     }
+    if (o.wg_size) {
+        // one size for the light and medium buckets, where their kernels have it
+        const bool l = light_wg_ok(o.wg_size), m = medium_wg_ok(o.wg_size);
+        if (!l && !m) return false;
+        if (l) p->wg[0] = o.wg_size;
+        if (m) p->wg[1] = o.wg_size;
+    }
+    if (o.agg == PB_AGG_AUTO) return true;
     if (o.agg != PB_AGG_LDS_HASH && o.agg != PB_AGG_DENSE_HIST && o.agg != PB_AGG_RADIX_SORT) return false;
     p->agg[0] = p->agg[1] = p->agg[2] = o.agg;
     p->packed = false;  // a forced aggregator serves every source
@@ -1913,9 +2014,14 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         }
     } host_free{hpc, !region};
 
+    // With per-edge counts of one graph at hand, per-vertex counts are summed
+    // from them at the end (k_vertex_from_edges) and the counting kernels run
+    // without per-vertex credits (kmode): no scattered vertex atomics.
+    const bool derive_vertex = (mode & MODE_VERTEX) && (mode & MODE_EDGE) && in.v_off && ng == 1;
+    const int kmode = derive_vertex ? mode & ~MODE_VERTEX : mode;
     // Accumulators first so an empty graph still writes zeros.
     unsigned long long *gacc = ws.alloc<unsigned long long>(ng);
-    unsigned long long *vacc = (mode & MODE_VERTEX) ? ws.alloc<unsigned long long>(n) : nullptr;
+    unsigned long long *vacc = (kmode & MODE_VERTEX) ? ws.alloc<unsigned long long>(n) : nullptr;
     // A slot's credit is at most b(e) <= (deg(y) - 1)(deg(x2) - 1), so 32-bit
     // slot counters are exact when max_deg^2 < 2^32.
     const bool slot32 = (uint64_t)in.max_deg * in.max_deg < (uint64_t(1) << 32);
@@ -1946,8 +2052,12 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
     // Hub tile candidates (one graph only): the first HUB_T vertices in rank
     // order of the rank-0 vertex's side.
     uint32_t hub_base = 0, hub_end = 0;
+    // AUTO: with a credit pass and no source that could take the giant-source
+    // path, the tile costs more per hub-pair path than the sparse path (its
+    // cost model could not choose it), so it is not even evaluated
+    const bool hub_auto_ok = m >= HUB_AUTO_MIN_M && (!(kmode & (MODE_VERTEX | MODE_EDGE)) || in.max_deg >= GH_MIN_UPS);
     if (m > 0 && ng == 1 && !copt && !region && opts.hub != PB_HUB_OFF &&
-        (opts.hub == PB_HUB_FORCE || m >= HUB_AUTO_MIN_M)) {
+        (opts.hub == PB_HUB_FORCE || hub_auto_ok)) {
         const bool hub_v = hpc->top >= in.n_u;
         const uint64_t side = hub_v ? n - in.n_u : in.n_u;
         const uint32_t H = (uint32_t)std::min<uint64_t>(HUB_T, side);
@@ -2060,11 +2170,13 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
             hub_roww = ws.alloc<unsigned long long>(HUB_T);
             hub_off = ws.alloc<uint32_t>(HUB_T + 1);
             if (ws.failed) return PB_ERR_NO_MEMORY;
-            const HubIn hin{n, in.n_u, smid, roff, upoff, nbr, hub_base, hub_end, opts.hub == PB_HUB_FORCE, gacc,
-                            vacc};
+            const HubIn hin{n,       in.n_u,  smid,
+                            roff,    upoff,   nbr,
+                            hub_base, hub_end, opts.hub == PB_HUB_FORCE,
+                            (kmode & (MODE_VERTEX | MODE_EDGE)) != 0, gacc, vacc};
             PB_TRY(hub_tile(hin, &pc->hub, HubOut{hub_rank, hub_d, hub_roww}, ws, s, ev.ok ? ev.e[E_HG0] : nullptr,
                             ev.ok ? ev.e[E_HG1] : nullptr, &hub_grid));
-            if (mode & (MODE_VERTEX | MODE_EDGE))
+            if (kmode & (MODE_VERTEX | MODE_EDGE))
                 hipLaunchKernelGGL(k_hub_items, dim3(1), dim3(HUB_T), 0, s, (const uint32_t *)upoff,
                                    (const uint32_t *)hub_rank, hub_end - hub_base, hub_off, pc);
             PB_TRY_HIP(hipGetLastError());
@@ -2132,7 +2244,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         const bool hub_on = plan.hub.on && hub_end > hub_base;
         Ranked G{roff, nbr, upoff, uprun, uplen, smid, cend, gid, in.n_u, (uint32_t)n,
                  hub_on ? hub_base : 0u, hub_on ? hub_end : 0u, copt};
-        Acc A{gacc, vacc, sacc, sacc32, &pc->flags, mode};
+        Acc A{gacc, vacc, sacc, sacc32, &pc->flags, kmode};
 
         // giant sources: per-die item lists, built on the host (one extra
         // synchronisation, only when there are such sources)
@@ -2188,34 +2300,54 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
             if (c) {
                 switch (l) {
                     case L_DENSE_HEAVY:
-                        launch_items(k_count_heavy<1024, 4>, c, 1024, s, G, A, sorted_src[2], sorted_w[2], cur, nxt,
-                                     cval, nval, (const uint32_t *)byte_from);
+                        launch_items(k_count_heavy<1024, 4>, c, 1024, pol.width[2], s, G, A, sorted_src[2], sorted_w[2],
+                                     cur, nxt, cval, nval, (const uint32_t *)byte_from);
                         break;
                     case L_SORT_HEAVY:
-                        launch_items(k_count_sort_heavy<256, 4, SORT_W>, c, 256, s, G, A, sorted_src[1], sorted_w[1],
-                                     cur, nxt, cval, nval);
+                        launch_items(k_count_sort_heavy<256, 4, SORT_W>, c, 256, pol.width[2], s, G, A, sorted_src[1],
+                                     sorted_w[1], cur, nxt, cval, nval);
                         break;
                     case L_HASH_WIN:
-                        launch_items(k_count_hash_win<256, 4, 2 * HASH_WIN>, plan.items, 256, s, G, A,
+                        launch_items(k_count_hash_win<256, 4, 2 * HASH_WIN>, plan.items, 256, pol.width[2], s, G, A,
                                      (const uint2 *)items);
                         break;
-                    case L_HASH_MEDIUM:
-                        launch_items(k_count_hash<256, 4, 2 * MEDIUM_D>, c, 256, s, G, A, list_of(l));
+                    case L_HASH_MEDIUM: {
+                        const uint32_t t = pol.wg[1], w = pol.width[1];
+                        if (t == 128) launch_items(k_count_hash<128, 4, 2 * MEDIUM_D>, c, t, w, s, G, A, list_of(l));
+                        else if (t == 512) launch_items(k_count_hash<512, 4, 2 * MEDIUM_D>, c, t, w, s, G, A, list_of(l));
+                        else launch_items(k_count_hash<256, 4, 2 * MEDIUM_D>, c, 256, w, s, G, A, list_of(l));
                         break;
-                    case L_HASH_LIGHT:
-                        launch_items(k_count_hash<64, 4, 2 * LIGHT_D>, c, 64, s, G, A, list_of(l));
+                    }
+                    case L_HASH_LIGHT: {
+                        const uint32_t t = pol.wg[0], w = pol.width[0];
+                        if (t == 128) launch_items(k_count_hash<128, 4, 2 * LIGHT_D>, c, t, w, s, G, A, list_of(l));
+                        else if (t == 256) launch_items(k_count_hash<256, 4, 2 * LIGHT_D>, c, t, w, s, G, A, list_of(l));
+                        else launch_items(k_count_hash<64, 4, 2 * LIGHT_D>, c, 64, w, s, G, A, list_of(l));
                         break;
-                    case L_SORT_MEDIUM:
-                        launch_items(k_count_sort<256, 4, SORT_W>, c, 256, s, G, A, list_of(l));
+                    }
+                    case L_SORT_MEDIUM: {
+                        const uint32_t t = pol.wg[1], w = pol.width[1];
+                        if (t == 128) launch_items(k_count_sort<128, 4, SORT_W>, c, t, w, s, G, A, list_of(l));
+                        else if (t == 512) launch_items(k_count_sort<512, 4, SORT_W>, c, t, w, s, G, A, list_of(l));
+                        else launch_items(k_count_sort<256, 4, SORT_W>, c, 256, w, s, G, A, list_of(l));
                         break;
-                    case L_SORT_LIGHT:
-                        launch_items(k_count_sort<64, 4, SORT_LIGHT_W>, c, 64, s, G, A, list_of(l));
+                    }
+                    case L_SORT_LIGHT: {
+                        const uint32_t t = pol.wg[0], w = pol.width[0];
+                        if (t == 128) launch_items(k_count_sort<128, 4, SORT_LIGHT_W>, c, t, w, s, G, A, list_of(l));
+                        else if (t == 256) launch_items(k_count_sort<256, 4, SORT_LIGHT_W>, c, t, w, s, G, A, list_of(l));
+                        else launch_items(k_count_sort<64, 4, SORT_LIGHT_W>, c, 64, w, s, G, A, list_of(l));
                         break;
-                    case L_DENSE_SMALL:
-                        launch_items(k_count_dense_src<256, 4, SMALL_WIN>, c, 256, s, G, A, list_of(l));
+                    }
+                    case L_DENSE_SMALL: {
+                        const uint32_t t = pol.wg[1], w = pol.width[1];
+                        if (t == 128) launch_items(k_count_dense_src<128, 4, SMALL_WIN>, c, t, w, s, G, A, list_of(l));
+                        else if (t == 512) launch_items(k_count_dense_src<512, 4, SMALL_WIN>, c, t, w, s, G, A, list_of(l));
+                        else launch_items(k_count_dense_src<256, 4, SMALL_WIN>, c, 256, w, s, G, A, list_of(l));
                         break;
+                    }
                     case L_HASH_PACKED:
-                        launch_items(k_count_phash<1024, 4>, c, 1024, s, G, A, sorted_src[sorted_slot(l)],
+                        launch_items(k_count_phash<1024, 4>, c, 1024, pol.width[2], s, G, A, sorted_src[sorted_slot(l)],
                                      sorted_w[sorted_slot(l)], cur, nxt, cval, nval);
                         break;
                     case L_DENSE_GLOBAL: {
@@ -2223,7 +2355,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
                         PB_TRY(fill<uint32_t>(gh_hist, 0u, gh_total, s));
                         k_gh_walk<256, 4, 1><<<grid, 256, 0, s>>>(G, A, d_gh_src, d_gh_items, d_gh_xoff, gh_hist);
                         k_gh_endpoint<256><<<grid, 256, 0, s>>>(G, A, d_gh_src, d_gh_eitems, d_gh_exoff, gh_hist);
-                        if (mode & (MODE_VERTEX | MODE_EDGE))
+                        if (kmode & (MODE_VERTEX | MODE_EDGE))
                             k_gh_walk<256, 4, 2><<<grid, 256, 0, s>>>(G, A, d_gh_src, d_gh_items, d_gh_xoff, gh_hist);
                         break;
                     }
@@ -2232,7 +2364,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
             }
             mark(2 + l);
         }
-        if (hub_on && (mode & (MODE_VERTEX | MODE_EDGE)) && plan.hub_items) {
+        if (hub_on && (kmode & (MODE_VERTEX | MODE_EDGE)) && plan.hub_items) {
             hub_pass_ran = true;
             if (ev.ok) ev.ok = hipEventRecord(ev.e[E_HP0], s) == hipSuccess;
             k_count_hub_pass<256, 4><<<dim3(std::min(plan.hub_items, HUB_PASS_GRID)), dim3(256), 0, s>>>(
@@ -2246,11 +2378,21 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
     }
 
     // 5. outputs -------------------------------------------------------------------
-    if (mode & MODE_VERTEX)
-        hipLaunchKernelGGL(k_out_vertex, dim3(grid_for(n)), dim3(256), 0, s, in.rank, smid, m ? vacc : nullptr, n,
-                           in.n_u, in.bl, out);
     if ((mode & MODE_EDGE) && m)
         hipLaunchKernelGGL(k_out_edge, dim3(grid_for(m)), dim3(256), 0, s, eslot, sacc, sacc32, m, in.bl, out);
+    if (derive_vertex) {
+        uint32_t *vcnt = ws.alloc<uint32_t>(n + 1), *vcoff = ws.alloc<uint32_t>(n + 1);
+        if (ws.failed) return PB_ERR_NO_MEMORY;
+        const int64_t *eo = out.eout;
+        hipLaunchKernelGGL(k_vtx_short, dim3(grid_for(n)), dim3(256), 0, s, in.u_off, in.v_off, in.v_eid, in.n_u, n,
+                           eo, out.vout, vcnt);
+        PB_TRY((scan_exclusive<uint32_t, uint32_t>(vcnt, vcoff, n, vcoff + n, ws)));
+        hipLaunchKernelGGL(k_vtx_long, dim3(4096), dim3(256), 0, s, in.u_off, in.v_off, in.v_eid, in.n_u, n,
+                           (const uint32_t *)vcoff, eo, out.vout);
+        hipLaunchKernelGGL(k_vtx_halve, dim3(grid_for(n)), dim3(256), 0, s, (const uint32_t *)vcnt, n, out.vout);
+    } else if (mode & MODE_VERTEX)
+        hipLaunchKernelGGL(k_out_vertex, dim3(grid_for(n)), dim3(256), 0, s, in.rank, smid, m ? vacc : nullptr, n,
+                           in.n_u, in.bl, out);
     if (mode & MODE_GLOBAL) hipLaunchKernelGGL(k_out_global, dim3(grid_for(ng)), dim3(256), 0, s, gacc, ng, out);
     PB_TRY_HIP(hipGetLastError());
     mark(2 + NLISTS);
@@ -2466,14 +2608,15 @@ NoallocDevice noalloc_devices[NOALLOC_MAX_DEVICES];
 // a graph of n vertices and m edges, before the data-dependent tables (window
 // items of forced hashing, giant-source histograms), which are checked when
 // they are sized.  Per vertex: 4-byte rank, side, offset and degree tables,
-// the 8-byte vertex credits and the work lists (196 bytes in all).  Per
+// the 8-byte vertex credits, the work lists and the per-vertex derivation's
+// item counts (204 bytes in all).  Per
 // up-slot: run start and length, four cursors and the wedge scan (32 bytes;
 // m up-slots, 2m with the cache-optimised order).  Per edge: sort keys and
 // values in two buffers (48 bytes), the ranked lists and slot table (16),
 // slot credits (16) and the sort histograms; plus block rounding.
 inline uint64_t noalloc_need(uint64_t n, uint64_t m, bool copt) {
     const uint64_t ups = copt ? 2 * m : m;
-    return 200 * n + 84 * m + 32 * ups + (uint64_t(1) << 16);
+    return 208 * n + 84 * m + 32 * ups + (uint64_t(1) << 16);
 }
 
 }  // namespace
@@ -2622,7 +2765,30 @@ pb_status pb_autotune(pb_graph *const *graphs, const uint32_t *const *ranks, uin
         PB_TRY(time_policy(p, &ms));
         if (ms < best_ms) { best = p; best_ms = ms; }
     }
-    *out = pb_tuning{best.light_max, best.medium_max, (pb_agg)best.agg[0], (pb_agg)best.agg[1], (pb_agg)best.agg[2]};
+    // workgroup sizes of the light and medium buckets' kernels
+    const uint32_t wg_opts[2][3] = {{64, 128, 256}, {128, 256, 512}};
+    for (int bkt = 0; bkt < 2; ++bkt)
+        for (uint32_t t : wg_opts[bkt]) {
+            if (t == best.wg[bkt]) continue;
+            Policy p = best;
+            p.wg[bkt] = t;
+            float ms;
+            PB_TRY(time_policy(p, &ms));
+            if (ms < best_ms) { best = p; best_ms = ms; }
+        }
+    // batch width of each bucket's launches
+    const uint32_t width_opts[] = {0, 256, 1024, 4096};
+    for (int bkt = 0; bkt < 3; ++bkt)
+        for (uint32_t wdt : width_opts) {
+            if (wdt == best.width[bkt]) continue;
+            Policy p = best;
+            p.width[bkt] = wdt;
+            float ms;
+            PB_TRY(time_policy(p, &ms));
+            if (ms < best_ms) { best = p; best_ms = ms; }
+        }
+    *out = pb_tuning{best.light_max, best.medium_max, (pb_agg)best.agg[0], (pb_agg)best.agg[1], (pb_agg)best.agg[2],
+                     best.wg[0],      best.wg[1],      best.width[0],      best.width[1],      best.width[2]};
     return PB_OK;
 }
 

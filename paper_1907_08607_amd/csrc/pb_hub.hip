@@ -34,11 +34,23 @@ constexpr uint32_t ROWB = KC + 16;         // bytes per tile row; the pad spread
 constexpr uint32_t GEMM_THREADS = 1024;    // 16 waves: one 64x64 block of D each (upper ones compute)
 constexpr uint32_t GEMM_MAX_GRID = 256;    // one workgroup per compute unit
 
-// AUTO cost model, nanoseconds: the sparse path spends about NS_PER_PATH per
-// hub-pair wedge in its first pass; the tile about NS_PER_COL per column.
-constexpr double NS_PER_PATH = 0.1;
+// AUTO cost model, nanoseconds, fitted to on/off runs of the tile on both
+// single-graph workloads (all three outputs):
+//   sparse path, per hub-pair path (a wedge the tile would take over), both
+//   passes: NS_SPARSE in LDS windows, NS_SPARSE_GIANT when a hub source has
+//   at least GIANT_UPS up-slots (its wedges go to the global histogram); one
+//   pass (total only) costs half;
+//   tile: NS_FIXED + NS_FIXED_VERTEX per vertex (column marking and
+//   compaction) + NS_PER_COL per compacted column (the matrix-core product),
+//   plus NS_HUB_PASS per path for the hub pairs' credit pass when per-vertex
+//   or per-edge counts are wanted.
+constexpr double NS_SPARSE = 0.0075;
+constexpr double NS_SPARSE_GIANT = 0.06;
+constexpr double NS_FIXED = 100000.0;
+constexpr double NS_FIXED_VERTEX = 0.035;
 constexpr double NS_PER_COL = 0.1;
-constexpr double NS_FIXED = 50000.0;
+constexpr double NS_HUB_PASS = 0.04;
+constexpr uint32_t GIANT_UPS = 65536;  // the planner's global-histogram threshold
 
 #define HUB_GRID_STRIDE(i, n)                                                       \
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); \
@@ -89,12 +101,19 @@ __global__ void k_hub_mark(HubIn in, uint32_t *keep, HubCounters *hc) {
     if ((threadIdx.x & (WAVE - 1)) == 0 && paths) atomicAdd(&hc->paths, paths);
 }
 
-__global__ void k_hub_decide(const uint32_t *cols, HubCounters *hc, bool force) {
+__global__ void k_hub_decide(const uint32_t *cols, const uint32_t *hub_rank, HubIn in, HubCounters *hc) {
     const uint32_t c = *cols;
     hc->cols = c;
-    const double dense = NS_FIXED + NS_PER_COL * (double)c;
-    const double sparse = NS_PER_PATH * (double)hc->paths;
-    hc->on = (force || sparse > dense) ? 1u : 0u;
+    bool giant = false;
+    for (uint32_t i = 0; i < in.end - in.base; ++i) {
+        const uint32_t r = hub_rank[i];
+        giant = giant || in.upoff[r + 1] - in.upoff[r] >= GIANT_UPS;
+    }
+    const double paths = (double)hc->paths;
+    const double dense = NS_FIXED + NS_FIXED_VERTEX * (double)in.n + NS_PER_COL * (double)c +
+                         (in.two_pass ? NS_HUB_PASS * paths : 0.0);
+    const double sparse = (giant ? NS_SPARSE_GIANT : NS_SPARSE) * paths * (in.two_pass ? 1.0 : 0.5);
+    hc->on = (in.force || sparse > dense) ? 1u : 0u;
 }
 
 __global__ void k_hub_fill(HubIn in, const uint32_t *keep, const uint32_t *coff, const HubCounters *hc,
@@ -138,12 +157,16 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_hub_gemm(const uint32_t *cstar
 #pragma unroll
             for (int q = 0; q < 16; ++q) acc[a][b][q] = 0;
 
-    for (uint32_t c0 = blockIdx.x * KC; c0 < C; c0 += gridDim.x * KC) {
+    // the tiles are cleared once; after each chunk every thread clears the
+    // bytes it set, so a chunk costs its neighbours, not 73 KB of stores
+    {
         uint4 *za = reinterpret_cast<uint4 *>(tA), *zb = reinterpret_cast<uint4 *>(tB);
         for (uint32_t i = tid; i < HUB_T * ROWB / 16; i += GEMM_THREADS) {
             za[i] = make_uint4(0, 0, 0, 0);
             zb[i] = make_uint4(0, 0, 0, 0);
         }
+    }
+    for (uint32_t c0 = blockIdx.x * KC; c0 < C; c0 += gridDim.x * KC) {
         if (tid < KC) {
             const uint32_t c = c0 + tid;
             if (c < C) {
@@ -182,6 +205,18 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_hub_gemm(const uint32_t *cstar
 #pragma unroll
                     for (int tj = 0; tj < 2; ++tj)
                         acc[ti][tj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+        {
+            const uint32_t col = tid >> 3, sub = tid & 7;
+            const uint32_t len = ml[col], st = ms[col];
+            for (uint32_t j = sub; j < len; j += 8) {
+                const uint32_t h = nbr[st + j] - base;
+                if (h < HUB_T) {
+                    tB[h * ROWB + col] = 0;
+                    tA[h * ROWB + col] = 0;
+                }
             }
         }
         __syncthreads();
@@ -255,7 +290,8 @@ pb_status hub_tile(const HubIn &in, HubCounters *hc, const HubOut &out, Workspac
     hipLaunchKernelGGL(k_hub_mark, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, in, keep, hc);
     PB_TRY_HIP(hipGetLastError());
     PB_TRY((scan_exclusive<uint32_t, uint32_t>(keep, coff, n, coff + n, ws)));
-    hipLaunchKernelGGL(k_hub_decide, dim3(1), dim3(1), 0, s, (const uint32_t *)(coff + n), hc, in.force);
+    hipLaunchKernelGGL(k_hub_decide, dim3(1), dim3(1), 0, s, (const uint32_t *)(coff + n),
+                       (const uint32_t *)out.hub_rank, in, hc);
     hipLaunchKernelGGL(k_hub_fill, dim3(grid_for(n)), dim3(256), 0, s, in, keep, coff, hc, cstart, clen, ca);
     PB_TRY_HIP(hipGetLastError());
     if (ev0) PB_TRY_HIP(hipEventRecord(ev0, s));

@@ -243,6 +243,7 @@ struct HubIn {
     const uint32_t *smid, *roff, *upoff, *nbr;  // ranked CSR (rank-indexed)
     uint32_t base, end;                         // hub side-major ids
     bool force;                                 // skip the cost model
+    bool two_pass;                              // per-vertex or per-edge counts: the hub pairs need a credit pass
     unsigned long long *g;                      // global accumulator (one graph)
     unsigned long long *v;                      // per-vertex accumulator by smid, or null
 };

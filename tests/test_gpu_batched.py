@@ -90,6 +90,8 @@ def test_autotune_table_is_valid_and_exact():
     d = t.as_dict()
     assert d["light_max"] <= 512 and d["medium_max"] <= 4096 and d["light_max"] <= d["medium_max"]
     assert d["light_agg"] in ("hash", "sort", "dense") and d["heavy_agg"] in ("hash", "sort", "dense")
+    assert d["light_wg"] in (64, 128, 256) and d["medium_wg"] in (128, 256, 512)
+    assert all(d[k] in (0, 256, 1024, 4096) for k in ("light_width", "medium_width", "heavy_width"))
     gl, ve, ed = pb.pb_count_batched(Gs, ranks, True, True, True, tuning=t)
     for i, g in enumerate(gs):
         want = oracle.count(g)
@@ -155,5 +157,40 @@ def test_mid_size_batch_matches_oracle(agg):
         assert st.wedges_hash == st.wedges and st.window_items > 0
     if agg == "sort":
         assert st.wedges_sort == st.wedges
+    for G in Gs:
+        G.close()
+
+
+def test_every_workgroup_size_and_batch_width_is_exact():
+    """Every launch shape the tuning table can name counts exactly: each
+    bucket's workgroup sizes and batch widths, one at a time, under the AUTO
+    table and with each aggregator forced, and the opts.wg_size override."""
+    gs = small_batch(5, 12) + mid_batch(23, 3)
+    want = [oracle.count(g) for g in gs]
+    Gs, ranks = to_gpu(gs)
+
+    def check(**kw):
+        gl, ve, ed = pb.pb_count_batched(Gs, ranks, True, True, True, **kw)
+        torch.cuda.synchronize()
+        for i, (g, (wg, wv, we)) in enumerate(zip(gs, want)):
+            assert int(gl[i].cpu()[0]) == wg, (kw, i)
+            assert np.array_equal(ve[i].cpu().numpy(), wv), (kw, i)
+            if g.m:
+                assert np.array_equal(ed[i].cpu().numpy()[:g.m], we), (kw, i)
+
+    H, S, D = pb.AGGS["hash"], pb.AGGS["sort"], pb.AGGS["dense"]
+    for lw in (64, 128, 256):
+        for mw in (128, 256, 512):
+            for aggs in ((H, H, D), (S, S, S), (D, D, H)):
+                check(tuning=pb.pb_tuning(512, 4096, *aggs, lw, mw, 0, 0, 0))
+    for width in (256, 1024, 4096):
+        check(tuning=pb.pb_tuning(512, 4096, H, H, D, 0, 0, width, width, width))
+        for agg in ("hash", "sort", "dense"):
+            check(agg=agg, tuning=pb.pb_tuning(512, 4096, H, H, D, 128, 512, width, width, width))
+    for wg in (64, 128, 256, 512):
+        check(wg_size=wg)
+    with pytest.raises(pb.PBError) as e:
+        pb.pb_count_batched(Gs, ranks, wg_size=96)
+    assert e.value.status == -1
     for G in Gs:
         G.close()
