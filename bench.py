@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="powerlaw_50m",
                     choices=["powerlaw_50m", "hub_100m", "er_1k", "batch", "serve", "copy", "approx", "choose", "tip",
-                             "wing"])
+                             "wing", "cpu_full"])
     ap.add_argument("--p", type=float, default=0.1, help="approx: sampling rate")
     ap.add_argument("--tip-scale", type=float, default=0.05, help="tip: size of the power-law graph")
     ap.add_argument("--wing-scale", type=float, default=0.003, help="wing: size of the power-law graph")
@@ -162,6 +162,24 @@ def cpu_baseline(g, wedges, target_s):
                       f"of its endpoint side: {t:.1f} s measured, x{stride} = {est:.1f} s estimated full run; "
                       f"wedges = the GPU ordering's wedge count",
             "est_full_s": est}
+
+
+def run_cpu_full(args):
+    """Checks the sampled CPU baseline once (host only, no GPU): the oracle's
+    full single-threaded run on the power-law workload next to the estimate
+    the cpu_baseline leg makes from its sample."""
+    import oracle
+    from paper_1907_08607_amd import graphgen as gg
+    g = gg.workload_powerlaw_50m(seed=2, scale=args.scale)
+    print("[bench] full single-threaded oracle run", file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    oracle.count(g)
+    full = time.perf_counter() - t
+    est = cpu_baseline(g, 1, args.cpu_target_s)
+    print(json.dumps({"metric": "oracle seconds, full run vs sampled estimate", "workload": "chung_lu_powerlaw",
+                      "m": g.m, "full_s": full, "estimate_s": est["est_full_s"],
+                      "full_over_estimate": full / est["est_full_s"], "sample": est["sample"], "cores": 1,
+                      **host_info()}), flush=True)
 
 
 def run_copy(args):
@@ -621,6 +639,8 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the counting path "
               "runs on a single device, with no collectives", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "cpu_full":
+        return run_cpu_full(args)
     import numpy as np
     import torch
 

@@ -281,7 +281,7 @@ __host__ __device__ inline int sorted_slot(int list) {
 constexpr uint32_t LIGHT_D = 512;       // 1-wave hash: 1024 slots
 constexpr uint32_t MEDIUM_D = 4096;     // 256-thread hash: 8192 slots
 constexpr uint32_t SMALL_WIN = 4096;    // dense range of the 256-thread whole-range dense kernel
-constexpr uint32_t WIN_WORDS = 32768;   // 128 KB of LDS counters in the heavy dense kernel
+constexpr uint32_t WIN_WORDS = 32704;   // about 128 KB of LDS counters in the heavy dense kernel
 constexpr uint32_t HASH_WIN = 4096;     // candidate window of a hash item over a heavy source
 constexpr uint32_t SORT_LIGHT_W = 512;  // wedges sorted by the 1-wave sort kernel
 constexpr uint32_t SORT_W = 2048;       // wedges sorted by the 256-thread sort kernels
@@ -961,6 +961,23 @@ struct RunShared {
     uint32_t keys;      // packed hash: keys inserted in the current window
 };
 
+// The run table of the heavy dense kernel: chunks of 2T up-slots, two per
+// thread, so a source's window takes half the chunk phases.  It fits beside
+// the 128 KB window by narrower fields: run sums in 32 bits (a run part's sum
+// of R - 1 over distinct endpoints x2 is below m) and up-slot indices
+// relative to the source's first (a heavy source has fewer than 65536).
+template <int T>
+struct HeavyRuns {
+    static constexpr int N = 2 * T;
+    unsigned long long tmp64[T / WAVE + 1];
+    uint32_t sum[N];
+    uint32_t off[N];
+    uint32_t begin[N];
+    uint16_t kidx[N];
+    uint8_t mark[4 * T];
+    uint32_t keys;
+};
+
 // Largest i in [lo, n) with off[i] <= f (off strictly increasing, off[lo] <= f).
 __device__ inline uint32_t last_le(const uint32_t *off, uint32_t lo, uint32_t n, uint32_t f) {
     uint32_t hi = n;
@@ -1019,6 +1036,13 @@ __device__ inline void segment_add(uint32_t d, bool ok, uint32_t first, bool las
         __hip_atomic_fetch_add(dst, (unsigned long long)seg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+__device__ inline void segment_add(uint32_t d, bool ok, uint32_t first, bool last, uint32_t *dst, uint32_t lane) {
+    const uint32_t incl = wave_inclusive_sum(ok ? d : 0u);
+    const uint32_t before = __shfl(incl, first ? first - 1 : 0, WAVE);
+    const uint32_t seg = incl - (first ? before : 0u);
+    if (ok && last && seg) __hip_atomic_fetch_add(dst, seg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Walks the compacted wedge sequence of one chunk (see count_item): pass 1
 // inserts each x2 into the aggregator; pass 2 credits R-1 to the slot
 // (y -> x2) and sums it per run into sh.sum.
@@ -1028,8 +1052,8 @@ __device__ inline void segment_add(uint32_t d, bool ok, uint32_t first, bool las
 // runs starting inside the tile are marked in a 64-byte LDS strip and
 // gathered with one ballot; a lane's run is then the run holding the tile's
 // first wedge plus the number of marked starts up to its own position.
-template <int T, int U, int PASS, class Agg>
-__device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, RunShared<T> &sh, uint32_t total,
+template <int T, int U, int PASS, class Agg, class SH>
+__device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, SH &sh, uint32_t total,
                                  uint32_t nne) {
     static_assert(U <= 4, "one byte strip per sub-tile");
     const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
@@ -1168,8 +1192,8 @@ __device__ inline void flush_runs(const Ranked &G, const Acc &A, uint32_t r, uin
 
 // The endpoint step after pass 1: C(R,2) per pair into the total and, for
 // per-vertex counts, into both endpoints.
-template <int T, class Agg>
-__device__ inline void endpoint_credit(const Ranked &G, const Acc &A, uint32_t r, const Agg &agg, RunShared<T> &sh) {
+template <int T, class Agg, class SH>
+__device__ inline void endpoint_credit(const Ranked &G, const Acc &A, uint32_t r, const Agg &agg, SH &sh) {
     unsigned long long local = 0;
     const bool vert = A.mode & MODE_VERTEX;
     agg.for_each([&](uint32_t key, uint32_t cc) {
@@ -1256,6 +1280,96 @@ __global__ __launch_bounds__(T) void k_count_hash_win(Ranked G, Acc A, const uin
         const uint32_t hi = side_end - lo > HASH_WIN ? lo + HASH_WIN : side_end;
         count_item<T, U>(G, A, r, agg, SearchRange{lo, hi}, sh, A.passes());
     }
+}
+
+// compact_runs for a HeavyRuns table, one run per thread, up-slot indices
+// relative to k0.
+template <int T>
+__device__ inline void compact_rel(uint32_t k, uint32_t k0, uint32_t start, uint32_t a, uint32_t cnt,
+                                   HeavyRuns<T> &sh, uint32_t *total, uint32_t *nne) {
+    const unsigned long long packed = ((unsigned long long)(cnt > 0) << 32) | cnt;
+    unsigned long long tot64;
+    const unsigned long long pre = block_exclusive_sum<T>(packed, sh.tmp64, &tot64);
+    *total = (uint32_t)tot64;
+    *nne = (uint32_t)(tot64 >> 32);
+    if (cnt > 0) {
+        const uint32_t ci = (uint32_t)(pre >> 32);
+        sh.off[ci] = (uint32_t)pre;
+        sh.begin[ci] = start + a;
+        sh.kidx[ci] = (uint16_t)(k - k0);
+        sh.sum[ci] = 0;
+    }
+    __syncthreads();
+}
+
+// The same with two runs per thread (entries j = 0, 1 in thread order).
+template <int T>
+__device__ inline void compact_two(const uint32_t *k, uint32_t k0, const uint32_t *start, const uint32_t *a,
+                                   const uint32_t *cnt, HeavyRuns<T> &sh, uint32_t *total, uint32_t *nne) {
+    const unsigned long long packed = ((unsigned long long)((cnt[0] > 0) + (cnt[1] > 0)) << 32) | (cnt[0] + cnt[1]);
+    unsigned long long tot64;
+    const unsigned long long pre = block_exclusive_sum<T>(packed, sh.tmp64, &tot64);
+    *total = (uint32_t)tot64;
+    *nne = (uint32_t)(tot64 >> 32);
+    uint32_t ci = (uint32_t)(pre >> 32), off = (uint32_t)pre;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+        if (cnt[j] > 0) {
+            sh.off[ci] = off;
+            sh.begin[ci] = start[j] + a[j];
+            sh.kidx[ci] = (uint16_t)(k[j] - k0);
+            sh.sum[ci] = 0;
+            ++ci;
+            off += cnt[j];
+        }
+    __syncthreads();
+}
+
+template <int T>
+__device__ inline void flush_rel(const Ranked &G, const Acc &A, uint32_t r, HeavyRuns<T> &sh, uint32_t nne) {
+    for (uint32_t i = threadIdx.x; i < nne; i += T) {
+        const uint32_t sm = sh.sum[i];
+        if (sm) {
+            const uint32_t up = G.roff[r] + sh.kidx[i];  // slot (r -> y)
+            if (A.mode & MODE_VERTEX) atomicAdd(&A.v[G.nbr[up]], (unsigned long long)sm);
+            if (A.mode & MODE_EDGE) A.slot_add(up, sm);
+        }
+    }
+    __syncthreads();
+}
+
+// count_item over chunks of 2T up-slots (thread t takes c + t and c + T + t).
+template <int T, int U, class Agg, class Range>
+__device__ void count_item_two(const Ranked &G, const Acc &A, uint32_t r, const Agg &agg, const Range &range,
+                               HeavyRuns<T> &sh, int passes) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t k0 = G.upoff[r], k1 = G.upoff[r + 1];
+    agg.init();
+    __syncthreads();
+    const bool credit = A.mode & (MODE_VERTEX | MODE_EDGE);
+    for (int pass = 1; pass <= passes; ++pass) {
+        for (uint32_t c = k0; c < k1; c += 2 * T) {
+            uint32_t k[2], a[2] = {0, 0}, cnt[2] = {0, 0}, start[2] = {0, 0};
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                k[j] = c + j * T + tid;
+                if (k[j] < k1) {
+                    start[j] = G.uprun[k[j]];
+                    range(G, pass, k[j], start[j], G.uplen[k[j]], a[j], cnt[j]);
+                }
+            }
+            uint32_t total, nne;
+            compact_two<T>(k, k0, start, a, cnt, sh, &total, &nne);
+            if (pass == 1) walk_runs<T, U, 1>(G, A, agg, sh, total, nne);
+            else if (credit) walk_runs<T, U, 2>(G, A, agg, sh, total, nne);
+            if (pass == 2) flush_rel<T>(G, A, r, sh, nne);
+        }
+        if (pass == 1) {
+            agg.finalize();  // dense windows are never refused
+            endpoint_credit<T>(G, A, r, agg, sh);
+        }
+    }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------- wave-independent heavy sweep
@@ -1382,9 +1496,9 @@ __device__ inline void wave_endpoint(const Ranked &G, const Acc &A, uint32_t r, 
 }
 
 // Heavy sources: one workgroup per source sweeps the source's candidate range
-// from the top in windows that fit 128 KB of LDS counters (65536 ids with
-// 16-bit counters when the source has fewer than 65536 up-neighbours, since
-// R(x1, x2) <= deg_x1(x1); else 32768 ids).  Within a window the up-slots are
+// from the top in windows that fit about 128 KB of LDS counters (65408 ids
+// with 16-bit counters when the source has fewer than 65536 up-neighbours,
+// since R(x1, x2) <= deg_x1(x1); else 32704 ids).  Within a window the up-slots are
 // walked in one of three ways:
 //   * sources with at most T up-slots: each thread keeps its up-slot's run and
 //     cursor in registers for the whole sweep; per window the run parts are
@@ -1395,8 +1509,9 @@ __device__ inline void wave_endpoint(const Ranked &G, const Acc &A, uint32_t r, 
 //     takes its own chunks of 64 up-slots and the workgroup synchronises only
 //     between the window's passes, since per-chunk block synchronisation
 //     would dominate;
-//   * block-wide chunks of T up-slots (count_item) for the other sources,
-//     which keeps whole chunks' wedges in one balanced flat walk.
+//   * block-wide chunks of 2T up-slots, two per thread (count_item_two), for
+//     the other sources, which keeps whole chunks' wedges in one balanced
+//     flat walk.
 constexpr uint64_t SHORT_RUN = 64;
 
 template <int T, int U>
@@ -1404,9 +1519,9 @@ __global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32
                                                    uint32_t *cur, uint32_t *nxt, uint32_t *cval, uint32_t *nval,
                                                    const uint32_t *byte_from, uint32_t count) {
     constexpr uint32_t NW = T / WAVE;
-    static_assert(sizeof(WaveRuns) * NW <= sizeof(RunShared<T>), "wave scratch shares the run table's LDS");
+    static_assert(sizeof(WaveRuns) * NW <= sizeof(HeavyRuns<T>), "wave scratch shares the run table's LDS");
     __shared__ uint32_t words[WIN_WORDS];
-    __shared__ RunShared<T> sh;
+    __shared__ HeavyRuns<T> sh;
     const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid / WAVE;
     WaveRuns &wr = reinterpret_cast<WaveRuns *>(&sh)[wv];
     const bool two_pass = A.mode & (MODE_VERTEX | MODE_EDGE);
@@ -1443,7 +1558,7 @@ __global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32
             const DenseAgg<T> agg{words, lo, hi - lo, half, A.err, byte, nib};
             const CursorRange rng{cur, nxt, cval, nval, lo, first, two_pass};
             if (!waves) {
-                count_item<T, U>(G, A, r, agg, rng, sh, A.passes());
+                count_item_two<T, U>(G, A, r, agg, rng, sh, A.passes());
             } else {
                 {
                     const uint32_t c = agg.cs(), nwords = (hi - lo + (1u << c) - 1) >> c;
@@ -1456,11 +1571,11 @@ __global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32
                     uint32_t e = s_cur, ev = s_val;
                     if (s_cur < s_pos && s_val >= lo) e = probe_below(G.nbr, s_start, s_cur, s_pos, lo, &ev);
                     uint32_t total, nne;
-                    compact_runs<T>(ks, s_start, s_cur, e - s_cur, sh, &total, &nne);
+                    compact_rel<T>(ks, k0, s_start, s_cur, e - s_cur, sh, &total, &nne);
                     walk_runs<T, U, 1>(G, A, agg, sh, total, nne);
                     if (two_pass) {
                         walk_runs<T, U, 2>(G, A, agg, sh, total, nne);
-                        flush_runs<T>(G, A, r, k0, sh, nne);
+                        flush_rel<T>(G, A, r, sh, nne);
                     }
                     s_cur = e;
                     s_val = ev;
@@ -1571,12 +1686,44 @@ __global__ __launch_bounds__(T) void k_count_phash(Ranked G, Acc A, const uint32
     __shared__ RunShared<T> sh;
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
         const uint32_t r = list[i];
-        const uint32_t cbits = bit_width(G.upoff[r + 1] - G.upoff[r]);
+        const uint32_t k0 = G.upoff[r], k1 = G.upoff[r + 1];
+        const uint32_t cbits = bit_width(k1 - k0);
         const uint32_t lo_min = G.lo(r);
         uint32_t hi = G.cend[r];
         const uint64_t w = wsrc[i] ? wsrc[i] : 1;
         const uint64_t guess = (uint64_t)(hi - lo_min) * PH_TARGET / w;
         uint32_t width = guess < 1 ? 1u : guess > hi - lo_min ? hi - lo_min : (uint32_t)guess;
+        if (k1 - k0 <= (uint32_t)T) {
+            // one up-slot per thread, its cursor in registers (committed once
+            // a window has been counted); one compaction serves both passes
+            const uint32_t k = k0 + threadIdx.x;
+            const bool have = k < k1;
+            const uint32_t start = have ? G.uprun[k] : 0u, pos = have ? G.uplen[k] : 0u;
+            uint32_t sc = 0, sv = pos ? G.nbr[start] : 0u;
+            while (hi > lo_min) {
+                const uint32_t lo = hi - lo_min > width ? hi - width : lo_min;
+                const PackedHashAgg<T, PH_SLOTS, PH_FULL> agg{words, &sh.keys, lo, cbits, A.err};
+                agg.init();
+                uint32_t e = sc, ev = sv;
+                if (sc < pos && sv >= lo) e = probe_below(G.nbr, start, sc, pos, lo, &ev);
+                uint32_t total, nne;
+                compact_runs<T>(k, start, sc, e - sc, sh, &total, &nne);
+                walk_runs<T, U, 1>(G, A, agg, sh, total, nne);
+                if (!agg.finalize()) {  // (uniform) the window overflowed: narrow it
+                    width = (hi - lo) / 2 ? (hi - lo) / 2 : 1u;
+                    continue;
+                }
+                endpoint_credit<T>(G, A, r, agg, sh);
+                if (A.mode & (MODE_VERTEX | MODE_EDGE)) {
+                    walk_runs<T, U, 2>(G, A, agg, sh, total, nne);
+                    flush_runs<T>(G, A, r, k0, sh, nne);
+                }
+                sc = e;
+                sv = ev;
+                hi = lo;
+            }
+            continue;
+        }
         bool first = true;
         while (hi > lo_min) {
             const uint32_t lo = hi - lo_min > width ? hi - width : lo_min;
