@@ -1756,15 +1756,50 @@ __global__ __launch_bounds__(T) void k_count_dense_src(Ranked G, Acc A, const ui
 
 // Dense per-source histogram in global scratch (GET-FREQ by histogramming,
 // Section 3.1.2, one counter per candidate endpoint): pass 1 adds one per
-// wedge with an atomic, the endpoint step reads every counter once, pass 2
-// reads R back.  Counters stay in the L2 of one die: all items of a source run
-// on workgroups of the same die.
+// wedge, the endpoint step reads every counter once, pass 2 reads R back.
+// Counters stay in the L2 of one die: all items of a source run on
+// workgroups of the same die.
+//
+// Pass 1 does not send every wedge to the histogram: a wedge's endpoint
+// among the first GH_HOT candidates of the source (the highest ranked ones,
+// which take most of a giant source's wedges) is counted in a window of
+// 16-bit LDS counters instead, and the window is added to the histogram, one
+// atomic per non-zero counter, when the workgroup moves to another source or
+// has walked GH_HOT_UPS up-slots into it.  A run holds an endpoint at most
+// once, so a counter never exceeds the up-slots walked since the last flush
+// and cannot wrap.  Global atomics on random histogram lines are what limits
+// the walk; the window takes most of them off the L2.
+constexpr uint32_t GH_HOT = 6144;       // ids in the window: 12 KB, so 8 workgroups of 256 fit a CU
+constexpr uint32_t GH_HOT_UPS = 65535;  // up-slots walked into one window between flushes
+
 struct GlobalAgg {
     uint32_t *h;
     uint32_t lo;
-    __device__ void insert(uint32_t x) const { atomicAdd(&h[x - lo], 1u); }
+    uint32_t *hot;  // pass 1: GH_HOT / 2 LDS words, two 16-bit counters each
+    __device__ void insert(uint32_t x) const {
+        const uint32_t i = x - lo;
+        if (i < GH_HOT) atomicAdd(&hot[i >> 1], 1u << ((i & 1u) * 16));
+        else atomicAdd(&h[i], 1u);
+    }
     __device__ uint32_t count(uint32_t x) const { return h[x - lo]; }
 };
+
+// Adds the LDS window to the histogram `h` and clears it.  Call from all
+// threads.
+template <int T>
+__device__ inline void gh_flush(uint32_t *hot, uint32_t *h) {
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < GH_HOT / 2; i += T) {
+        const uint32_t w = hot[i];
+        if (w) {
+            hot[i] = 0;
+            // only inserted endpoints, which are inside the source's range, are non-zero
+            if (w & 0xFFFFu) atomicAdd(&h[2 * i], w & 0xFFFFu);
+            if (w >> 16) atomicAdd(&h[2 * i + 1], w >> 16);
+        }
+    }
+    __syncthreads();
+}
 
 struct GhSrc {
     uint32_t r, lo, ups, range;  // source rank, first candidate id, up-slots, candidate range
@@ -1783,19 +1818,38 @@ __global__ void k_gh_info(Ranked G, const uint32_t *src, uint32_t c, uint32_t *i
 }
 
 // Walks items (source s, up-slot chunk j) of this workgroup's die: pass 1
-// inserts every wedge into the source's counters, pass 2 credits R - 1.
+// inserts every wedge into the source's counters, pass 2 credits R - 1.  A
+// workgroup takes a contiguous share of its die's list (sources in order,
+// each source's chunks in order), so its items mostly belong to one source
+// and the LDS window of pass 1 is flushed rarely.
 template <int T, int U, int PASS>
 __global__ __launch_bounds__(T) void k_gh_walk(Ranked G, Acc A, const GhSrc *src, const uint2 *items,
                                                const uint32_t *xoff, uint32_t *hist) {
     __shared__ RunShared<T> sh;
-    const uint32_t x = blockIdx.x % NXCD, per = gridDim.x / NXCD;
-    for (uint32_t j = xoff[x] + blockIdx.x / NXCD; j < xoff[x + 1]; j += per) {
+    __shared__ uint32_t hot[PASS == 1 ? GH_HOT / 2 : 1];
+    const uint32_t x = blockIdx.x % NXCD, per = gridDim.x / NXCD, b = blockIdx.x / NXCD;
+    const uint64_t nx = xoff[x + 1] - xoff[x];
+    const uint32_t j0 = xoff[x] + (uint32_t)(nx * b / per), j1 = xoff[x] + (uint32_t)(nx * (b + 1) / per);
+    uint32_t held = 0xFFFFFFFFu, acc = 0;  // source the window holds, up-slots walked into it
+    if (PASS == 1) {
+        for (uint32_t i = threadIdx.x; i < GH_HOT / 2; i += T) hot[i] = 0;
+        __syncthreads();
+    }
+    for (uint32_t j = j0; j < j1; ++j) {
         const uint2 it = items[j];
         const GhSrc sr = src[it.x];
         const uint32_t k0 = G.upoff[sr.r], k1 = G.upoff[sr.r + 1];
         const uint32_t kb = k0 + it.y * GH_CHUNK;
         const uint32_t ke = kb + GH_CHUNK < k1 ? kb + GH_CHUNK : k1;
-        const GlobalAgg agg{hist + sr.hoff, sr.lo};
+        if (PASS == 1) {
+            if (held != it.x || acc + (ke - kb) > GH_HOT_UPS) {
+                if (held != 0xFFFFFFFFu) gh_flush<T>(hot, hist + src[held].hoff);
+                held = it.x;
+                acc = 0;
+            }
+            acc += ke - kb;
+        }
+        const GlobalAgg agg{hist + sr.hoff, sr.lo, hot};
         const bool cut = sr.lo != G.smid[sr.r] + 1;
         for (uint32_t c = kb; c < ke; c += T) {
             const uint32_t k = c + threadIdx.x;
@@ -1811,6 +1865,7 @@ __global__ __launch_bounds__(T) void k_gh_walk(Ranked G, Acc A, const GhSrc *src
             if (PASS == 2) flush_runs<T>(G, A, sr.r, k0, sh, nne);
         }
     }
+    if (PASS == 1 && held != 0xFFFFFFFFu) gh_flush<T>(hot, hist + src[held].hoff);
 }
 
 // Endpoint step over the counters: C(R,2) per candidate into the total and,
