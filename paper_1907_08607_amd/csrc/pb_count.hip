@@ -292,7 +292,8 @@ constexpr uint32_t GH_MIN_UPS = 65536;
 constexpr uint32_t GH_CHUNK = 8192;
 constexpr uint32_t GH_SEG = 65536;      // histogram entries per endpoint-step item
 constexpr uint32_t NXCD = 8;            // accelerator complex dies; workgroup b runs on die b % NXCD
-constexpr uint32_t GH_WG_PER_XCD = 256;
+constexpr uint32_t GH_WG_PER_XCD = 256;  // of 256 threads (the walk: that many threads per die)
+constexpr int GH_T = 256;               // workgroup size of the giant-source walk
 
 // Aggregator per bucket of the distinct-endpoint bound (light, medium, heavy),
 // the workgroup size of the light and medium buckets' kernels (hash, sort,
@@ -1769,7 +1770,7 @@ __global__ __launch_bounds__(T) void k_count_dense_src(Ranked G, Acc A, const ui
 // once, so a counter never exceeds the up-slots walked since the last flush
 // and cannot wrap.  Global atomics on random histogram lines are what limits
 // the walk; the window takes most of them off the L2.
-constexpr uint32_t GH_HOT = 6144;       // ids in the window: 12 KB, so 8 workgroups of 256 fit a CU
+constexpr uint32_t GH_HOT = 14336;      // ids in the window: 28 KB, 4 walk workgroups per CU
 constexpr uint32_t GH_HOT_UPS = 65535;  // up-slots walked into one window between flushes
 
 struct GlobalAgg {
@@ -1781,7 +1782,11 @@ struct GlobalAgg {
         if (i < GH_HOT) atomicAdd(&hot[i >> 1], 1u << ((i & 1u) * 16));
         else atomicAdd(&h[i], 1u);
     }
-    __device__ uint32_t count(uint32_t x) const { return h[x - lo]; }
+    // pass 2: the first GH_HOT / 2 counts were copied to `hot`
+    __device__ uint32_t count(uint32_t x) const {
+        const uint32_t i = x - lo;
+        return i < GH_HOT / 2 ? hot[i] : h[i];
+    }
 };
 
 // Adds the LDS window to the histogram `h` and clears it.  Call from all
@@ -1820,13 +1825,14 @@ __global__ void k_gh_info(Ranked G, const uint32_t *src, uint32_t c, uint32_t *i
 // Walks items (source s, up-slot chunk j) of this workgroup's die: pass 1
 // inserts every wedge into the source's counters, pass 2 credits R - 1.  A
 // workgroup takes a contiguous share of its die's list (sources in order,
-// each source's chunks in order), so its items mostly belong to one source
-// and the LDS window of pass 1 is flushed rarely.
+// each source's chunks in order), so its items mostly belong to one source:
+// the LDS window of pass 1 is flushed rarely, and pass 2 copies the counts of
+// a source's first GH_HOT / 2 candidates to LDS once.
 template <int T, int U, int PASS>
 __global__ __launch_bounds__(T) void k_gh_walk(Ranked G, Acc A, const GhSrc *src, const uint2 *items,
                                                const uint32_t *xoff, uint32_t *hist) {
     __shared__ RunShared<T> sh;
-    __shared__ uint32_t hot[PASS == 1 ? GH_HOT / 2 : 1];
+    __shared__ uint32_t hot[GH_HOT / 2];
     const uint32_t x = blockIdx.x % NXCD, per = gridDim.x / NXCD, b = blockIdx.x / NXCD;
     const uint64_t nx = xoff[x + 1] - xoff[x];
     const uint32_t j0 = xoff[x] + (uint32_t)(nx * b / per), j1 = xoff[x] + (uint32_t)(nx * (b + 1) / per);
@@ -1848,6 +1854,13 @@ __global__ __launch_bounds__(T) void k_gh_walk(Ranked G, Acc A, const GhSrc *src
                 acc = 0;
             }
             acc += ke - kb;
+        } else if (held != it.x) {
+            // pass 2 reads the counts of the first GH_HOT / 2 candidates from LDS
+            __syncthreads();
+            const uint32_t lim = sr.range < GH_HOT / 2 ? sr.range : GH_HOT / 2;
+            for (uint32_t i = threadIdx.x; i < lim; i += T) hot[i] = hist[sr.hoff + i];
+            __syncthreads();
+            held = it.x;
         }
         const GlobalAgg agg{hist + sr.hoff, sr.lo, hot};
         const bool cut = sr.lo != G.smid[sr.r] + 1;
@@ -2555,10 +2568,13 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
                     case L_DENSE_GLOBAL: {
                         const dim3 grid(NXCD * GH_WG_PER_XCD);
                         PB_TRY(fill<uint32_t>(gh_hist, 0u, gh_total, s));
-                        k_gh_walk<256, 4, 1><<<grid, 256, 0, s>>>(G, A, d_gh_src, d_gh_items, d_gh_xoff, gh_hist);
+                        const dim3 walk_grid(NXCD * GH_WG_PER_XCD * 256 / GH_T);
+                        k_gh_walk<GH_T, 4, 1><<<walk_grid, GH_T, 0, s>>>(G, A, d_gh_src, d_gh_items, d_gh_xoff,
+                                                                         gh_hist);
                         k_gh_endpoint<256><<<grid, 256, 0, s>>>(G, A, d_gh_src, d_gh_eitems, d_gh_exoff, gh_hist);
                         if (kmode & (MODE_VERTEX | MODE_EDGE))
-                            k_gh_walk<256, 4, 2><<<grid, 256, 0, s>>>(G, A, d_gh_src, d_gh_items, d_gh_xoff, gh_hist);
+                            k_gh_walk<GH_T, 4, 2><<<walk_grid, GH_T, 0, s>>>(G, A, d_gh_src, d_gh_items, d_gh_xoff,
+                                                                             gh_hist);
                         break;
                     }
                 }
