@@ -1232,8 +1232,12 @@ __device__ bool count_item(const Ranked &G, const Acc &A, uint32_t r, const Agg 
     agg.init();
     __syncthreads();
     const bool credit = A.mode & (MODE_VERTEX | MODE_EDGE);
+    const uint32_t c_last = k1 > k0 ? k0 + (k1 - k0 - 1) / T * T : k0;
     for (int pass = 1; pass <= passes; ++pass) {
-        for (uint32_t c = k0; c < k1; c += T) {
+        // pass 2 takes the chunks in reverse (the runs pass 1 read last are
+        // still in the L2)
+        for (uint32_t i = 0, c = pass == 1 ? k0 : c_last; c < k1 && i <= (c_last - k0) / T;
+             ++i, c = pass == 1 ? c + T : c - T) {
             const uint32_t k = c + tid;
             uint32_t a = 0, cnt = 0, start = 0;
             if (k < k1) {
@@ -1348,8 +1352,12 @@ __device__ void count_item_two(const Ranked &G, const Acc &A, uint32_t r, const 
     agg.init();
     __syncthreads();
     const bool credit = A.mode & (MODE_VERTEX | MODE_EDGE);
+    const uint32_t c_last = k1 > k0 ? k0 + (k1 - k0 - 1) / (2 * T) * (2 * T) : k0;
     for (int pass = 1; pass <= passes; ++pass) {
-        for (uint32_t c = k0; c < k1; c += 2 * T) {
+        // pass 2 takes the chunks in reverse, so it starts on the runs pass 1
+        // read last, while they are still in the L2
+        for (uint32_t i = 0, c = pass == 1 ? k0 : c_last; c < k1 && i <= (c_last - k0) / (2 * T);
+             ++i, c = pass == 1 ? c + 2 * T : c - 2 * T) {
             uint32_t k[2], a[2] = {0, 0}, cnt[2] = {0, 0}, start[2] = {0, 0};
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
