@@ -126,15 +126,52 @@ __device__ inline void dest_entries(const DestRows &D, uint32_t d, uint64_t j0, 
     }
 }
 
-// Short rows, one thread each; cnt = items of the long rows.
-__global__ void k_dest_small(DestRows D, uint64_t n, uint64_t *keys, uint32_t *vals, uint32_t *cnt) {
-    GRID_STRIDE(d, n) {
-        const uint32_t len = D.roff[d + 1] - D.roff[d];
-        if (len > DEST_SMALL) {
-            cnt[d] = (len + DEST_CHUNK - 1) / DEST_CHUNK;
-        } else {
-            cnt[d] = 0;
-            dest_entries(D, (uint32_t)d, 0, len, keys, vals, 1);
+// Short rows: a wave takes 64 consecutive destination ranks, lays their
+// entries end to end and deals them to its lanes in order, so every store
+// covers consecutive positions (a thread per row would leave most lanes idle
+// behind the longest row and scatter each store).  cnt = items of the long
+// rows, which this kernel leaves to k_dest_long.  Slot ids, positions and
+// row offsets are below 2m < 2^32.
+__global__ __launch_bounds__(256) void k_dest_small(DestRows D, uint64_t n, uint64_t *keys, uint32_t *vals,
+                                                    uint32_t *cnt) {
+    const uint32_t lane = threadIdx.x & (WAVE - 1);
+    const uint64_t mask = (uint64_t(1) << D.b) - 1;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w0 = (uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(WAVE - 1)); w0 < n; w0 += stride) {
+        const uint64_t d = w0 + lane;
+        uint32_t len = 0, y = 0, q0 = 0, src = 0;  // row length, vertex, first position, first CSR entry
+        if (d < n) {
+            len = D.roff[d + 1] - D.roff[d];
+            cnt[d] = len > DEST_SMALL ? (len + DEST_CHUNK - 1) / DEST_CHUNK : 0u;
+            if (len > DEST_SMALL) len = 0;
+            y = D.order[d];
+            q0 = (uint32_t)(D.ns - D.roff[d + 1]);
+            src = y < D.n_u ? (uint32_t)D.u_off[y] : D.v_off[y - D.n_u];
+        }
+        const uint32_t incl = wave_inclusive_sum(len);
+        const uint32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, WAVE - 1, WAVE));
+        for (uint32_t t = 0; t < total; t += WAVE) {
+            const uint32_t f = t + lane;
+            // the row holding flat entry f: the first lane whose inclusive sum exceeds f
+            uint32_t i = 0;
+#pragma unroll
+            for (uint32_t step = WAVE / 2; step; step >>= 1)
+                if (__shfl(incl, (int)(i + step - 1), WAVE) <= f) i += step;
+            const uint32_t ii = i < WAVE ? i : WAVE - 1;
+            const uint32_t j = f - (__shfl(incl, (int)ii, WAVE) - __shfl(len, (int)ii, WAVE));
+            const uint32_t yi = __shfl(y, (int)ii, WAVE);
+            const uint32_t q = __shfl(q0, (int)ii, WAVE) + j;
+            const uint32_t e = __shfl(src, (int)ii, WAVE) + j;
+            const uint64_t low = mask - (w0 + ii);
+            if (f < total) {
+                if (yi < D.n_u) {
+                    keys[q] = ((uint64_t)D.rank[D.n_u + D.u_adj[e]] << D.b) | low;
+                    vals[q] = 2 * e + 1;  // slot (v -> u)
+                } else {
+                    keys[q] = ((uint64_t)D.rank[D.v_adj[e]] << D.b) | low;
+                    vals[q] = 2 * D.v_eid[e];  // slot (u -> v)
+                }
+            }
         }
     }
 }
@@ -2344,7 +2381,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
             uint32_t *dcnt = ws.alloc<uint32_t>(n + 1), *dcoff = ws.alloc<uint32_t>(n + 1);
             if (ws.failed) return PB_ERR_NO_MEMORY;
             const DestRows D{order, roff, in.rank, in.u_off, in.u_adj, in.v_off, in.v_adj, in.v_eid, in.n_u, ns, b};
-            hipLaunchKernelGGL(k_dest_small, dim3(grid_for(n)), dim3(256), 0, s, D, n, k0, v0, dcnt);
+            hipLaunchKernelGGL(k_dest_small, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, D, n, k0, v0, dcnt);
             PB_TRY((scan_exclusive<uint32_t, uint32_t>(dcnt, dcoff, n, dcoff + n, ws)));
             hipLaunchKernelGGL(k_dest_long, dim3(DEST_GRID), dim3(256), 0, s, D, n, (const uint32_t *)dcoff, k0, v0);
             PB_TRY_HIP(hipGetLastError());
