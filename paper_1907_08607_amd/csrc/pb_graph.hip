@@ -65,10 +65,13 @@ __global__ __launch_bounds__(EDGE_BLOCK) void k_edge_rows(const int64_t *u_off, 
     if (bad) atomicOr(flags, bad);
 }
 
-__global__ void k_iota_keys(const uint32_t *u_adj, uint64_t m, uint64_t *keys, uint32_t *vals) {
+// Sort keys of the V-side CSR: the V id in the high word, the edge's U
+// endpoint riding along in the low word (the sort reads the high word only),
+// so the sorted keys give v_adj without a gather through the edge ids.
+__global__ void k_iota_keys(const uint32_t *u_adj, const uint32_t *eu, uint64_t m, uint64_t *keys, uint32_t *vals) {
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
          e += (uint64_t)gridDim.x * blockDim.x) {
-        keys[e] = u_adj[e];
+        keys[e] = ((uint64_t)u_adj[e] << 32) | eu[e];
         vals[e] = (uint32_t)e;
     }
 }
@@ -81,18 +84,18 @@ __global__ void k_voff_from_sorted(const uint64_t *key, uint64_t m, uint32_t n_v
     if (flags[0] & BAD_ID) return;
     for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p <= m;
          p += (uint64_t)gridDim.x * blockDim.x) {
-        const int64_t prev = p == 0 ? -1 : (int64_t)key[p - 1];
-        const int64_t cur = p == m ? (int64_t)n_v : (int64_t)key[p];
+        const int64_t prev = p == 0 ? -1 : (int64_t)(key[p - 1] >> 32);
+        const int64_t cur = p == m ? (int64_t)n_v : (int64_t)(key[p] >> 32);
         for (int64_t v = prev + 1; v <= cur; ++v) v_off[v] = (uint32_t)p;
     }
 }
 
-__global__ void k_gather_u(const uint32_t *eids, const uint32_t *eu, uint64_t m, uint32_t *v_adj, uint32_t *v_eid) {
+__global__ void k_split_sorted(const uint64_t *keys, const uint32_t *eids, uint64_t m, uint32_t *v_adj,
+                               uint32_t *v_eid) {
     for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < m;
          p += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t e = eids[p];
-        v_adj[p] = eu[e];
-        v_eid[p] = e;
+        v_adj[p] = (uint32_t)keys[p];
+        v_eid[p] = eids[p];
     }
 }
 
@@ -753,13 +756,14 @@ pb_status pb_graph_create(const pb_csr *csr, hipStream_t s, pb_graph **out) {
                 uint64_t *k0 = ws.alloc<uint64_t>(m), *k1 = ws.alloc<uint64_t>(m);
                 uint32_t *v0 = ws.alloc<uint32_t>(m), *v1 = ws.alloc<uint32_t>(m);
                 if (ws.failed) { st = PB_ERR_NO_MEMORY; break; }
-                hipLaunchKernelGGL(k_iota_keys, dim3(grid_for(m)), dim3(256), 0, s, g->u_adj, m, k0, v0);
+                hipLaunchKernelGGL(k_iota_keys, dim3(grid_for(m)), dim3(256), 0, s, g->u_adj, g->eu, m, k0, v0);
                 uint64_t *kr;
                 uint32_t *vr;
-                if ((st = radix_sort_pairs(k0, v0, k1, v1, m, bits_for(g->n_v ? g->n_v - 1 : 0), ws, &kr, &vr)) !=
-                    PB_OK)
+                if ((st = radix_sort_pairs_bits(k0, v0, k1, v1, m, 32, 32 + bits_for(g->n_v ? g->n_v - 1 : 0), ws,
+                                                &kr, &vr)) != PB_OK)
                     break;
-                hipLaunchKernelGGL(k_gather_u, dim3(grid_for(m)), dim3(256), 0, s, vr, g->eu, m, g->v_adj, g->v_eid);
+                hipLaunchKernelGGL(k_split_sorted, dim3(grid_for(m)), dim3(256), 0, s, (const uint64_t *)kr,
+                                   (const uint32_t *)vr, m, g->v_adj, g->v_eid);
                 hipLaunchKernelGGL(k_voff_from_sorted, dim3(grid_for(m + 1)), dim3(256), 0, s, (const uint64_t *)kr, m,
                                    g->n_v, (const uint32_t *)flags, g->v_off);
             }
