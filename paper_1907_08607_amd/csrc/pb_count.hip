@@ -1821,14 +1821,18 @@ constexpr uint32_t GH_HOT_UPS = 65535;  // up-slots walked into one window betwe
 struct GlobalAgg {
     uint32_t *h;
     uint32_t lo;
-    uint32_t *hot;  // pass 1: GH_HOT / 2 LDS words, two 16-bit counters each
+    uint32_t *hot;         // pass 1: GH_HOT / 2 LDS words, two 16-bit counters each
+    const uint32_t *drow;  // pass 2 of a hub source: its row of the hub tile, for partners below lo
+    uint32_t hub_base;
     __device__ void insert(uint32_t x) const {
         const uint32_t i = x - lo;
         if (i < GH_HOT) atomicAdd(&hot[i >> 1], 1u << ((i & 1u) * 16));
         else atomicAdd(&h[i], 1u);
     }
-    // pass 2: the first GH_HOT / 2 counts were copied to `hot`
+    // pass 2: the first GH_HOT / 2 counts were copied to `hot`; a hub
+    // partner's count is the tile's
     __device__ uint32_t count(uint32_t x) const {
+        if (x < lo) return drow[x - hub_base];
         const uint32_t i = x - lo;
         return i < GH_HOT / 2 ? hot[i] : h[i];
     }
@@ -1856,7 +1860,9 @@ struct GhSrc {
     uint64_t hoff;               // its counters: hist[hoff .. hoff + range)
 };
 
-__global__ void k_gh_info(Ranked G, const uint32_t *src, uint32_t c, uint32_t *info) {
+// Also marks, in gh_hub (HUB_T flags, zeroed by the caller), the tile's hubs
+// that are giant sources: their pass 2 credits the hub partners too.
+__global__ void k_gh_info(Ranked G, const uint32_t *src, uint32_t c, uint32_t *info, uint32_t *gh_hub) {
     GRID_STRIDE(i, (uint64_t)c) {
         const uint32_t r = src[i];
         const uint32_t lo = G.lo(r);
@@ -1864,6 +1870,8 @@ __global__ void k_gh_info(Ranked G, const uint32_t *src, uint32_t c, uint32_t *i
         info[4 * i + 1] = lo;
         info[4 * i + 2] = G.upoff[r + 1] - G.upoff[r];
         info[4 * i + 3] = G.cend[r] - lo;
+        const uint32_t sm = G.smid[r];
+        if (sm >= G.hub_base && sm < G.hub_end) gh_hub[sm - G.hub_base] = 1u;
     }
 }
 
@@ -1873,9 +1881,14 @@ __global__ void k_gh_info(Ranked G, const uint32_t *src, uint32_t c, uint32_t *i
 // each source's chunks in order), so its items mostly belong to one source:
 // the LDS window of pass 1 is flushed rarely, and pass 2 copies the counts of
 // a source's first GH_HOT / 2 candidates to LDS once.
+//
+// A giant source that is one of the tile's hubs skips its hub partners in
+// pass 1 (the tile counts those pairs).  With `D` (the tile) its pass 2 walks
+// the whole run and takes a hub partner's R from the tile, which does the hub
+// credit pass's work for that source in the same walk.
 template <int T, int U, int PASS>
 __global__ __launch_bounds__(T) void k_gh_walk(Ranked G, Acc A, const GhSrc *src, const uint2 *items,
-                                               const uint32_t *xoff, uint32_t *hist) {
+                                               const uint32_t *xoff, uint32_t *hist, const uint32_t *D) {
     __shared__ RunShared<T> sh;
     __shared__ uint32_t hot[GH_HOT / 2];
     const uint32_t x = blockIdx.x % NXCD, per = gridDim.x / NXCD, b = blockIdx.x / NXCD;
@@ -1907,15 +1920,18 @@ __global__ __launch_bounds__(T) void k_gh_walk(Ranked G, Acc A, const GhSrc *src
             __syncthreads();
             held = it.x;
         }
-        const GlobalAgg agg{hist + sr.hoff, sr.lo, hot};
-        const bool cut = sr.lo != G.smid[sr.r] + 1;
+        const uint32_t sm = G.smid[sr.r];
+        const bool cut = sr.lo != sm + 1;  // a hub source: its run ends in hub partners
+        const uint32_t *drow = PASS == 2 && cut && D ? D + (uint64_t)(sm - G.hub_base) * HUB_T : nullptr;
+        const GlobalAgg agg{hist + sr.hoff, sr.lo, hot, drow, G.hub_base};
         for (uint32_t c = kb; c < ke; c += T) {
             const uint32_t k = c + threadIdx.x;
             uint32_t cnt = 0, start = 0;
             if (k < ke) {
                 start = G.uprun[k];
                 const uint32_t pos = G.uplen[k];
-                cnt = cut ? first_below(G.nbr + start, 0, pos, sr.lo) : pos;
+                // the whole run is ranked after the source; the hub partners come last
+                cnt = cut && !drow ? first_below(G.nbr + start, 0, pos, sr.lo) : pos;
             }
             uint32_t total, nne;
             compact_runs<T>(k, start, 0u, cnt, sh, &total, &nne);
@@ -1996,9 +2012,11 @@ __global__ __launch_bounds__(HUB_T) void k_hub_items(const uint32_t *upoff, cons
 // hub partners; each gets R - 1 on the slot (y -> h2) and the run's sum goes
 // to the centre y and the slot (h1 -> y).  A hub's up-slots are split into
 // items of HUB_CHUNK, so one giant hub spreads over many workgroups.
+// Hubs flagged in `skip` (giant sources whose histogram walk credits their
+// hub partners) are left out.
 template <int T, int U>
 __global__ __launch_bounds__(T) void k_count_hub_pass(Ranked G, Acc A, const uint32_t *hub_rank, const uint32_t *hoff,
-                                                      const uint32_t *D) {
+                                                      const uint32_t *D, const uint32_t *skip) {
     __shared__ RunShared<T> sh;
     const uint32_t count = hoff[HUB_T];
     for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
@@ -2007,6 +2025,7 @@ __global__ __launch_bounds__(T) void k_count_hub_pass(Ranked G, Acc A, const uin
             const uint32_t mid = (lo + hi) >> 1;
             if (hoff[mid] <= it) lo = mid; else hi = mid;
         }
+        if (skip[lo]) continue;  // (uniform)
         const uint32_t r = hub_rank[lo];
         const uint32_t k0 = G.upoff[r], k1 = G.upoff[r + 1];
         const uint32_t kb = k0 + (it - hoff[lo]) * HUB_CHUNK;
@@ -2512,11 +2531,15 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         uint2 *d_gh_items = nullptr, *d_gh_eitems = nullptr;
         uint32_t *d_gh_xoff = nullptr, *d_gh_exoff = nullptr, *gh_hist = nullptr;
         uint64_t gh_total = 0;
+        // hubs whose pass 2 the giant-source walk does (read by the hub credit pass)
+        uint32_t *gh_hub = ws.alloc<uint32_t>(HUB_T);
+        if (ws.failed) return PB_ERR_NO_MEMORY;
+        PB_TRY(fill<uint32_t>(gh_hub, 0u, HUB_T, s));
         if (const uint32_t c = plan.list[L_DENSE_GLOBAL]) {
             uint32_t *d_info = ws.alloc<uint32_t>(4ull * c);
             if (ws.failed) return PB_ERR_NO_MEMORY;
             hipLaunchKernelGGL(k_gh_info, dim3(grid_for(c)), dim3(256), 0, s, G, sorted_src[sorted_slot(L_DENSE_GLOBAL)],
-                               c, d_info);
+                               c, d_info, gh_hub);
             PB_TRY_HIP(hipGetLastError());
             gh_info.resize(4ull * c);
             PB_TRY_HIP(hipMemcpyAsync(gh_info.data(), d_info, 16ull * c, hipMemcpyDeviceToHost, s));
@@ -2615,11 +2638,11 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
                         PB_TRY(fill<uint32_t>(gh_hist, 0u, gh_total, s));
                         const dim3 walk_grid(NXCD * GH_WG_PER_XCD * 256 / GH_T);
                         k_gh_walk<GH_T, 4, 1><<<walk_grid, GH_T, 0, s>>>(G, A, d_gh_src, d_gh_items, d_gh_xoff,
-                                                                         gh_hist);
+                                                                         gh_hist, nullptr);
                         k_gh_endpoint<256><<<grid, 256, 0, s>>>(G, A, d_gh_src, d_gh_eitems, d_gh_exoff, gh_hist);
                         if (kmode & (MODE_VERTEX | MODE_EDGE))
-                            k_gh_walk<GH_T, 4, 2><<<walk_grid, GH_T, 0, s>>>(G, A, d_gh_src, d_gh_items, d_gh_xoff,
-                                                                             gh_hist);
+                            k_gh_walk<GH_T, 4, 2><<<walk_grid, GH_T, 0, s>>>(
+                                G, A, d_gh_src, d_gh_items, d_gh_xoff, gh_hist, hub_on ? (const uint32_t *)hub_d : nullptr);
                         break;
                     }
                 }
@@ -2631,7 +2654,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
             hub_pass_ran = true;
             if (ev.ok) ev.ok = hipEventRecord(ev.e[E_HP0], s) == hipSuccess;
             k_count_hub_pass<256, 4><<<dim3(std::min(plan.hub_items, HUB_PASS_GRID)), dim3(256), 0, s>>>(
-                G, A, hub_rank, hub_off, hub_d);
+                G, A, hub_rank, hub_off, hub_d, gh_hub);
             PB_TRY_HIP(hipGetLastError());
             if (ev.ok) ev.ok = hipEventRecord(ev.e[E_HP1], s) == hipSuccess;
         }
