@@ -709,12 +709,9 @@ struct HashAgg {
     __device__ void insert(uint32_t x) const {
         uint32_t h = slot(x);
         for (int probe = 0; probe < CAP; ++probe) {
-            uint32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (k == EMPTY) {
-                k = atomicCAS(&keys[h], EMPTY, x);
-                if (k == EMPTY) k = x;
-            }
-            if (k == x) { atomicAdd(&cnts[h], 1u); return; }
+            // one compare-and-swap both claims an empty slot and reads a taken one
+            const uint32_t k = atomicCAS(&keys[h], EMPTY, x);
+            if (k == EMPTY || k == x) { atomicAdd(&cnts[h], 1u); return; }
             h = (h + 1) & (CAP - 1);
         }
         atomicOr(err, FLAG_INTERNAL);
@@ -752,28 +749,38 @@ struct PackedHashAgg {
         for (uint32_t i = threadIdx.x; i < CAP; i += T) w[i] = 0;
         if (threadIdx.x == 0) *keys = 0;
     }
-    // Once FULL keys are in (the table is then 3/4 full), further new keys are
-    // dropped and finalize() refuses the window: the caller narrows it.
+    // A new key claims an empty slot by compare-and-swap (which also reads a
+    // taken slot), and each call's new keys are counted with one atomic per
+    // wave.  The walk skips a wave's inserts once FULL keys are in
+    // (saturated(), read once per U x 64 wedges of the wave), so fewer than
+    // FULL + T * U keys are ever in: with FULL + T * U <= CAP probing always
+    // ends, and finalize() refuses a window that reached FULL, which the
+    // caller narrows.
     __device__ void insert(uint32_t x) const {
         const uint32_t key = x - lo, tag = key + 1;
         uint32_t h = slot(key);
-        for (int probe = 0; probe < CAP; ++probe) {
-            uint32_t e = __hip_atomic_load(&w[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        bool fresh = false;
+        int probe = 0;
+        for (; probe < CAP; ++probe) {
+            const uint32_t e = atomicCAS(&w[h], 0u, (tag << cbits) | 1u);
             if (e == 0) {
-                if (__hip_atomic_load(keys, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= FULL) return;
-                e = atomicCAS(&w[h], 0u, (tag << cbits) | 1u);
-                if (e == 0) {
-                    atomicAdd(keys, 1u);
-                    return;
-                }
+                fresh = true;
+                break;
             }
             if ((e >> cbits) == tag) {
                 atomicAdd(&w[h], 1u);
-                return;
+                break;
             }
             h = (h + 1) & (CAP - 1);
         }
-        atomicOr(err, FLAG_INTERNAL);
+        if (probe == CAP) atomicOr(err, FLAG_INTERNAL);
+        const uint64_t nb = __ballot(fresh);
+        if (nb && __lane_id() == (uint32_t)__ffsll((unsigned long long)__ballot(1)) - 1)
+            atomicAdd(keys, (uint32_t)__popcll(nb));
+    }
+    __device__ bool saturated() const {
+        return __builtin_amdgcn_readfirstlane(
+                   __hip_atomic_load(keys, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) >= FULL;
     }
     __device__ bool finalize() const {
         __syncthreads();
@@ -800,6 +807,13 @@ struct PackedHashAgg {
         }
     }
 };
+
+// Whether the walk should skip a wave's inserts: only a packed hash refuses
+// keys.
+template <class Agg>
+__device__ inline bool saturated(const Agg &) { return false; }
+template <int T, int CAP, int FULL>
+__device__ inline bool saturated(const PackedHashAgg<T, CAP, FULL> &a) { return a.saturated(); }
 
 // Block-wide stable LSD radix sort of n 64-bit keys in LDS, 4 bits a pass
 // over bits [0, nbits) (nbits a multiple of 8, so the result ends in `a`).
@@ -1192,9 +1206,11 @@ __device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, 
         for (int u = 0; u < U; ++u)
             if (ok[u]) xs[u] = G.nbr[pidx[u]];
         if (PASS == 1) {
+            if (!saturated(agg)) {
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (ok[u]) agg.insert(xs[u]);
+                for (int u = 0; u < U; ++u)
+                    if (ok[u]) agg.insert(xs[u]);
+            }
         } else {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -1728,6 +1744,7 @@ template <int T, int U>
 __global__ __launch_bounds__(T) void k_count_phash(Ranked G, Acc A, const uint32_t *list, const uint64_t *wsrc,
                                                    uint32_t *cur, uint32_t *nxt, uint32_t *cval, uint32_t *nval,
                                                    uint32_t count) {
+    static_assert(PH_FULL + T * U <= PH_SLOTS, "keys inserted after the walk's last check must still fit");
     __shared__ uint32_t words[PH_SLOTS];
     __shared__ RunShared<T> sh;
     for (uint32_t i = blockIdx.x; i < count; i += gridDim.x) {
