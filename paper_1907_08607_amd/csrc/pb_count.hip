@@ -782,6 +782,65 @@ struct PackedHashAgg {
         return __builtin_amdgcn_readfirstlane(
                    __hip_atomic_load(keys, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) >= FULL;
     }
+    // The inserts of U sub-tiles at once: the first probes of all of them are
+    // issued back to back, so their LDS round trips overlap; a probe that meets
+    // another key continues alone.  Call with the whole wave.
+    template <int U>
+    __device__ void insert_all(const uint32_t *x, const bool *ok) const {
+        uint32_t h[U], v[U], e[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t key = x[u] - lo;
+            h[u] = slot(key);
+            v[u] = ((key + 1) << cbits) | 1u;
+            e[u] = ok[u] ? atomicCAS(&w[h[u]], 0u, v[u]) : 0u;
+        }
+        uint32_t fresh = 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!ok[u]) continue;
+            if (e[u] == 0) {
+                ++fresh;
+                continue;
+            }
+            const uint32_t tag = v[u] >> cbits;
+            uint32_t hh = h[u], ee = e[u];
+            int probe = 1;
+            while ((ee >> cbits) != tag && probe < CAP) {
+                hh = (hh + 1) & (CAP - 1);
+                ee = atomicCAS(&w[hh], 0u, v[u]);
+                ++probe;
+                if (ee == 0) break;
+            }
+            if (ee == 0) ++fresh;
+            else if ((ee >> cbits) == tag) atomicAdd(&w[hh], 1u);
+            else atomicOr(err, FLAG_INTERNAL);
+        }
+        const uint32_t total = wave_sum(fresh);
+        if (total && __lane_id() == 0) atomicAdd(keys, total);
+    }
+    // count() of U sub-tiles, first probes issued back to back.
+    template <int U>
+    __device__ void count_all(const uint32_t *x, const bool *ok, uint32_t *c) const {
+        uint32_t h[U], e[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            h[u] = slot(x[u] - lo);
+            e[u] = ok[u] ? w[h[u]] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c[u] = 1u;
+            if (!ok[u]) continue;
+            const uint32_t tag = x[u] - lo + 1;
+            uint32_t hh = h[u], ee = e[u];
+            for (int probe = 1; (ee >> cbits) != tag && ee != 0 && probe < CAP; ++probe) {
+                hh = (hh + 1) & (CAP - 1);
+                ee = w[hh];
+            }
+            if ((ee >> cbits) == tag) c[u] = ee & ((1u << cbits) - 1);
+        }
+    }
     __device__ bool finalize() const {
         __syncthreads();
         const bool ok = *keys < FULL;
@@ -814,6 +873,29 @@ template <class Agg>
 __device__ inline bool saturated(const Agg &) { return false; }
 template <int T, int CAP, int FULL>
 __device__ inline bool saturated(const PackedHashAgg<T, CAP, FULL> &a) { return a.saturated(); }
+
+// The inserts and count reads of a walk's U sub-tiles (ok[u]: lane holds a
+// wedge of sub-tile u); the packed hash overlaps their first probes.
+template <int U, class Agg>
+__device__ inline void insert_all(const Agg &agg, const uint32_t *x, const bool *ok) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (ok[u]) agg.insert(x[u]);
+}
+template <int U, int T, int CAP, int FULL>
+__device__ inline void insert_all(const PackedHashAgg<T, CAP, FULL> &agg, const uint32_t *x, const bool *ok) {
+    agg.template insert_all<U>(x, ok);
+}
+template <int U, class Agg>
+__device__ inline void count_all(const Agg &agg, const uint32_t *x, const bool *ok, uint32_t *c) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) c[u] = ok[u] ? agg.count(x[u]) : 1u;
+}
+template <int U, int T, int CAP, int FULL>
+__device__ inline void count_all(const PackedHashAgg<T, CAP, FULL> &agg, const uint32_t *x, const bool *ok,
+                                 uint32_t *c) {
+    agg.template count_all<U>(x, ok, c);
+}
 
 // Block-wide stable LSD radix sort of n 64-bit keys in LDS, 4 bits a pass
 // over bits [0, nbits) (nbits a multiple of 8, so the result ends in `a`).
@@ -1126,7 +1208,7 @@ __device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, 
     // runs i0 .. i0+63 held one per lane
     uint32_t i0 = 0, o = 0xFFFFFFFFu, dlt = 0, o_end = 0;
     for (uint32_t wb = t0 * WAVE; wb < f1; wb += U * WAVE) {
-        uint32_t pidx[U], rel[U], xs[U];
+        uint32_t pidx[U], rel[U], xs[U] = {};  // xs of lanes past the end stay 0
         uint64_t st[U];
         bool ok[U];
         const uint32_t span_last = wb + U * WAVE - 1 < f1 ? wb + U * WAVE - 1 : f1 - 1;
@@ -1206,16 +1288,14 @@ __device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, 
         for (int u = 0; u < U; ++u)
             if (ok[u]) xs[u] = G.nbr[pidx[u]];
         if (PASS == 1) {
-            if (!saturated(agg)) {
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (ok[u]) agg.insert(xs[u]);
-            }
+            if (!saturated(agg)) insert_all<U>(agg, xs, ok);
         } else {
+            uint32_t cs[U];
+            count_all<U>(agg, xs, ok, cs);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (wb + u * WAVE >= f1) break;  // wave-uniform
-                const uint32_t d = ok[u] ? agg.count(xs[u]) - 1 : 0u;
+                const uint32_t d = ok[u] ? cs[u] - 1 : 0u;
                 if (d && edge) A.slot_add(pidx[u], d);
                 const uint64_t sm = st[u] & le;
                 const uint32_t first = sm ? 63u - (uint32_t)__clzll(sm) : 0u;
