@@ -1292,9 +1292,10 @@ __device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, 
         } else {
             uint32_t cs[U];
             count_all<U>(agg, xs, ok, cs);
+            // sub-tiles past the end credit nothing (ok false, d = 0); no early
+            // exit, so the four sub-tiles' credit chains can interleave
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (wb + u * WAVE >= f1) break;  // wave-uniform
                 const uint32_t d = ok[u] ? cs[u] - 1 : 0u;
                 if (d && edge) A.slot_add(pidx[u], d);
                 const uint64_t sm = st[u] & le;
