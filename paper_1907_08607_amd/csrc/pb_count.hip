@@ -1177,6 +1177,17 @@ __device__ inline void segment_add(uint32_t d, bool ok, uint32_t first, bool las
     if (ok && last && seg) __hip_atomic_fetch_add(dst, seg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Adds the wave's d to one run's sum (every lane's wedge is in that run).
+__device__ inline void run_add(unsigned long long *dst, uint32_t d, uint32_t lane) {
+    const uint32_t tot = __builtin_amdgcn_readlane(wave_inclusive_sum(d), WAVE - 1);
+    if (tot && lane == 0)
+        __hip_atomic_fetch_add(dst, (unsigned long long)tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ inline void run_add(uint32_t *dst, uint32_t d, uint32_t lane) {
+    const uint32_t tot = __builtin_amdgcn_readlane(wave_inclusive_sum(d), WAVE - 1);
+    if (tot && lane == 0) __hip_atomic_fetch_add(dst, tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Walks the compacted wedge sequence of one chunk (see count_item): pass 1
 // inserts each x2 into the aggregator; pass 2 credits R-1 to the slot
 // (y -> x2) and sums it per run into sh.sum.
@@ -1212,7 +1223,20 @@ __device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, 
         uint64_t st[U];
         bool ok[U];
         const uint32_t span_last = wb + U * WAVE - 1 < f1 ? wb + U * WAVE - 1 : f1 - 1;
-        if (span_last < o_end) {
+        if (span_last < o_end && __ballot(o > wb && o <= span_last) == 0) {
+            // no held run starts inside the span: one run (the last held
+            // one starting at or before wb) covers all of it
+            const uint32_t j0 = (uint32_t)__popcll(__ballot(o <= wb)) - 1;
+            const uint32_t d0 = __builtin_amdgcn_readlane(dlt, j0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t base = wb + u * WAVE;
+                ok[u] = base + lane < f1;
+                st[u] = 0;
+                rel[u] = i0 + j0;
+                pidx[u] = d0 + base + lane;
+            }
+        } else if (span_last < o_end) {
             // every sub-tile lies inside the held runs: the strips of all
             // sub-tiles are cleared, marked and read back to back, so their
             // LDS round trips overlap
@@ -1298,10 +1322,17 @@ __device__ inline void walk_runs(const Ranked &G, const Acc &A, const Agg &agg, 
             for (int u = 0; u < U; ++u) {
                 const uint32_t d = ok[u] ? cs[u] - 1 : 0u;
                 if (d && edge) A.slot_add(pidx[u], d);
-                const uint64_t sm = st[u] & le;
-                const uint32_t first = sm ? 63u - (uint32_t)__clzll(sm) : 0u;
-                const bool last = lane == WAVE - 1 || ((st[u] >> (lane + 1)) & 1) || !(wb + u * WAVE + lane + 1 < f1);
-                segment_add(d, ok[u], first, last, &sh.sum[rel[u]], lane);
+                if (st[u] == 0) {
+                    // (uniform) no run starts in the sub-tile: all its wedges
+                    // belong to run rel[u]
+                    run_add(&sh.sum[rel[u]], d, lane);
+                } else {
+                    const uint64_t sm = st[u] & le;
+                    const uint32_t first = sm ? 63u - (uint32_t)__clzll(sm) : 0u;
+                    const bool last =
+                        lane == WAVE - 1 || ((st[u] >> (lane + 1)) & 1) || !(wb + u * WAVE + lane + 1 < f1);
+                    segment_add(d, ok[u], first, last, &sh.sum[rel[u]], lane);
+                }
             }
         }
     }
