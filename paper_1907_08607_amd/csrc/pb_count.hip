@@ -2583,7 +2583,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
                             hub_base, hub_end, opts.hub == PB_HUB_FORCE,
                             (kmode & (MODE_VERTEX | MODE_EDGE)) != 0, gacc, vacc};
             PB_TRY(hub_tile(hin, &pc->hub, HubOut{hub_rank, hub_d, hub_roww}, ws, s, ev.ok ? ev.e[E_HG0] : nullptr,
-                            ev.ok ? ev.e[E_HG1] : nullptr, &hub_grid));
+                            ev.ok ? ev.e[E_HG1] : nullptr, &hub_grid, &hpc->hub.on));
             if (kmode & (MODE_VERTEX | MODE_EDGE))
                 hipLaunchKernelGGL(k_hub_items, dim3(1), dim3(HUB_T), 0, s, (const uint32_t *)upoff,
                                    (const uint32_t *)hub_rank, hub_end - hub_base, hub_off, pc);

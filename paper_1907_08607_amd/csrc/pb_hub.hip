@@ -38,19 +38,23 @@ constexpr uint32_t GEMM_MAX_GRID = 256;    // one workgroup per compute unit
 // single-graph workloads (all three outputs):
 //   sparse path, per hub-pair path (a wedge the tile would take over), both
 //   passes: NS_SPARSE in LDS windows, NS_SPARSE_GIANT when a hub source has
-//   at least GIANT_UPS up-slots (its wedges go to the global histogram); one
-//   pass (total only) costs half;
+//   at least GIANT_UPS up-slots (its wedges go to the global histogram, where
+//   a source's highest-ranked candidates, the hubs among them, are counted
+//   in LDS: the 9.7e7 hub paths of the 100M-edge hub graph cost the walk
+//   nothing measurable); one pass (total only) costs half;
 //   tile: NS_FIXED + NS_FIXED_VERTEX per vertex (column marking and
 //   compaction) + NS_PER_COL per compacted column (the matrix-core product),
 //   plus NS_HUB_PASS per path for the hub pairs' credit pass when per-vertex
-//   or per-edge counts are wanted.
+//   or per-edge counts are wanted and no hub source is giant (a giant hub's
+//   credits ride in the histogram walk's pass 2).
 constexpr double NS_SPARSE = 0.0075;
-constexpr double NS_SPARSE_GIANT = 0.06;
+constexpr double NS_SPARSE_GIANT = 0.005;
 constexpr double NS_FIXED = 100000.0;
 constexpr double NS_FIXED_VERTEX = 0.035;
 constexpr double NS_PER_COL = 0.1;
 constexpr double NS_HUB_PASS = 0.04;
 constexpr uint32_t GIANT_UPS = 65536;  // the planner's global-histogram threshold
+constexpr uint32_t HUB_SAMPLE = 16;     // AUTO estimates paths and columns from every 16th vertex
 
 #define HUB_GRID_STRIDE(i, n)                                                       \
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); \
@@ -81,9 +85,14 @@ __global__ void k_hub_rank(const uint32_t *smid, uint64_t n, uint32_t base, uint
     }
 }
 
-__global__ void k_hub_mark(HubIn in, uint32_t *keep, HubCounters *hc) {
+// Marks the kept centre columns (keep[r]) and adds their hub-pair paths and
+// their number to hc.  With stride > 1 (keep null) it visits every stride-th
+// vertex only: a sample for the AUTO estimate.
+__global__ void k_hub_mark(HubIn in, uint32_t *keep, HubCounters *hc, uint32_t stride) {
     unsigned long long paths = 0;
-    HUB_GRID_STRIDE(r, in.n) {
+    uint32_t cols = 0;
+    HUB_GRID_STRIDE(i, (in.n + stride - 1) / stride) {
+        const uint64_t r = i * stride;
         uint32_t flag = 0;
         if (other_side(in, in.smid[r])) {
             const uint32_t o = in.roff[r], deg = in.roff[r + 1] - o;
@@ -94,26 +103,39 @@ __global__ void k_hub_mark(HubIn in, uint32_t *keep, HubCounters *hc) {
                 paths += (unsigned long long)k * (k - 1) / 2;
             }
         }
-        keep[r] = flag;
+        if (keep) keep[r] = flag;
+        cols += flag;
     }
     // one atomic per wave for the whole kernel
     paths = wave_sum(paths);
+    cols = wave_sum(cols);
     if ((threadIdx.x & (WAVE - 1)) == 0 && paths) atomicAdd(&hc->paths, paths);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && cols) atomicAdd(&hc->cols, cols);
 }
 
-__global__ void k_hub_decide(const uint32_t *cols, const uint32_t *hub_rank, HubIn in, HubCounters *hc) {
-    const uint32_t c = *cols;
-    hc->cols = c;
+// Clears the sample's sums before the exact marking.
+__global__ void k_hub_reset(HubCounters *hc) {
+    hc->paths = 0;
+    hc->cols = 0;
+}
+
+// The AUTO decision from k_hub_mark's sums over every stride-th vertex.
+__global__ void k_hub_decide(const uint32_t *hub_rank, HubIn in, HubCounters *hc, uint32_t stride) {
+    const double c = (double)hc->cols * stride;
     bool giant = false;
     for (uint32_t i = 0; i < in.end - in.base; ++i) {
         const uint32_t r = hub_rank[i];
         giant = giant || in.upoff[r + 1] - in.upoff[r] >= GIANT_UPS;
     }
-    const double paths = (double)hc->paths;
-    const double dense = NS_FIXED + NS_FIXED_VERTEX * (double)in.n + NS_PER_COL * (double)c +
-                         (in.two_pass ? NS_HUB_PASS * paths : 0.0);
+    const double paths = (double)hc->paths * stride;
+    const double dense = NS_FIXED + NS_FIXED_VERTEX * (double)in.n + NS_PER_COL * c +
+                         (in.two_pass && !giant ? NS_HUB_PASS * paths : 0.0);
     const double sparse = (giant ? NS_SPARSE_GIANT : NS_SPARSE) * paths * (in.two_pass ? 1.0 : 0.5);
     hc->on = (in.force || sparse > dense) ? 1u : 0u;
+    if (!hc->on) {  // a declined tile reports no columns
+        hc->cols = 0;
+        hc->paths = 0;
+    }
 }
 
 __global__ void k_hub_fill(HubIn in, const uint32_t *keep, const uint32_t *coff, const HubCounters *hc,
@@ -273,10 +295,25 @@ uint64_t hub_gemm_ops(uint32_t cols) {
 }
 
 pb_status hub_tile(const HubIn &in, HubCounters *hc, const HubOut &out, Workspace &ws, hipStream_t s,
-                   hipEvent_t ev0, hipEvent_t ev1, uint32_t *gemm_grid) {
+                   hipEvent_t ev0, hipEvent_t ev1, uint32_t *gemm_grid, uint32_t *host_on) {
     const uint64_t n = in.n;
     const uint32_t H = in.end - in.base;
     if (H < 2 || H > HUB_T) return PB_ERR_INVALID_ARG;
+    *gemm_grid = 0;
+    hipLaunchKernelGGL(k_hub_rank, dim3(grid_for(n)), dim3(256), 0, s, in.smid, n, in.base, in.end, out.hub_rank);
+    if (!in.force) {
+        // AUTO decides from every HUB_SAMPLE-th vertex's columns; the host
+        // reads the decision, so a declined tile costs the sample and one
+        // synchronisation, not the marking, scan and compaction of all columns
+        hipLaunchKernelGGL(k_hub_mark, dim3(grid_for((n + HUB_SAMPLE - 1) / HUB_SAMPLE, 256, 1024)), dim3(256), 0, s,
+                           in, (uint32_t *)nullptr, hc, HUB_SAMPLE);
+        hipLaunchKernelGGL(k_hub_decide, dim3(1), dim3(1), 0, s, (const uint32_t *)out.hub_rank, in, hc, HUB_SAMPLE);
+        PB_TRY_HIP(hipGetLastError());
+        PB_TRY_HIP(hipMemcpyAsync(host_on, &hc->on, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        PB_TRY_HIP(hipStreamSynchronize(s));
+        if (!*host_on) return PB_OK;
+        hipLaunchKernelGGL(k_hub_reset, dim3(1), dim3(1), 0, s, hc);
+    }
     // centres live on the other side: at most that many columns
     const uint64_t other = in.base >= in.n_u ? in.n_u : n - in.n_u;
     uint32_t *keep = ws.alloc<uint32_t>(n + 1), *coff = ws.alloc<uint32_t>(n + 1);
@@ -286,12 +323,10 @@ pb_status hub_tile(const HubIn &in, HubCounters *hc, const HubOut &out, Workspac
     uint32_t *part = ws.alloc<uint32_t>((uint64_t)grid * HUB_T * HUB_T);
     if (ws.failed) return PB_ERR_NO_MEMORY;
     *gemm_grid = grid;
-    hipLaunchKernelGGL(k_hub_rank, dim3(grid_for(n)), dim3(256), 0, s, in.smid, n, in.base, in.end, out.hub_rank);
-    hipLaunchKernelGGL(k_hub_mark, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, in, keep, hc);
+    hipLaunchKernelGGL(k_hub_mark, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, in, keep, hc, 1u);
     PB_TRY_HIP(hipGetLastError());
     PB_TRY((scan_exclusive<uint32_t, uint32_t>(keep, coff, n, coff + n, ws)));
-    hipLaunchKernelGGL(k_hub_decide, dim3(1), dim3(1), 0, s, (const uint32_t *)(coff + n),
-                       (const uint32_t *)out.hub_rank, in, hc);
+    if (in.force) hipLaunchKernelGGL(k_hub_decide, dim3(1), dim3(1), 0, s, (const uint32_t *)out.hub_rank, in, hc, 1u);
     hipLaunchKernelGGL(k_hub_fill, dim3(grid_for(n)), dim3(256), 0, s, in, keep, coff, hc, cstart, clen, ca);
     PB_TRY_HIP(hipGetLastError());
     if (ev0) PB_TRY_HIP(hipEventRecord(ev0, s));

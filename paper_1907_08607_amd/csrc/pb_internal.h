@@ -255,10 +255,12 @@ struct HubOut {
 };
 
 // Builds the tile and credits C(R,2) per hub pair to the global count and both
-// endpoints.  Everything stays on the device (hc->on may turn the tile off);
-// `ev0`/`ev1`, if not null, are recorded around the matrix-core kernel.
+// endpoints.  Without in.force the AUTO cost model decides from a sample of
+// the columns; the decision goes to `host_on` (pinned host memory) and a
+// declined tile returns at once (hc->on = 0).  `ev0`/`ev1`, if not null, are
+// recorded around the matrix-core kernel; *gemm_grid is 0 when it did not run.
 pb_status hub_tile(const HubIn &in, HubCounters *hc, const HubOut &out, Workspace &ws, hipStream_t s,
-                   hipEvent_t ev0, hipEvent_t ev1, uint32_t *gemm_grid);
+                   hipEvent_t ev0, hipEvent_t ev1, uint32_t *gemm_grid, uint32_t *host_on);
 
 // int8 operations the matrix-core kernel issues for `cols` compacted columns.
 uint64_t hub_gemm_ops(uint32_t cols);
