@@ -176,21 +176,17 @@ __global__ __launch_bounds__(256) void k_dest_small(DestRows D, uint64_t n, uint
     }
 }
 
-// Long rows: item `it` belongs to destination rank d with coff[d] <= it < coff[d + 1].
+// Long rows: item `it` belongs to destination rank d with coff[d] <= it < coff[d + 1];
+// each workgroup takes a contiguous share of the items.
 __global__ void k_dest_long(DestRows D, uint64_t n, const uint32_t *coff, uint64_t *keys, uint32_t *vals) {
-    const uint32_t items = coff[n];
-    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
-        uint64_t lo = 0, hi = n;  // coff[lo] <= it < coff[hi]
-        while (hi - lo > 1) {
-            const uint64_t mid = (lo + hi) >> 1;
-            if (coff[mid] <= it) lo = mid; else hi = mid;
-        }
-        const uint32_t d = (uint32_t)lo;
+    uint32_t i0, i1;
+    item_share(coff[n], blockIdx.x, gridDim.x, &i0, &i1);
+    rows_of_items(coff, n, i0, i1, [&](uint32_t d, uint32_t it) {
         const uint64_t len = D.roff[d + 1] - D.roff[d];
         const uint64_t j0 = (uint64_t)(it - coff[d]) * DEST_CHUNK;
         const uint64_t j1 = j0 + DEST_CHUNK < len ? j0 + DEST_CHUNK : len;
         dest_entries(D, d, j0 + threadIdx.x, j1, keys, vals, blockDim.x);
-    }
+    });
 }
 
 __global__ void k_slots(const uint64_t *keys, const uint32_t *vals, uint64_t ns, int b, const uint32_t *smid,
@@ -2272,29 +2268,32 @@ __global__ void k_vtx_short(const int64_t *u_off, const uint32_t *v_off, const u
     }
 }
 
-// Item `it` belongs to vertex x with coff[x] <= it < coff[x + 1].
+// Item `it` belongs to vertex x with coff[x] <= it < coff[x + 1]; each wave
+// takes a contiguous share of the items and adds one total per row.
 __global__ __launch_bounds__(256) void k_vtx_long(const int64_t *u_off, const uint32_t *v_off, const uint32_t *v_eid,
                                                   uint32_t n_u, uint64_t n, const uint32_t *coff, const int64_t *eout,
                                                   int64_t *vout) {
     const uint32_t lane = threadIdx.x & (WAVE - 1);
-    const uint32_t items = coff[n];
-    const uint32_t waves = gridDim.x * (blockDim.x / WAVE);
-    for (uint32_t it = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; it < items; it += waves) {
-        uint64_t lo = 0, hi = n;  // coff[lo] <= it < coff[hi]
-        while (hi - lo > 1) {
-            const uint64_t mid = (lo + hi) >> 1;
-            if (coff[mid] <= it) lo = mid; else hi = mid;
+    uint32_t i0, i1;  // a contiguous share of the items per wave
+    item_share(coff[n], blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE, gridDim.x * (blockDim.x / WAVE), &i0,
+               &i1);
+    uint32_t held = 0xFFFFFFFFu;  // the row whose items the wave is summing
+    int64_t acc = 0;
+    rows_of_items(coff, n, i0, i1, [&](uint32_t x, uint32_t it) {
+        if (x != held) {
+            if (lane == 0 && acc) atomicAdd((unsigned long long *)&vout[held], (unsigned long long)acc);
+            held = x;
+            acc = 0;
         }
-        const uint64_t x = lo;
         uint64_t b, e;
         vertex_row(u_off, v_off, n_u, x, &b, &e);
         const uint64_t cb = b + (uint64_t)(it - coff[x]) * VTX_CHUNK;
         const uint64_t ce = cb + VTX_CHUNK < e ? cb + VTX_CHUNK : e;
         int64_t sum = 0;
         for (uint64_t i = cb + lane; i < ce; i += WAVE) sum += eout[x < n_u ? i : v_eid[i]];
-        sum = wave_sum(sum);
-        if (lane == 0) atomicAdd((unsigned long long *)&vout[x], (unsigned long long)sum);
-    }
+        acc += wave_sum(sum);
+    });
+    if (lane == 0 && acc) atomicAdd((unsigned long long *)&vout[held], (unsigned long long)acc);
 }
 
 __global__ void k_vtx_halve(const uint32_t *cnt, uint64_t n, int64_t *vout) {

@@ -265,19 +265,16 @@ __global__ void k_codeg_small(const uint32_t *front, uint32_t nfront, const uint
 }
 
 // Large front vertices: every live neighbour loses one remaining neighbour.
-// Item `it` belongs to the front vertex i with coff[i] <= it < coff[i + 1].
+// Item `it` belongs to the front vertex i with coff[i] <= it < coff[i + 1];
+// each workgroup takes a contiguous share of the items.
 __global__ void k_codeg_decrement(const uint32_t *front, const uint32_t *coff, uint32_t nfront,
                                   const int64_t *u_off, const uint32_t *u_adj, const uint32_t *v_off,
                                   const uint32_t *v_adj, uint32_t n_u, const uint32_t *alive, uint32_t *cur) {
-    const uint32_t items = coff[nfront];
-    for (uint32_t it = blockIdx.x; it < items; it += gridDim.x) {
-        uint32_t lo = 0, hi = nfront;  // coff[lo] <= it < coff[hi]
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (coff[mid] <= it) lo = mid; else hi = mid;
-        }
-        const uint32_t x = front[lo];
-        const uint64_t skip = (uint64_t)(it - coff[lo]) * DEC_CHUNK;
+    uint32_t i0, i1;  // a contiguous share of the items per workgroup
+    item_share(coff[nfront], blockIdx.x, gridDim.x, &i0, &i1);
+    rows_of_items(coff, nfront, i0, i1, [&](uint32_t i, uint32_t it) {
+        const uint32_t x = front[i];
+        const uint64_t skip = (uint64_t)(it - coff[i]) * DEC_CHUNK;
         if (x < n_u) {
             const int64_t b = u_off[x] + (int64_t)skip, e = u_off[x + 1];
             const int64_t end = b + DEC_CHUNK < e ? b + DEC_CHUNK : e;
@@ -288,7 +285,7 @@ __global__ void k_codeg_decrement(const uint32_t *front, const uint32_t *coff, u
             const uint64_t end = b + DEC_CHUNK < e ? b + DEC_CHUNK : e;
             for (uint64_t k = b + threadIdx.x; k < end; k += blockDim.x) codeg_drop(v_adj[k], alive, cur);
         }
-    }
+    });
 }
 
 // Exact complement coreness over key windows.  A window holds every live

@@ -219,6 +219,51 @@ __device__ inline T block_sum(T v, T *s_tmp) {
 }
 
 
+// Calls f(row, item) for the items [i0, i1) of a scanned item count (coff
+// over n rows: row d owns items coff[d] .. coff[d + 1] - 1, coff[n] in all),
+// in order.  The first item's row comes from a binary search; leaving a row,
+// the next is found by galloping forward from it (rows without items can lie
+// between, millions of them in a skewed graph), so a caller that takes a
+// contiguous share of the items searches once per row instead of once per
+// item, and never walks rows one by one.
+template <class F>
+__device__ inline void rows_of_items(const uint32_t *coff, uint64_t n, uint32_t i0, uint32_t i1, F f) {
+    if (i0 >= i1) return;
+    uint64_t d = 0;
+    for (uint32_t it = i0; it < i1; ++it) {
+        if (it == i0 || coff[d + 1] <= it) {
+            // the last row r with coff[r] <= it (rows after the one holding it start above it)
+            uint64_t lo = it == i0 ? 0 : d + 1, hi;
+            if (it == i0) {
+                hi = n;
+            } else {
+                uint64_t step = 1;
+                hi = lo + 1;
+                while (hi < n && coff[hi] <= it) {
+                    lo = hi;
+                    step <<= 1;
+                    hi = lo + step;
+                }
+                if (hi > n) hi = n;
+            }
+            while (hi - lo > 1) {  // coff[lo] <= it < coff[hi] (coff[n] = all items > it)
+                const uint64_t mid = (lo + hi) >> 1;
+                if (coff[mid] <= it) lo = mid; else hi = mid;
+            }
+            d = lo;
+        }
+        f((uint32_t)d, it);
+    }
+}
+
+// The share [*i0, *i1) of `items` that part `part` of `parts` takes.
+__device__ inline void item_share(uint32_t items, uint32_t part, uint32_t parts, uint32_t *i0, uint32_t *i1) {
+    const uint32_t q = (uint32_t)(((uint64_t)items + parts - 1) / parts);
+    const uint64_t a = (uint64_t)part * q, b = a + q;
+    *i0 = a < items ? (uint32_t)a : items;
+    *i1 = b < items ? (uint32_t)b : items;
+}
+
 // ---------------------------------------------------------------- hub tile
 
 // Dense hub-to-hub pairs on int8 matrix cores.  The hubs are the first HUB_T
