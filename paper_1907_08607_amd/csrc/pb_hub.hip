@@ -86,13 +86,16 @@ __global__ void k_hub_rank(const uint32_t *smid, uint64_t n, uint32_t base, uint
 }
 
 // Marks the kept centre columns (keep[r]) and adds their hub-pair paths and
-// their number to hc.  With stride > 1 (keep null) it visits every stride-th
-// vertex only: a sample for the AUTO estimate.
+// their number to hc.  With stride > 1 (keep null) it visits one vertex in
+// `stride`, as runs of 64 consecutive ranks every 64 * stride (whole cache
+// lines of the rank-indexed tables): a sample for the AUTO estimate.
 __global__ void k_hub_mark(HubIn in, uint32_t *keep, HubCounters *hc, uint32_t stride) {
     unsigned long long paths = 0;
     uint32_t cols = 0;
-    HUB_GRID_STRIDE(i, (in.n + stride - 1) / stride) {
-        const uint64_t r = i * stride;
+    const uint64_t runs = (in.n + 64ull * stride - 1) / (64ull * stride);
+    HUB_GRID_STRIDE(i, stride == 1 ? in.n : runs * 64) {
+        const uint64_t r = stride == 1 ? i : (i >> 6) * 64 * stride + (i & 63);
+        if (r >= in.n) continue;
         uint32_t flag = 0;
         if (other_side(in, in.smid[r])) {
             const uint32_t o = in.roff[r], deg = in.roff[r + 1] - o;
