@@ -565,14 +565,16 @@ constexpr uint32_t NBR_PAD = 64;
 
 // Smallest e in (s, len] with p[e] < v, where p = nbr + start is strictly
 // decreasing, s < len and p[s] >= v; *pe = p[e] (0 when e == len).  The 16
-// entries after s come in one round trip of aligned 16-byte loads, which
-// settles every part of at most 16 entries; a longer part gallops and then
-// narrows with 8 independent probes per round trip, instead of one
-// dependent load per step.
+// entries after s come in one round trip of aligned 16-byte loads, together
+// with the run's last entry: that settles every part of at most 16 entries,
+// and every part that runs to the end of the run (the last window a run
+// reaches); a longer part gallops and then narrows with 8 independent probes
+// per round trip, instead of one dependent load per step.
 __device__ inline uint32_t probe_below(const uint32_t *nbr, uint32_t start, uint32_t s, uint32_t len, uint32_t v,
                                        uint32_t *pe) {
     const uint32_t a = start + s + 1;  // absolute index of p[s + 1]
     const uint32_t b = a & ~3u;
+    const uint32_t last = nbr[start + len - 1];  // the run's smallest entry, in the same round trip
     uint32_t w[20];
     const uint4 *q = reinterpret_cast<const uint4 *>(nbr + b);
 #pragma unroll
@@ -598,7 +600,7 @@ __device__ inline uint32_t probe_below(const uint32_t *nbr, uint32_t start, uint
         *pe = val;
         return s + 1 + cnt;
     }
-    if (lim < 16) {  // every entry after s is >= v
+    if (lim < 16 || last >= v) {  // every entry after s is >= v
         *pe = 0;
         return len;
     }
