@@ -604,8 +604,11 @@ __device__ inline uint32_t probe_below(const uint32_t *nbr, uint32_t start, uint
         *pe = 0;
         return len;
     }
-    // answer in (x, y]; p[x] >= v; y == len or p[y] = yv < v
-    uint32_t x = s + 16, y = len, yv = 0;
+    // answer in (x, y]; p[x] >= v; p[y] = yv < v (the last entry is below v)
+    uint32_t x = s + 16, y = len - 1, yv = last;
+    // a remaining run of at most 81 entries is narrowed directly (two rounds
+    // of 8 probes); a longer one gallops first
+    if (y - x > 81)
     for (uint64_t scale = 16;; scale <<= 8) {
         uint32_t qi[8], qv[8];
 #pragma unroll
