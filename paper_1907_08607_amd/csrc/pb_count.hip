@@ -681,16 +681,26 @@ struct DenseAgg {
         const uint32_t v = w[d >> c] >> ((d & ((1u << c) - 1)) << (5 - c));
         return c ? v & ((1u << (32 >> c)) - 1) : v;
     }
+    // Every non-zero counter, four words a thread per step: the four LDS
+    // reads are issued before any is tested, so a window that is mostly
+    // empty costs a quarter of the round trips.
     template <class F>
     __device__ void for_each(F f) const {
         const uint32_t c = cs(), per = 1u << c, bits = 32 >> c;
         const uint32_t mask = c ? (1u << bits) - 1 : 0xFFFFFFFFu;
-        for (uint32_t i = threadIdx.x; i * per < size; i += T) {
-            const uint32_t v = w[i];
-            if (!v) continue;
-            for (uint32_t j = 0; j < per; ++j) {
-                const uint32_t cc = (v >> (j * bits)) & mask;
-                if (cc) f(lo + i * per + j, cc);
+        const uint32_t words = (size + per - 1) >> c;
+        for (uint32_t i0 = threadIdx.x; i0 < words; i0 += 4 * T) {
+            uint32_t v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = i0 + k * T < words ? w[i0 + k * T] : 0u;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (!v[k]) continue;
+                const uint32_t i = i0 + k * T;
+                for (uint32_t j = 0; j < per; ++j) {
+                    const uint32_t cc = (v[k] >> (j * bits)) & mask;
+                    if (cc) f(lo + i * per + j, cc);
+                }
             }
         }
     }
