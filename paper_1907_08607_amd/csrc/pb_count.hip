@@ -736,11 +736,21 @@ struct HashAgg {
         }
         return 1u;
     }
+    // every key and its count, four slots a thread per step with the reads
+    // issued before any is tested
     template <class F>
     __device__ void for_each(F f) const {
-        for (uint32_t i = threadIdx.x; i < CAP; i += T) {
-            const uint32_t k = keys[i];
-            if (k != EMPTY) f(k, cnts[i]);
+        for (uint32_t i0 = threadIdx.x; i0 < CAP; i0 += 4 * T) {
+            uint32_t k[4], c[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool in = i0 + q * T < CAP;
+                k[q] = in ? keys[i0 + q * T] : EMPTY;
+                c[q] = in ? cnts[i0 + q * T] : 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (k[q] != EMPTY) f(k[q], c[q]);
         }
     }
 };
@@ -871,9 +881,13 @@ struct PackedHashAgg {
     }
     template <class F>
     __device__ void for_each(F f) const {
-        for (uint32_t i = threadIdx.x; i < CAP; i += T) {
-            const uint32_t e = w[i];
-            if (e) f(lo + (e >> cbits) - 1, e & ((1u << cbits) - 1));
+        for (uint32_t i0 = threadIdx.x; i0 < CAP; i0 += 4 * T) {
+            uint32_t e[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) e[q] = i0 + q * T < CAP ? w[i0 + q * T] : 0u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (e[q]) f(lo + (e[q] >> cbits) - 1, e[q] & ((1u << cbits) - 1));
         }
     }
 };
