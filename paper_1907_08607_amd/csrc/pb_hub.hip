@@ -157,23 +157,74 @@ __global__ void k_hub_fill(HubIn in, const uint32_t *keep, const uint32_t *coff,
     }
 }
 
-// Split-K product.  Wave w owns block (w / 4, w % 4) of D in 64x64 blocks and
-// computes it when it is on or above the diagonal: 2x2 tiles of 32x32, each a
-// chain of 32x32x32 int8 MFMAs over the chunk.  Both operands are read from
-// LDS with the same lane/byte pattern, so the K order inside an instruction
-// does not matter.  Output layout of a 32x32 tile: lane l, register q holds
-// row 8(q/4) + 4(l/32) + q%4, column l%32.
+// Split-K product.  The upper triangle of D in 64x64 blocks is 6 blocks off
+// the diagonal (2x2 tiles of 32x32 each) and 4 on it (3 tiles: the lower-left
+// one lies below the diagonal).  Waves are placed on SIMD w % 4, so the blocks
+// go to waves 0-7, 10 and 11: each SIMD issues 8 or 10 tile products per K
+// step (one wave per block on waves 0-9 would put 16 on one SIMD).  Every
+// tile is a chain of 32x32x32 int8 MFMAs over the chunk.  Both operands are
+// read from LDS with the same lane/byte pattern, so the K order inside an
+// instruction does not matter.  Output layout of a 32x32 tile: lane l,
+// register q holds row 8(q/4) + 4(l/32) + q%4, column l%32.
+//
+// Column work: 8 threads per column.  While the matrix cores run on chunk c,
+// the threads load the neighbours of chunk c+1 (whose column table arrived
+// during chunk c-1) and the column table of chunk c+2, so the product, not
+// the two dependent global loads, sets the pace.  A thread keeps its first
+// two neighbours of a chunk in registers for setting and clearing the tile
+// bytes; longer columns read the rest again.  A column's bytes are set and
+// cleared only by its own 8 threads, which sit in one wave, and a wave's LDS
+// stores take effect in order, so clearing chunk c and setting chunk c+1
+// need no barrier between them.
+// block (4 bi + bj) of wave w in bits 4w..4w+3; GEMM_ACTIVE: the waves that compute
+constexpr uint64_t GEMM_BLOCKS = 0x1ull | 0x3ull << 4 | 0x7ull << 8 | 0xbull << 12 | 0x2ull << 16 | 0x6ull << 20 |
+                                 0x0ull << 24 | 0xaull << 28 | 0x5ull << 40 | 0xfull << 44;
+constexpr uint32_t GEMM_ACTIVE = 0x0cff;
+
+struct HubCol {
+    uint32_t st, len, a0;
+};
+
+__device__ inline HubCol hub_col(const uint32_t *cstart, const uint32_t *clen, const uint32_t *ca, uint64_t c,
+                                 uint32_t C) {
+    if (c >= C) return HubCol{0u, 0u, 0u};
+    return HubCol{cstart[c], clen[c], ca[c]};
+}
+
+// The thread's neighbours at positions sub and sub + 8 of the column, read
+// unconditionally (position st stands in for an absent one; the hub tile
+// only runs on a graph with edges), so that nothing waits for them before
+// they are used; hub_idx turns them into hub indices.
+__device__ inline void hub_first(const uint32_t *nbr, const HubCol &k, uint32_t sub, uint32_t &r0, uint32_t &r1) {
+    r0 = nbr[sub < k.len ? k.st + sub : k.st];
+    r1 = nbr[sub + 8 < k.len ? k.st + sub + 8 : k.st];
+}
+
+// hub index of the neighbour at position j of the column, HUB_T when absent
+__device__ inline uint32_t hub_idx(uint32_t raw, uint32_t j, const HubCol &k, uint32_t base) {
+    return j < k.len ? raw - base : HUB_T;
+}
+
+__device__ inline void hub_put(uint8_t *tA, uint8_t *tB, uint32_t h, uint32_t j, uint32_t a0, uint32_t col,
+                               uint8_t v) {
+    if (h < HUB_T) {
+        tB[h * ROWB + col] = v;
+        if (j >= a0) tA[h * ROWB + col] = v;
+    }
+}
+
 __global__ __launch_bounds__(GEMM_THREADS) void k_hub_gemm(const uint32_t *cstart, const uint32_t *clen,
                                                            const uint32_t *ca, const uint32_t *nbr, uint32_t base,
                                                            const HubCounters *hc, uint32_t *part) {
     __shared__ __attribute__((aligned(16))) uint8_t tA[HUB_T * ROWB];  // A' (lower endpoint h1)
     __shared__ __attribute__((aligned(16))) uint8_t tB[HUB_T * ROWB];  // A (upper endpoint h2)
-    __shared__ uint32_t ms[KC], ml[KC], ma[KC];
     if (!hc->on) return;
     const uint32_t C = hc->cols;
     const uint32_t tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
-    const uint32_t bi = w >> 2, bj = w & 3;
-    const bool active = bj >= bi;
+    const uint32_t blk = (uint32_t)(GEMM_BLOCKS >> (4 * w)) & 15u;
+    const bool active = (GEMM_ACTIVE >> w) & 1u;
+    const uint32_t bi = blk >> 2, bj = blk & 3;
+    const bool diag = bi == bj;
     v16i acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -191,30 +242,24 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_hub_gemm(const uint32_t *cstar
             zb[i] = make_uint4(0, 0, 0, 0);
         }
     }
-    for (uint32_t c0 = blockIdx.x * KC; c0 < C; c0 += gridDim.x * KC) {
-        if (tid < KC) {
-            const uint32_t c = c0 + tid;
-            if (c < C) {
-                ms[tid] = cstart[c];
-                ml[tid] = clen[c];
-                ma[tid] = ca[c];
-            } else {
-                ml[tid] = 0;
-            }
-        }
+    const uint32_t col = tid >> 3, sub = tid & 7;
+    const uint32_t step = gridDim.x * KC;
+    uint64_t c0 = (uint64_t)blockIdx.x * KC;
+    HubCol k0 = hub_col(cstart, clen, ca, c0 + col, C);
+    uint32_t r0, r1;
+    hub_first(nbr, k0, sub, r0, r1);
+    HubCol k1 = hub_col(cstart, clen, ca, c0 + step + col, C);
+    __syncthreads();
+    for (; c0 < C; c0 += step) {
+        const uint32_t h0 = hub_idx(r0, sub, k0, base), h1 = hub_idx(r1, sub + 8, k0, base);
+        hub_put(tA, tB, h0, sub, k0.a0, col, 1);
+        hub_put(tA, tB, h1, sub + 8, k0.a0, col, 1);
+        for (uint32_t j = sub + 16; j < k0.len; j += 8) hub_put(tA, tB, nbr[k0.st + j] - base, j, k0.a0, col, 1);
         __syncthreads();
-        {
-            const uint32_t col = tid >> 3, sub = tid & 7;  // 8 threads per column
-            const uint32_t len = ml[col], st = ms[col], a0 = ma[col];
-            for (uint32_t j = sub; j < len; j += 8) {
-                const uint32_t h = nbr[st + j] - base;
-                if (h < HUB_T) {
-                    tB[h * ROWB + col] = 1;
-                    if (j >= a0) tA[h * ROWB + col] = 1;
-                }
-            }
-        }
-        __syncthreads();
+        // next chunk's neighbours and the column table after it, in flight during the product
+        uint32_t g0, g1;
+        hub_first(nbr, k1, sub, g0, g1);
+        const HubCol k2 = hub_col(cstart, clen, ca, c0 + 2ull * step + col, C);
         if (active) {
 #pragma unroll
             for (uint32_t ks = 0; ks < KC; ks += 32) {
@@ -225,39 +270,35 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_hub_gemm(const uint32_t *cstar
                     a[t] = *reinterpret_cast<const v4i *>(&tA[(bi * 64 + t * 32 + (lane & 31)) * ROWB + kb]);
                     b[t] = *reinterpret_cast<const v4i *>(&tB[(bj * 64 + t * 32 + (lane & 31)) * ROWB + kb]);
                 }
-#pragma unroll
-                for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-                    for (int tj = 0; tj < 2; ++tj)
-                        acc[ti][tj] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+                acc[0][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[0], b[0], acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[0], b[1], acc[0][1], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[1], b[1], acc[1][1], 0, 0, 0);
+                if (!diag) acc[1][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[1], b[0], acc[1][0], 0, 0, 0);
             }
         }
         __syncthreads();
-        {
-            const uint32_t col = tid >> 3, sub = tid & 7;
-            const uint32_t len = ml[col], st = ms[col];
-            for (uint32_t j = sub; j < len; j += 8) {
-                const uint32_t h = nbr[st + j] - base;
-                if (h < HUB_T) {
-                    tB[h * ROWB + col] = 0;
-                    tA[h * ROWB + col] = 0;
-                }
-            }
-        }
-        __syncthreads();
+        hub_put(tA, tB, h0, sub, k0.a0, col, 0);
+        hub_put(tA, tB, h1, sub + 8, k0.a0, col, 0);
+        for (uint32_t j = sub + 16; j < k0.len; j += 8) hub_put(tA, tB, nbr[k0.st + j] - base, j, k0.a0, col, 0);
+        k0 = k1;
+        k1 = k2;
+        r0 = g0;
+        r1 = g1;
     }
     if (active) {
         uint32_t *P = part + (uint64_t)blockIdx.x * HUB_T * HUB_T;
 #pragma unroll
         for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-            for (int tj = 0; tj < 2; ++tj)
+            for (int tj = 0; tj < 2; ++tj) {
+                if (diag && ti == 1 && tj == 0) continue;  // below the diagonal: never read
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
                     const uint32_t i = bi * 64 + ti * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
                     const uint32_t j = bj * 64 + tj * 32 + (lane & 31);
                     P[i * HUB_T + j] = (uint32_t)acc[ti][tj][q];
                 }
+            }
     }
 }
 
@@ -291,10 +332,10 @@ __global__ __launch_bounds__(HUB_T) void k_hub_reduce(const uint32_t *part, uint
 namespace pb {
 
 uint64_t hub_gemm_ops(uint32_t cols) {
-    // per chunk of KC columns: 10 upper 64x64 blocks of 2x2 tiles, KC/32
-    // MFMAs of 32x32x32 (2 * 32^3 operations) each
+    // per chunk of KC columns: 36 tiles of 32x32 (6 blocks of 4, 4 diagonal
+    // blocks of 3), KC/32 MFMAs of 32x32x32 (2 * 32^3 operations) each
     const uint64_t chunks = (cols + KC - 1) / KC;
-    return chunks * 10ull * 4ull * (KC / 32) * 2ull * 32 * 32 * 32;
+    return chunks * 36ull * (KC / 32) * 2ull * 32 * 32 * 32;
 }
 
 pb_status hub_tile(const HubIn &in, HubCounters *hc, const HubOut &out, Workspace &ws, hipStream_t s,
