@@ -740,6 +740,12 @@ def main():
         traffic = measured_traffic("k_count_heavy", args.workload, args.outputs) if profiled else None
         traffic_note = None
     achieved = (rw * bpw / (rms * 1e-3)) / 1e9 if rms > 0 else 0.0
+    # the unit figure above prices the per-edge credit as an int64
+    # read-modify-write; where every slot credit fits 32 bits the library keeps
+    # 4-byte counters, so the kernel's own floor is lower: quoted beside it
+    sb = stats[0].slot_credit_bytes
+    kbpw = bpw if args.outputs in ("global", "vertex") or not sb else 8 + 2 * sb
+    achieved_k = (rw * kbpw / (rms * 1e-3)) / 1e9 if rms > 0 else 0.0
     phases = {k: round(mean(k), 3) for k in ("ms_prepare", "ms_heavy", "ms_global", "ms_dense", "ms_hash",
                                               "ms_sort", "ms_hub_gemm", "ms_hub_pass", "ms_output")}
     st0 = stats[0]
@@ -759,7 +765,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": rk, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
-                     "bytes_per_wedge": bpw, "wedges_per_launch": rw, "launch_ms": rms},
+                     "bytes_per_wedge": bpw, "wedges_per_launch": rw, "launch_ms": rms,
+                     "slot_credit_bytes": sb, "kernel_bytes_per_wedge": kbpw,
+                     "frac_at_kernel_bytes": achieved_k / HBM_PEAK_GBS},
         "cpu_baseline": None,
     }
     if traffic_note:

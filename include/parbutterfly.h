@@ -171,6 +171,10 @@ typedef struct {
     /* Giant sources (global-histogram path; included in the dense figures). */
     uint64_t wedges_global;   /* wedges they hold */
     double ms_global;         /* their time: histogram clear, walks and endpoint step (PB_FLAG_TIMING) */
+    /* Bytes of one per-slot credit counter: 4 when no edge can lie in 2^32
+     * butterflies (squared maximum degree below 2^32), else 8; 0 without
+     * per-edge counts.  Pass 2 reads and writes one such counter per wedge. */
+    uint64_t slot_credit_bytes;
 } pb_stats;
 
 /* opts.flags bits */

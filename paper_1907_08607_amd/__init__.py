@@ -54,7 +54,8 @@ class pb_stats(ctypes.Structure):
         ("wedges_heavy", ctypes.c_uint64), ("ms_heavy", ctypes.c_double)] + [
         (name, ctypes.c_uint64) for name in ("hub_rows", "hub_cols", "hub_mfma_ops")] + [
         (name, ctypes.c_double) for name in ("ms_hub_gemm", "ms_hub_pass")] + [
-        ("wedges_global", ctypes.c_uint64), ("ms_global", ctypes.c_double)]
+        ("wedges_global", ctypes.c_uint64), ("ms_global", ctypes.c_double),
+        ("slot_credit_bytes", ctypes.c_uint64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

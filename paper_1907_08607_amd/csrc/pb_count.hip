@@ -345,12 +345,14 @@ struct Policy {
 __host__ __device__ inline bool light_wg_ok(uint32_t t) { return t == 64 || t == 128 || t == 256; }
 __host__ __device__ inline bool medium_wg_ok(uint32_t t) { return t == 128 || t == 256 || t == 512; }
 
-constexpr uint32_t PH_SLOTS = 32768;          // packed hash: 128 KB of LDS
-constexpr uint32_t PH_FULL = PH_SLOTS / 4 * 3;  // keys at which a window is refused and narrowed
-constexpr uint32_t PH_TARGET = 12288;          // keys a window is sized for
-// Sources with at most PH_SLOTS / 2 wedges (about one window), or sparser
-// than PH_DENSITY wedges per candidate, take packed-hash windows sized to
-// their wedges instead of dense windows sized to the LDS.
+constexpr uint32_t PH_T = 1024;                   // threads of a packed-hash workgroup
+constexpr uint32_t PH_SLOTS = 32768;              // packed hash: 128 KB of LDS
+constexpr uint32_t PH_FULL = PH_SLOTS / 4 * 3;    // keys at which a window is refused and narrowed
+constexpr uint32_t PH_TARGET = PH_SLOTS / 8 * 3;  // keys a window is sized for
+// Sources with at most PH_ONE_WINDOW wedges, or sparser than PH_DENSITY
+// wedges per candidate, take packed-hash windows sized to their wedges
+// instead of dense windows sized to the LDS.
+constexpr uint32_t PH_ONE_WINDOW = 16384;
 constexpr double PH_DENSITY = 0.05;
 
 __host__ __device__ inline uint32_t bit_width(uint32_t x) {
@@ -426,7 +428,7 @@ __global__ __launch_bounds__(256) void k_plan(const uint32_t *upoff, const uint6
                         // few wedges over a wide range: packed-hash windows
                         // sized to the wedges instead of many dense windows
                         if (which == L_DENSE_HEAVY && pol.packed &&
-                            (w <= PH_SLOTS / 2 || (double)w < PH_DENSITY * range) &&
+                            (w <= PH_ONE_WINDOW || (double)w < PH_DENSITY * range) &&
                             bit_width(range) + bit_width(ups) <= 32)
                             which = L_HASH_PACKED;
                         break;
@@ -2787,7 +2789,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
                         break;
                     }
                     case L_HASH_PACKED:
-                        launch_items(k_count_phash<1024, 4>, c, 1024, pol.width[2], s, G, A, sorted_src[sorted_slot(l)],
+                        launch_items(k_count_phash<PH_T, 4>, c, PH_T, pol.width[2], s, G, A, sorted_src[sorted_slot(l)],
                                      sorted_w[sorted_slot(l)], cur, nxt, cval, nval);
                         break;
                     case L_DENSE_GLOBAL: {
@@ -2871,6 +2873,7 @@ pb_status count_core(const CoreIn &in, const CoreOut &out, int mode, const pb_op
         st.workspace_bytes = ws.peak;
         st.wedges_heavy = plan.wedges[L_DENSE_HEAVY];
         st.wedges_global = plan.wedges[L_DENSE_GLOBAL];
+        st.slot_credit_bytes = sacc32 ? 4u : sacc ? 8u : 0u;
         if (hub_grid && plan.hub.on) {
             st.wedges_hub = plan.hub.wedges;
             st.hub_rows = hub_end - hub_base;

@@ -123,3 +123,4 @@ def test_vertex_of_degree_above_2_22(kind):
     got, st = run(g, rank)
     assert_same(got, want, kind)
     assert st.wedges == oracle.wedges(g, rank)
+    assert st.slot_credit_bytes == 8  # squared maximum degree above 2^32: 64-bit slot counters

@@ -121,6 +121,7 @@ def test_er_1k_planted(kind, agg):
     stats = pb.pb_stats()
     assert_same(gpu_counts(g, rank, agg, stats), want, f"{kind} {agg}")
     assert stats.wedges == oracle.wedges(g, rank)
+    assert stats.slot_credit_bytes == 4  # small degrees: 32-bit slot counters
     # the planted K_{20,15}: closed forms
     _, ve, ed = want
     assert (ed[-300:] == 266).all()
