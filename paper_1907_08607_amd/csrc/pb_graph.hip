@@ -211,25 +211,69 @@ __global__ __launch_bounds__(256) void k_codeg_max(const uint32_t *cur, const ui
     }
 }
 
-__global__ void k_codeg_flags(const uint32_t *cur, const uint32_t *alive, uint64_t n, int approx,
-                              const uint32_t *best, uint32_t *flag) {
-    const uint32_t top = *best;
-    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
-         x += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t k = (approx ? level_key(cur[x]) : cur[x]) + 1;
-        flag[x] = alive[x] && k == top;
+// One round's removal: the live vertices whose key equals the largest
+// (`best`, +1) are ranked next in increasing id, without a flag array or a
+// scan over all vertices.  A tile of CR_TILE ids is 4 waves of 16 steps of
+// 64 consecutive ids; k_codeg_count counts the tile's picks, the tile counts
+// are scanned, and k_codeg_take recounts them by ballots and ranks them.
+constexpr uint32_t CR_T = 256;
+constexpr uint32_t CR_STEPS = 16;
+constexpr uint32_t CR_WAVE_SPAN = WAVE * CR_STEPS;            // 1024 ids per wave
+constexpr uint32_t CR_TILE = CR_T / WAVE * CR_WAVE_SPAN;      // 4096 ids per workgroup
+
+__device__ inline bool codeg_pick(const uint32_t *cur, const uint32_t *alive, uint64_t x, uint64_t n, int approx,
+                                  uint32_t top) {
+    return x < n && alive[x] && (approx ? level_key(cur[x]) : cur[x]) + 1 == top;
+}
+
+__global__ __launch_bounds__(CR_T) void k_codeg_count(const uint32_t *cur, const uint32_t *alive, uint64_t n,
+                                                      int approx, const uint32_t *best, uint32_t *tcnt) {
+    __shared__ uint32_t wc[CR_T / WAVE];
+    const uint32_t top = *best, lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const uint64_t x0 = (uint64_t)blockIdx.x * CR_TILE + (uint64_t)w * CR_WAVE_SPAN + lane;
+    uint32_t c = 0;
+#pragma unroll 4
+    for (uint32_t j = 0; j < CR_STEPS; ++j) c += (uint32_t)__popcll(__ballot(codeg_pick(cur, alive, x0 + j * WAVE, n, approx, top)));
+    if (lane == 0) wc[w] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (uint32_t i = 0; i < CR_T / WAVE; ++i) t += wc[i];
+        tcnt[blockIdx.x] = t;
     }
 }
 
-__global__ void k_codeg_assign(const uint32_t *flag, const uint32_t *pos, uint64_t n, uint32_t next,
-                               uint32_t *alive, uint32_t *rank, uint32_t *front) {
-    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
-         x += (uint64_t)gridDim.x * blockDim.x)
-        if (flag[x]) {
-            rank[x] = next + pos[x];
-            front[pos[x]] = (uint32_t)x;
+// toff: exclusive scan of the tile counts.  Ranks next + (picks before x)
+// in increasing id, fills front in that order and retires the picks.
+__global__ __launch_bounds__(CR_T) void k_codeg_take(const uint32_t *cur, uint32_t *alive, uint64_t n, int approx,
+                                                     const uint32_t *best, const uint32_t *toff, uint32_t next,
+                                                     uint32_t *rank, uint32_t *front) {
+    __shared__ uint32_t wc[CR_T / WAVE];
+    const uint32_t top = *best, lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const uint64_t x0 = (uint64_t)blockIdx.x * CR_TILE + (uint64_t)w * CR_WAVE_SPAN + lane;
+    uint64_t bal[CR_STEPS];
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < CR_STEPS; ++j) {
+        bal[j] = __ballot(codeg_pick(cur, alive, x0 + j * WAVE, n, approx, top));
+        c += (uint32_t)__popcll(bal[j]);
+    }
+    if (lane == 0) wc[w] = c;
+    __syncthreads();
+    uint32_t p = toff[blockIdx.x];
+    for (uint32_t i = 0; i < w; ++i) p += wc[i];
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (uint32_t j = 0; j < CR_STEPS; ++j) {
+        if ((bal[j] >> lane) & 1) {
+            const uint64_t x = x0 + j * WAVE;
+            const uint32_t q = p + (uint32_t)__popcll(bal[j] & lt);
+            rank[x] = next + q;
+            front[q] = (uint32_t)x;
             alive[x] = 0;
         }
+        p += (uint32_t)__popcll(bal[j]);
+    }
 }
 
 // A removed vertex of degree at most DEC_SMALL is handled by one thread;
@@ -626,9 +670,10 @@ pb_status rank_codeg_exact(pb_graph *g, uint32_t *rank, hipStream_t s) {
 
 pb_status rank_codeg(pb_graph *g, bool approx, uint32_t *rank, hipStream_t s) {
     const uint64_t n = (uint64_t)g->n_u + g->n_v;
+    const uint32_t nt = ceil_div(n, CR_TILE);
     Workspace ws(s, 0);
     uint32_t *cur = ws.alloc<uint32_t>(n), *alive = ws.alloc<uint32_t>(n);
-    uint32_t *flag = ws.alloc<uint32_t>(n), *pos = ws.alloc<uint32_t>(n + 1);
+    uint32_t *tcnt = ws.alloc<uint32_t>(nt + 1), *toff = ws.alloc<uint32_t>(nt + 1);
     uint32_t *front = ws.alloc<uint32_t>(n), *best = ws.alloc<uint32_t>(1);
     uint32_t *ccnt = ws.alloc<uint32_t>(n + 1), *coff = ws.alloc<uint32_t>(n + 1);
     uint32_t *host = nullptr;
@@ -646,12 +691,12 @@ pb_status rank_codeg(pb_graph *g, bool approx, uint32_t *rank, hipStream_t s) {
             if ((st = fill<uint32_t>(best, 0u, 1, s)) != PB_OK) break;
             hipLaunchKernelGGL(k_codeg_max, dim3(grid_for(n, 256, CODEG_MAX_GRID)), dim3(256), 0, s, cur, alive, n,
                                (int)approx, best);
-            hipLaunchKernelGGL(k_codeg_flags, dim3(grid_for(n)), dim3(256), 0, s, cur, alive, n, (int)approx,
-                               best, flag);
-            if ((st = scan_exclusive<uint32_t, uint32_t>(flag, pos, n, pos + n, ws)) != PB_OK) break;
-            hipLaunchKernelGGL(k_codeg_assign, dim3(grid_for(n)), dim3(256), 0, s, flag, pos, n, next, alive,
-                               rank, front);
-            if (hipMemcpyAsync(host, pos + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipLaunchKernelGGL(k_codeg_count, dim3(nt), dim3(CR_T), 0, s, (const uint32_t *)cur,
+                               (const uint32_t *)alive, n, (int)approx, (const uint32_t *)best, tcnt);
+            if ((st = scan_exclusive<uint32_t, uint32_t>(tcnt, toff, nt, toff + nt, ws)) != PB_OK) break;
+            hipLaunchKernelGGL(k_codeg_take, dim3(nt), dim3(CR_T), 0, s, (const uint32_t *)cur, alive, n,
+                               (int)approx, (const uint32_t *)best, (const uint32_t *)toff, next, rank, front);
+            if (hipMemcpyAsync(host, toff + nt, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess) {
                 st = PB_ERR_HIP;
                 break;
