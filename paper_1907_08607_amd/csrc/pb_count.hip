@@ -1059,6 +1059,7 @@ struct FullRange {
         a = 0;
         cnt = cut ? first_below(G.nbr + start, 0, pos, lo) : pos;
     }
+    __device__ void commit(uint32_t) const {}
 };
 __device__ inline FullRange full_range(const Ranked &G, uint32_t r) {
     const uint32_t lo = G.lo(r);
@@ -1073,6 +1074,7 @@ struct SearchRange {
         a = first_below(G.nbr + start, 0, pos, hi);
         cnt = first_below(G.nbr + start, a, pos, lo) - a;
     }
+    __device__ void commit(uint32_t) const {}
 };
 
 // Windows of one source taken from the highest ids down: each run's part in
@@ -1117,6 +1119,13 @@ struct CursorRange {
         }
         a = s;
         cnt = e - s;
+    }
+    // pass 2 skipped: the cursor moves on as pass 2 would have moved it
+    __device__ void commit(uint32_t k) const {
+        if (two_pass) {
+            cur[k] = nxt[k];
+            cval[k] = nval[k];
+        }
     }
 };
 
@@ -1395,7 +1404,8 @@ __device__ inline void flush_runs(const Ranked &G, const Acc &A, uint32_t r, uin
 // The endpoint step after pass 1: C(R,2) per pair into the total and, for
 // per-vertex counts, into both endpoints.
 template <int T, class Agg, class SH>
-__device__ inline void endpoint_credit(const Ranked &G, const Acc &A, uint32_t r, const Agg &agg, SH &sh) {
+__device__ inline unsigned long long endpoint_credit(const Ranked &G, const Acc &A, uint32_t r, const Agg &agg,
+                                                    SH &sh) {
     unsigned long long local = 0;
     const bool vert = A.mode & MODE_VERTEX;
     agg.for_each([&](uint32_t key, uint32_t cc) {
@@ -1411,6 +1421,7 @@ __device__ inline void endpoint_credit(const Ranked &G, const Acc &A, uint32_t r
         if (vert) atomicAdd(&A.v[G.smid[r]], tot);
     }
     __syncthreads();
+    return tot;  // the same in every thread
 }
 
 // One work item: source r and the part of each of its runs that `range`
@@ -1434,7 +1445,13 @@ __device__ bool count_item(const Ranked &G, const Acc &A, uint32_t r, const Agg 
     __syncthreads();
     const bool credit = A.mode & (MODE_VERTEX | MODE_EDGE);
     const uint32_t c_last = k1 > k0 ? k0 + (k1 - k0 - 1) / T * T : k0;
+    bool pairs = true;
     for (int pass = 1; pass <= passes; ++pass) {
+        if (pass == 2 && !pairs) {
+            // no pair has R >= 2: every pass-2 credit is zero
+            for (uint32_t k = k0 + tid; k < k1; k += T) range.commit(k);
+            break;
+        }
         // pass 2 takes the chunks in reverse (the runs pass 1 read last are
         // still in the L2)
         for (uint32_t i = 0, c = pass == 1 ? k0 : c_last; c < k1 && i <= (c_last - k0) / T;
@@ -1453,7 +1470,7 @@ __device__ bool count_item(const Ranked &G, const Acc &A, uint32_t r, const Agg 
         }
         if (pass == 1) {
             if (!agg.finalize()) return false;  // (uniform) capacity exceeded: caller retries
-            endpoint_credit<T>(G, A, r, agg, sh);
+            pairs = endpoint_credit<T>(G, A, r, agg, sh) != 0;
         }
     }
     __syncthreads();
@@ -1554,7 +1571,17 @@ __device__ void count_item_two(const Ranked &G, const Acc &A, uint32_t r, const 
     __syncthreads();
     const bool credit = A.mode & (MODE_VERTEX | MODE_EDGE);
     const uint32_t c_last = k1 > k0 ? k0 + (k1 - k0 - 1) / (2 * T) * (2 * T) : k0;
+    bool pairs = true;
     for (int pass = 1; pass <= passes; ++pass) {
+        if (pass == 2 && !pairs) {
+            // no endpoint pair of the window has R >= 2, so every pass-2
+            // credit (R - 1 per wedge) is zero: only the cursors move on
+            for (uint32_t c = k0; c < k1; c += 2 * T)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    if (c + j * T + tid < k1) range.commit(c + j * T + tid);
+            break;
+        }
         // pass 2 takes the chunks in reverse, so it starts on the runs pass 1
         // read last, while they are still in the L2
         for (uint32_t i = 0, c = pass == 1 ? k0 : c_last; c < k1 && i <= (c_last - k0) / (2 * T);
@@ -1576,7 +1603,7 @@ __device__ void count_item_two(const Ranked &G, const Acc &A, uint32_t r, const 
         }
         if (pass == 1) {
             agg.finalize();  // dense windows are never refused
-            endpoint_credit<T>(G, A, r, agg, sh);
+            pairs = endpoint_credit<T>(G, A, r, agg, sh) != 0;
         }
     }
     __syncthreads();
@@ -1687,7 +1714,7 @@ __device__ inline void wave_flush(const Ranked &G, const Acc &A, uint32_t r, uin
 
 // Endpoint step of one window, every wave on its own share of the counters.
 template <int T>
-__device__ inline void wave_endpoint(const Ranked &G, const Acc &A, uint32_t r, const DenseAgg<T> &agg,
+__device__ inline bool wave_endpoint(const Ranked &G, const Acc &A, uint32_t r, const DenseAgg<T> &agg,
                                      uint32_t lane) {
     unsigned long long local = 0;
     const bool vert = A.mode & MODE_VERTEX;
@@ -1703,6 +1730,7 @@ __device__ inline void wave_endpoint(const Ranked &G, const Acc &A, uint32_t r, 
         if (A.mode & MODE_GLOBAL) atomicAdd(&A.g[G.gid ? G.gid[r] : 0u], local);
         if (vert) atomicAdd(&A.v[G.smid[r]], local);
     }
+    return local != 0;  // the same in every lane
 }
 
 // Heavy sources: one workgroup per source sweeps the source's candidate range
@@ -1783,7 +1811,9 @@ __global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32
                     uint32_t total, nne;
                     compact_rel<T>(ks, k0, s_start, s_cur, e - s_cur, sh, &total, &nne);
                     walk_runs<T, U, 1>(G, A, agg, sh, total, nne);
-                    if (two_pass) {
+                    // (walk_runs ends on a barrier) the endpoint step, then
+                    // pass 2 only if some pair has R >= 2
+                    if (block_sum<T>((unsigned long long)wave_endpoint<T>(G, A, r, agg, lane), sh.tmp64) && two_pass) {
                         walk_runs<T, U, 2>(G, A, agg, sh, total, nne);
                         flush_rel<T>(G, A, r, sh, nne);
                     }
@@ -1802,7 +1832,11 @@ __global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32
                         wave_walk<U, 1>(G, A, agg, wr, o, dlt, total, lane);
                     }
                     __syncthreads();
-                    if (two_pass) {
+                    // (tmp64 overlaps wave 0's strips, free between the passes; block_sum ends on a barrier)
+                    const bool pairs = block_sum<T>((unsigned long long)wave_endpoint<T>(G, A, r, agg, lane), sh.tmp64);
+                    if (two_pass && !pairs) {
+                        for (uint32_t k = k0 + tid; k < k1; k += T) rng.commit(k);  // no credit to give
+                    } else if (two_pass) {
                         for (uint32_t c = k0 + wv * WAVE; c < k1; c += NW * WAVE) {
                             const uint32_t k = c + lane;
                             uint32_t a = 0, cnt = 0, start = 0;
@@ -1817,8 +1851,6 @@ __global__ __launch_bounds__(T) void k_count_heavy(Ranked G, Acc A, const uint32
                         }
                     }
                 }
-                __syncthreads();
-                wave_endpoint<T>(G, A, r, agg, lane);
                 __syncthreads();
             }
             hi = lo;
@@ -1924,8 +1956,8 @@ __global__ __launch_bounds__(T) void k_count_phash(Ranked G, Acc A, const uint32
                     width = (hi - lo) / 2 ? (hi - lo) / 2 : 1u;
                     continue;
                 }
-                endpoint_credit<T>(G, A, r, agg, sh);
-                if (A.mode & (MODE_VERTEX | MODE_EDGE)) {
+                // pass 2 only when some pair has R >= 2 (else every credit is zero)
+                if (endpoint_credit<T>(G, A, r, agg, sh) && (A.mode & (MODE_VERTEX | MODE_EDGE))) {
                     walk_runs<T, U, 2>(G, A, agg, sh, total, nne);
                     flush_runs<T>(G, A, r, k0, sh, nne);
                 }
