@@ -35,15 +35,45 @@ PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ("pb_count.hip", "pb_hub.hip", "pb_internal.h")
 
 
+def code_only(text):
+    """C++ source with its comments and empty lines removed and each run of
+    blanks outside string and character literals (kept as written) reduced
+    to one space, so only a change of code changes it."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in " \t":
+            if out and out[-1] not in " \n":
+                out.append(" ")
+            i += 1
+        elif c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            while i < n and text[i] != "\n":
+                i += 1
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    return "\n".join(l.strip() for l in "".join(out).split("\n") if l.strip())
+
+
 def kernel_source_hash():
-    """sha256 over the counting kernels' sources (a measured HBM traffic
-    figure is only quoted for the sources it was measured on)."""
+    """sha256 over the code of the counting kernels' sources, comments left
+    out (a measured HBM traffic figure is only quoted for the code it was
+    measured on)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1907_08607_amd", "csrc")
     for name in KERNEL_SOURCES:
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
+        with open(os.path.join(csrc, name), encoding="utf-8") as f:
+            h.update(name.encode() + b"\0" + code_only(f.read()).encode())
     return h.hexdigest()
 
 

@@ -4,17 +4,20 @@
 // update per wedge.  The products are 0/1, so every sum is an exact integer no
 // larger than the number of centres.
 //
-// Pipeline (all on the device, no host synchronisation):
+// Pipeline (on the device; AUTO reads its decision back once, and a declined
+// tile launches nothing more):
 //   k_hub_rank    rank of each hub
 //   k_hub_mark    keep the centres with >= 2 hub neighbours, at least one of
 //                 them ranked below the centre; sum C(k,2) over kept centres
+//                 (AUTO first runs it on a 1/16 sample to decide)
 //   k_hub_decide  cost model (or forced on)
 //   k_hub_fill    compacted column table: slot range of the hub neighbours
 //                 (the tail of N(y), since hubs have the smallest side-major
 //                 ids) and where A' starts inside it
 //   k_hub_gemm    split-K over column chunks: each workgroup scatters 128
 //                 columns into two LDS byte tiles and accumulates the upper
-//                 64x64 blocks of D in registers, then writes its partial D
+//                 64x64 blocks of D in registers (loading the next chunks'
+//                 columns meanwhile), then writes its partial D
 //   k_hub_reduce  sums the partials; per pair: C(R,2) into the total and both
 //                 endpoints (Section 3.1.3); per hub: its wedges as the lower
 //                 endpoint (the plan subtracts them)

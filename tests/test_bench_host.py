@@ -54,3 +54,16 @@ def test_traffic_summaries_name_their_sources():
         assert float(fields["traffic_bytes_per_launch"]) > 0
         found += 1
     assert found >= 1
+
+
+def test_source_digest_ignores_comments_only():
+    """The digest covers code, not comments: a comment edit keeps a traffic
+    summary valid, a code edit voids it; string literals count as code."""
+    a = 'int f(int x) {  // one\n    /* two\n       lines */ return x + 1;\n}\nconst char *s = "a // b";\n'
+    b = 'int f(int x) {\n    return x + 1;  // changed comment\n}\n\nconst char *s = "a // b";\n'
+    c = 'int f(int x) {\n    return x + 2;\n}\nconst char *s = "a // b";\n'
+    d = 'int f(int x) {\n    return x + 1;\n}\nconst char *s = "a // c";\n'
+    assert bench.code_only(a) == bench.code_only(b)
+    assert bench.code_only(a) != bench.code_only(c)
+    assert bench.code_only(a) != bench.code_only(d)
+    assert "return x + 1;" in bench.code_only(a) and "one" not in bench.code_only(a)
