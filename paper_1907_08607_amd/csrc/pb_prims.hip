@@ -119,10 +119,11 @@ constexpr int RSS_ITEMS = RS_TILE / RSS_THREADS;
 constexpr int RSS_WAVES = RSS_THREADS / WAVE;
 
 // Lanes of this wave whose (valid) digit equals this lane's digit.
+template <int BITS>
 __device__ inline uint64_t match_digit(uint32_t d, bool valid) {
     uint64_t m = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < BITS; ++b) {
         const bool bit = (d >> b) & 1;
         const uint64_t bal = __ballot(valid && bit);
         m &= bit ? bal : ~bal;
@@ -130,44 +131,51 @@ __device__ inline uint64_t match_digit(uint32_t d, bool valid) {
     return m;
 }
 
+// Digits of BITS bits (8, or 9 where that saves a pass): 2^BITS buckets.
+template <int BITS>
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *keys, uint64_t n, int shift,
                                                         uint32_t *hist, uint32_t nb) {
-    __shared__ uint32_t cnt[256];
-    cnt[threadIdx.x] = 0;
+    constexpr uint32_t DIG = 1u << BITS;
+    __shared__ uint32_t cnt[DIG];
+    for (uint32_t d = threadIdx.x; d < DIG; d += RS_THREADS) cnt[d] = 0;
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
     for (int it = 0; it < RS_ITEMS; ++it) {
         const uint64_t idx = base + (uint64_t)it * RS_THREADS + threadIdx.x;
         const bool valid = idx < n;
-        const uint32_t d = valid ? (uint32_t)(keys[idx] >> shift) & 255u : 0u;
-        const uint64_t m = match_digit(d, valid);
+        const uint32_t d = valid ? (uint32_t)(keys[idx] >> shift) & (DIG - 1) : 0u;
+        const uint64_t m = match_digit<BITS>(d, valid);
         if (valid && (m & lanemask_lt()) == 0) atomicAdd(&cnt[d], (uint32_t)__popcll(m));
     }
     __syncthreads();
-    hist[(uint64_t)threadIdx.x * nb + blockIdx.x] = cnt[threadIdx.x];
+    for (uint32_t d = threadIdx.x; d < DIG; d += RS_THREADS) hist[(uint64_t)d * nb + blockIdx.x] = cnt[d];
 }
 
 // Stable scatter of one tile of RS_TILE keys.  `hist` holds the exclusive
 // scan over (digit, tile) of the per-tile digit counts, with the total at
-// hist[256 * nb], so this tile's count of digit d is the difference of two
+// hist[2^BITS * nb], so this tile's count of digit d is the difference of two
 // neighbouring entries.  The tile is first ordered by digit in LDS (each key at
 // its digit's tile-local start plus the number of equal digits before it in
 // the tile), then written out run by run, so consecutive lanes store to
-// consecutive addresses of one bucket.
+// consecutive addresses of one bucket.  Per-wave digit counts and offsets are
+// below RS_TILE, so they are kept in 16 bits.
+template <int BITS>
 __global__ __launch_bounds__(RSS_THREADS) void k_rs_scatter(const uint64_t *kin, const uint32_t *vin,
                                                             uint64_t n, int shift,
                                                             const uint32_t *hist, uint32_t nb,
                                                             uint64_t *kout, uint32_t *vout) {
+    constexpr uint32_t DIG = 1u << BITS;
+    static_assert(DIG <= RSS_THREADS && RS_TILE < 65536, "one thread per digit; 16-bit offsets");
     __shared__ uint64_t s_key[RS_TILE];
     __shared__ uint32_t s_val[RS_TILE];
-    __shared__ uint32_t s_gbase[256];  // global start of this tile's part of bucket d
-    __shared__ uint32_t s_lbase[256];  // tile-local start of digit d
-    __shared__ uint32_t s_run[256];    // next tile-local slot of digit d
-    __shared__ uint32_t s_w[RSS_WAVES][256];
+    __shared__ uint32_t s_gbase[DIG];  // global start of this tile's part of bucket d
+    __shared__ uint32_t s_lbase[DIG];  // tile-local start of digit d
+    __shared__ uint32_t s_run[DIG];    // next tile-local slot of digit d
+    __shared__ uint16_t s_w[RSS_WAVES][DIG];
     __shared__ uint32_t s_tmp[RSS_WAVES + 1];
     const int tid = threadIdx.x;
     const int w = tid / WAVE;
-    const bool dig = tid < 256;  // the first 256 threads own one digit each
+    const bool dig = tid < (int)DIG;  // the first DIG threads own one digit each
     uint32_t g0 = 0, cnt = 0;
     if (dig) {
         const uint64_t hb = (uint64_t)tid * nb + blockIdx.x;
@@ -187,22 +195,22 @@ __global__ __launch_bounds__(RSS_THREADS) void k_rs_scatter(const uint64_t *kin,
         const bool valid = idx < n;
         const uint64_t k = valid ? kin[idx] : 0;
         const uint32_t v = valid ? vin[idx] : 0;
-        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const uint32_t d = (uint32_t)(k >> shift) & (DIG - 1);
         if (dig) {
 #pragma unroll
             for (int q = 0; q < RSS_WAVES; ++q) s_w[q][tid] = 0;
         }
         __syncthreads();
-        const uint64_t m = match_digit(d, valid);
+        const uint64_t m = match_digit<BITS>(d, valid);
         const uint32_t rank_in_wave = (uint32_t)__popcll(m & lanemask_lt());
-        if (valid && rank_in_wave == 0) s_w[w][d] = (uint32_t)__popcll(m);
+        if (valid && rank_in_wave == 0) s_w[w][d] = (uint16_t)__popcll(m);
         __syncthreads();
         if (dig) {
             uint32_t run = s_run[tid];
 #pragma unroll
             for (int q = 0; q < RSS_WAVES; ++q) {
                 const uint32_t c = s_w[q][tid];
-                s_w[q][tid] = run;
+                s_w[q][tid] = (uint16_t)run;
                 run += c;
             }
             s_run[tid] = run;
@@ -217,7 +225,7 @@ __global__ __launch_bounds__(RSS_THREADS) void k_rs_scatter(const uint64_t *kin,
     }
     for (uint32_t i = tid; i < tile_n; i += RSS_THREADS) {
         const uint64_t k = s_key[i];
-        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const uint32_t d = (uint32_t)(k >> shift) & (DIG - 1);
         const uint32_t dst = s_gbase[d] + (i - s_lbase[d]);
         kout[dst] = k;
         vout[dst] = s_val[i];
@@ -340,17 +348,29 @@ pb_status radix_sort_pairs_bits(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32
     *vres = v0;
     if (n <= 1 || hi_bit <= lo_bit) return PB_OK;
     if (n >= (uint64_t(1) << 32)) return PB_ERR_INVALID_ARG;
+    // 9-bit digits where they take one pass fewer than 8-bit ones (a 25-bit
+    // key in 3 passes instead of 4, a 17-bit one in 2 instead of 3)
+    const int bits = hi_bit - lo_bit;
+    const int dbits = (bits + 8) / 9 < (bits + 7) / 8 ? 9 : 8;
     const uint32_t nb = ceil_div(n, RS_TILE);
-    uint32_t *hist = ws.alloc<uint32_t>((uint64_t)nb * 256 + 1);
+    const uint64_t nh = (uint64_t)nb << dbits;
+    uint32_t *hist = ws.alloc<uint32_t>(nh + 1);
     if (!hist) return PB_ERR_NO_MEMORY;
     uint64_t *ks = k0, *kd = k1;
     uint32_t *vs = v0, *vd = v1;
-    for (int shift = lo_bit; shift < hi_bit; shift += 8) {
-        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_THREADS), 0, ws.stream, ks, n, shift, hist, nb);
+    for (int shift = lo_bit; shift < hi_bit; shift += dbits) {
+        if (dbits == 9)
+            hipLaunchKernelGGL(k_rs_hist<9>, dim3(nb), dim3(RS_THREADS), 0, ws.stream, ks, n, shift, hist, nb);
+        else
+            hipLaunchKernelGGL(k_rs_hist<8>, dim3(nb), dim3(RS_THREADS), 0, ws.stream, ks, n, shift, hist, nb);
         PB_TRY_HIP(hipGetLastError());
-        PB_TRY((scan_exclusive<uint32_t, uint32_t>(hist, hist, (uint64_t)nb * 256, hist + (uint64_t)nb * 256, ws)));
-        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RSS_THREADS), 0, ws.stream, ks, vs, n, shift,
-                           hist, nb, kd, vd);
+        PB_TRY((scan_exclusive<uint32_t, uint32_t>(hist, hist, nh, hist + nh, ws)));
+        if (dbits == 9)
+            hipLaunchKernelGGL(k_rs_scatter<9>, dim3(nb), dim3(RSS_THREADS), 0, ws.stream, ks, vs, n, shift, hist,
+                               nb, kd, vd);
+        else
+            hipLaunchKernelGGL(k_rs_scatter<8>, dim3(nb), dim3(RSS_THREADS), 0, ws.stream, ks, vs, n, shift, hist,
+                               nb, kd, vd);
         PB_TRY_HIP(hipGetLastError());
         uint64_t *tk = ks; ks = kd; kd = tk;
         uint32_t *tv = vs; vs = vd; vd = tv;
