@@ -189,6 +189,11 @@ __global__ void k_dest_long(DestRows D, uint64_t n, const uint32_t *coff, uint64
     });
 }
 
+// Position of each slot in the ranked CSR: slot 2e (u -> v of edge e) at
+// eslot[e], slot 2e + 1 (v -> u) at eslot[m + e], so a U row's edges, which
+// are consecutive input edges, write and read consecutive words.
+__device__ inline uint64_t eslot_at(uint32_t slot, uint64_t m) { return (slot & 1u) * m + (slot >> 1); }
+
 __global__ void k_slots(const uint64_t *keys, const uint32_t *vals, uint64_t ns, int b, const uint32_t *smid,
                         const uint32_t *roff, uint32_t *nbr, uint32_t *eslot, uint32_t *hideg) {
     const uint64_t mask = (uint64_t(1) << b) - 1;
@@ -197,7 +202,7 @@ __global__ void k_slots(const uint64_t *keys, const uint32_t *vals, uint64_t ns,
         const uint32_t r = (uint32_t)(key >> b);
         const uint32_t d = (uint32_t)(mask - (key & mask));
         nbr[p] = smid[d];
-        eslot[vals[p]] = (uint32_t)p;
+        eslot[eslot_at(vals[p], ns >> 1)] = (uint32_t)p;
         if (d > r) {
             bool last_up = p + 1 == ns;
             if (!last_up) {
@@ -220,7 +225,7 @@ __global__ void k_upslots(const uint64_t *keys, const uint32_t *vals, uint64_t n
         const uint32_t d = (uint32_t)(mask - (key & mask));
         if (d > r && p - roff[r] < upoff[r + 1] - upoff[r]) {
             const uint32_t k = upoff[r] + (uint32_t)(p - roff[r]);
-            const uint32_t rev = eslot[vals[p] ^ 1u];  // slot (d -> r)
+            const uint32_t rev = eslot[eslot_at(vals[p] ^ 1u, ns >> 1)];  // slot (d -> r)
             uprun[k] = roff[d];
             uplen[k] = rev - roff[d];
         }
@@ -238,7 +243,7 @@ __global__ void k_upslots_copt(const uint64_t *keys, const uint32_t *vals, uint6
     GRID_STRIDE(p, ns) {
         const uint64_t key = keys[p];
         const uint32_t d = (uint32_t)(mask - (key & mask));
-        const uint32_t pos = eslot[vals[p] ^ 1u] - roff[d];  // slot (d -> u) within N(d)
+        const uint32_t pos = eslot[eslot_at(vals[p] ^ 1u, ns >> 1)] - roff[d];  // slot (d -> u) within N(d)
         const uint32_t degy = roff[d + 1] - roff[d];
         const uint32_t before_y = degy - hideg[d], before_u = degy - pos - 1;
         const uint32_t q = before_y < before_u ? before_y : before_u;
@@ -2290,8 +2295,8 @@ __global__ void k_out_vertex(const uint32_t *rank, const uint32_t *smid, const u
 __global__ void k_out_edge(const uint32_t *eslot, const unsigned long long *s, const uint32_t *s32, uint64_t m,
                            BatchLayout bl, CoreOut out) {
     GRID_STRIDE(e, m) {
-        const int64_t val = s32 ? (int64_t)s32[eslot[2 * e]] + (int64_t)s32[eslot[2 * e + 1]]
-                                : (int64_t)(s[eslot[2 * e]] + s[eslot[2 * e + 1]]);
+        const int64_t val = s32 ? (int64_t)s32[eslot[e]] + (int64_t)s32[eslot[m + e]]
+                                : (int64_t)(s[eslot[e]] + s[eslot[m + e]]);
         if (!out.eouts) {
             out.eout[e] = val;
         } else {
